@@ -1,0 +1,112 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds none of the split-BF16 arithmetic: it only draws random
+numbers (NumPy PCG64 from an explicit seed, generated in FP64 and rounded once
+to FP32) in the shapes and value distributions of the paper's experiments
+(Sec. IV-A: uniform [-1,1] as with drand48; a wide exponent range; a Gaussian
+exponent range; Sec. IV-B: conditioned dense systems).
+
+Recipes (each is stated again in the design doc):
+  uniform      iid U[-1, 1]
+  normal       iid N(0, 1)
+  wide         +-2^u, u ~ U[-20, 20] continuous, random sign
+  gauss_exp    +-m * 2^e, m ~ U[1, 2), e = round(N(0, 8)) clipped to [-100, 100]
+  cancellation B[:, j] = -A[j, :]^T + 1e-4 * N(0, 1)  (B's j-th column is the
+               negated j-th row of A plus noise)
+  batched      shapes M, N, K iid uniform over {32, 48, ..., 512}; entries N(0,1)
+  conditioned  A = U diag(s) V^T, U and V orthogonal from the Householder QR
+               of a Gaussian matrix with the signs of diag(R) folded in
+               (Haar distributed), s_i = kappa^(-(i-1)/(n-1)); A rounded to
+               FP32; x_true ~ N(0,1); b = A32 x_true in FP64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "rng", "uniform", "normal", "wide", "gauss_exp", "cancellation",
+    "batched_shapes", "batched_problems", "haar", "conditioned_system",
+    "batch_sizes",
+]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.PCG64(seed))
+
+
+def uniform(shape, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    return rng(seed).uniform(lo, hi, size=shape).astype(np.float32)
+
+
+def normal(shape, seed: int) -> np.ndarray:
+    return rng(seed).standard_normal(size=shape).astype(np.float32)
+
+
+def wide(shape, seed: int, umax: float = 20.0) -> np.ndarray:
+    g = rng(seed)
+    u = g.uniform(-umax, umax, size=shape)
+    s = np.where(g.random(size=shape) < 0.5, -1.0, 1.0)
+    return (s * np.exp2(u)).astype(np.float32)
+
+
+def gauss_exp(shape, seed: int, sigma: float = 8.0, emax: int = 100) -> np.ndarray:
+    g = rng(seed)
+    m = g.uniform(1.0, 2.0, size=shape)
+    e = np.clip(np.rint(g.normal(0.0, sigma, size=shape)), -emax, emax)
+    s = np.where(g.random(size=shape) < 0.5, -1.0, 1.0)
+    return (s * m * np.exp2(e)).astype(np.float32)
+
+
+def cancellation(M: int, K: int, seed: int, noise: float = 1e-4):
+    """A (M x K) uniform; B (K x M) with column j = -(row j of A) + noise."""
+    g = rng(seed)
+    A64 = g.uniform(-1.0, 1.0, size=(M, K))
+    A = A64.astype(np.float32)
+    B = (-A.astype(np.float64).T + noise * g.standard_normal(size=(K, M))).astype(np.float32)
+    return A, np.ascontiguousarray(B)
+
+
+def batched_shapes(count: int, seed: int, lo: int = 32, hi: int = 512, step: int = 16):
+    g = rng(seed)
+    vals = np.arange(lo, hi + 1, step)
+    return g.choice(vals, size=(count, 3)).astype(np.int64)
+
+
+def batched_problems(count: int, seed: int, lo: int = 32, hi: int = 512, step: int = 16):
+    """List of (A, B) FP32 pairs with uniformly drawn multiple-of-16 shapes."""
+    shapes = batched_shapes(count, seed, lo, hi, step)
+    g = rng(seed + 1)
+    out = []
+    for (M, N, K) in shapes:
+        A = g.standard_normal(size=(M, K)).astype(np.float32)
+        B = g.standard_normal(size=(K, N)).astype(np.float32)
+        out.append((A, B))
+    return shapes, out
+
+
+def haar(n: int, g: np.random.Generator) -> np.ndarray:
+    """Haar-distributed orthogonal matrix: Householder QR of a Gaussian."""
+    Z = g.standard_normal(size=(n, n))
+    Q, R = np.linalg.qr(Z)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :]
+
+
+def conditioned_system(n: int, kappa: float, seed: int):
+    """(A32, b64, x_true) with A = U diag(s) V^T, s geometric from 1 to 1/kappa."""
+    g = rng(seed)
+    U = haar(n, g)
+    V = haar(n, g)
+    if n > 1:
+        s = kappa ** (-np.arange(n) / (n - 1))
+    else:
+        s = np.ones(1)
+    A = ((U * s[None, :]) @ V.T).astype(np.float32)
+    x_true = g.standard_normal(size=n)
+    b = A.astype(np.float64) @ x_true
+    return A, b, x_true
+
+
+def batch_sizes(count: int, seed: int, lo: int = 64, hi: int = 1024) -> np.ndarray:
+    return rng(seed).integers(lo, hi + 1, size=count).astype(np.int64)
