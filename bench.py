@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Benchmark of the split-BF16 GEMM / LU / IR library on one MI355X.
+
+Timed step: one bf16x6 split GEMM C = A x B with M = N = K = 8192, FP32 in and
+out, A and B iid N(0,1) already resident in HBM (the operands are split into
+BF16 terms inside the kernel every step).  `value` is FP32-equivalent
+throughput 2MNK / t in TFLOP/s.  The same run also reports, as extra fields:
+the x3 and x9 variants, the plain FP32 vector-ALU GEMM comparator and torch's
+FP32 matmul (library context), errors against an FP64 product on sampled
+entries, the 64 x 64 x 2^20 split-K shape (GB/s), the 4096-problem batched
+launch against one launch per problem, and LU + iterative refinement solves.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BF16_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="only the timed step, roofline and CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def time_launches(torch, fn, reps, stream):
+    """Average duration of fn() over reps launches, with HIP events on `stream`."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for s, e in ev:
+        s.record(stream)
+        fn()
+        e.record(stream)
+    torch.cuda.synchronize()
+    ts = [s.elapsed_time(e) for s, e in ev]
+    return float(np.mean(ts)), float(np.median(ts))
+
+
+def sampled_errors(orc, A, B, C, variant, nsample=256, seed=0):
+    g = np.random.default_rng(seed)
+    r = g.integers(0, A.shape[0], nsample)
+    c = g.integers(0, B.shape[1], nsample)
+    Ar = A[r].astype(np.float64)
+    Bc = B[:, c].astype(np.float64)
+    z = np.einsum("ij,ji->i", Ar, Bc)
+    zh = np.einsum("ij,ji->i", np.abs(Ar), np.abs(Bc))
+    K = A.shape[1]
+    if variant in (6, 9):
+        bnd = 2 * K * 2.0 ** -24
+    elif variant == 3:
+        bnd = 3 * 2.0 ** -16 + 2 * K * 2.0 ** -24
+    else:
+        bnd = K * 2.0 ** -24
+    got = C[r, c].astype(np.float64)
+    ratio = np.abs(got - z) / (bnd * zh)
+    rel = np.linalg.norm(got - z) / np.linalg.norm(z)
+    return dict(max_err_over_bound=float(ratio.max()), rel_err_sample=float(rel),
+                max_componentwise=float(np.max(np.abs(got - z) / zh)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        sys.exit(2)
+
+    import torch
+    import paper_1904_06376_amd as bfx
+    import workloads
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = args.size
+    log(f"[bench] generating {n}x{n} N(0,1) operands")
+    A = workloads.normal((n, n), 100)
+    B = workloads.normal((n, n), 101)
+    tA = torch.from_numpy(A).to(dev)
+    tB = torch.from_numpy(B).to(dev)
+    tC = torch.empty((n, n), dtype=torch.float32, device=dev)
+    flop = 2.0 * n * n * n
+
+    def step(v=6):
+        bfx.gemm(v, tA, tB, tC)
+
+    # ---------------- timed region: K steps of the x6 GEMM ----------------
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = flop / (ms_per_step * 1e-3) / 1e12
+    log(f"[bench] x6 {n}^3: {ms_per_step:.3f} ms/step, {value:.1f} TFLOP/s FP32-equivalent")
+
+    # kernel duration with HIP events on the launch stream (roofline)
+    avg_ms, med_ms = time_launches(torch, step, max(args.steps, 5), stream)
+    bf16_flop = 6 * flop
+    achieved = bf16_flop / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                "traffic": None, "kernel": "gemm_split_kernel<6,128,128,2,2>",
+                "algorithmic_flop_per_launch": bf16_flop, "avg_launch_ms": round(avg_ms, 4)}
+
+    import oracle as orc
+    C6 = tC.cpu().numpy()
+    errors = {"x6": sampled_errors(orc, A, B, C6, 6)}
+
+    extras = {}
+    if not args.skip_extras:
+        variants = {}
+        for v in (3, 9):
+            for _ in range(2):
+                step(v)
+            ms, _ = time_launches(torch, lambda: step(v), 5, stream)
+            variants[f"x{v}"] = {"ms": round(ms, 3), "tflops_fp32eq": round(flop / ms / 1e9, 2),
+                                 "tflops_bf16": round(v * flop / ms / 1e9, 2)}
+            errors[f"x{v}"] = sampled_errors(orc, A, B, tC.cpu().numpy(), v)
+        variants["x6"] = {"ms": round(avg_ms, 3), "tflops_fp32eq": round(flop / avg_ms / 1e9, 2),
+                          "tflops_bf16": round(achieved, 2)}
+        # FP32 comparators
+        tS = torch.empty_like(tC)
+        bfx.sgemm_fp32(tA, tB, tS)
+        ms_s, _ = time_launches(torch, lambda: bfx.sgemm_fp32(tA, tB, tS), 3, stream)
+        errors["fp32_vector"] = sampled_errors(orc, A, B, tS.cpu().numpy(), 0)
+        torch.backends.cuda.matmul.allow_tf32 = False
+        torch.matmul(tA, tB, out=tS)
+        ms_t, _ = time_launches(torch, lambda: torch.matmul(tA, tB, out=tS), 5, stream)
+        errors["torch_fp32"] = sampled_errors(orc, A, B, tS.cpu().numpy(), 0)
+        extras["variants"] = variants
+        extras["fp32_vector_gemm"] = {"ms": round(ms_s, 3), "tflops": round(flop / ms_s / 1e9, 2)}
+        extras["torch_fp32_matmul"] = {"ms": round(ms_t, 3), "tflops": round(flop / ms_t / 1e9, 2)}
+        extras["speedup_x6_vs_fp32_vector"] = round(ms_s / avg_ms, 3)
+        extras["speedup_x6_vs_torch_fp32"] = round(ms_t / avg_ms, 3)
+        del tS
+        log(f"[bench] variants {variants} fp32-vector {ms_s:.2f} ms torch-fp32 {ms_t:.2f} ms")
+
+        # wide-range input set (2^u, u ~ U[-20,20])
+        W1 = workloads.wide((n, n), 102)
+        W2 = workloads.wide((n, n), 103)
+        tW1 = torch.from_numpy(W1).to(dev)
+        tW2 = torch.from_numpy(W2).to(dev)
+        wide_err = {}
+        for v in (3, 6, 9):
+            bfx.gemm(v, tW1, tW2, tC)
+            wide_err[f"x{v}"] = sampled_errors(orc, W1, W2, tC.cpu().numpy(), v)
+        torch.matmul(tW1, tW2, out=tC)
+        wide_err["torch_fp32"] = sampled_errors(orc, W1, W2, tC.cpu().numpy(), 0)
+        extras["errors_wide"] = wide_err
+        del tW1, tW2, W1, W2
+
+        # split-K, 64 x 64 x 2^20
+        K3 = 1 << 20
+        X = torch.from_numpy(workloads.uniform((64, K3), 201)).to(dev)
+        Y = torch.from_numpy(workloads.uniform((K3, 64), 202)).to(dev)
+        Z = torch.empty((64, 64), dtype=torch.float32, device=dev)
+        ws = torch.empty(max(bfx.gemm_ws_size(6, 64, 64, K3), 1), dtype=torch.uint8, device=dev)
+        sk = {}
+        for v in (3, 6, 9):
+            bfx.gemm(v, X, Y, Z, ws=ws)
+            ms, _ = time_launches(torch, lambda: bfx.gemm(v, X, Y, Z, ws=ws), 10, stream)
+            sk[f"x{v}"] = {"us": round(ms * 1e3, 1),
+                           "GBps": round(2 * 64 * K3 * 4 / (ms * 1e-3) / 1e9, 1)}
+        ms_s, _ = time_launches(torch, lambda: bfx.sgemm_fp32(X, Y, Z), 5, stream)
+        sk["fp32_vector"] = {"us": round(ms_s * 1e3, 1)}
+        extras["splitk_64x64x1M"] = sk
+        del X, Y, Z, ws
+        log(f"[bench] split-K {sk}")
+
+        # batched: 4096 uneven problems
+        shapes, probs = workloads.batched_problems(4096, 0)
+        tens = []
+        for (a, b) in probs:
+            tens.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev),
+                         torch.empty((a.shape[0], b.shape[1]), dtype=torch.float32, device=dev),
+                         1.0, 0.0))
+        tune = os.path.join(ROOT, "paper_1904_06376_amd", "tune", "gfx950_x6.json")
+        plan = bfx.BatchedGemmPlan(6, tens, tune if os.path.exists(tune) else None)
+        plan.launch()
+        plan.launch_per_problem()
+        torch.cuda.synchronize()
+        ms_p, _ = time_launches(torch, plan.launch, 10, stream)
+        ms_pp, _ = time_launches(torch, plan.launch_per_problem, 3, stream)
+        bflop = float(sum(2.0 * M * N * K for M, N, K in shapes))
+        extras["batched_4096"] = {"persistent_ms": round(ms_p, 3), "per_problem_ms": round(ms_pp, 3),
+                                  "speedup": round(ms_pp / ms_p, 2),
+                                  "tflops_fp32eq": round(bflop / ms_p / 1e9, 2),
+                                  "tiles": plan.info()[0]}
+        plan.close()
+        del tens, probs
+        log(f"[bench] batched {extras['batched_4096']}")
+
+        # LU + IR solves
+        try:
+            extras["solves"] = bench_solves(torch, bfx, workloads, dev, stream)
+        except Exception as e:  # report, do not hide
+            extras["solves"] = {"error": repr(e)}
+        log(f"[bench] solves {extras['solves']}")
+
+    # ---------------- CPU baseline: the oracle on a row sample ----------------
+    cores = orc.num_threads()
+    rows = 2
+    t0 = time.perf_counter()
+    orc.gemm(6, A[:rows], B)
+    dt = time.perf_counter() - t0
+    rows2 = int(min(256, max(rows, rows * args.cpu_seconds / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    orc.gemm(6, A[:rows2], B)
+    dt2 = time.perf_counter() - t0
+    cpu_val = 2.0 * rows2 * n * n / dt2 / 1e12
+    cpu = {"value": cpu_val, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"bf16x6 oracle on {rows2} rows of C ({rows2}x{n}x{n}, full K), {dt2:.1f} s"}
+    log(f"[bench] cpu oracle {cpu}")
+
+    out = {
+        "metric": "bf16x6 split-BF16 GEMM throughput (FP32-equivalent) at the paper's error bound",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"split-BF16 GEMM {n}x{n}x{n}, FP32 operands N(0,1), "
+                               "bf16x6 on MFMA with FP32 accumulation",
+                   "variant": "bf16x6", "M": n, "N": n, "K": n, "parallelism": "single-gpu"},
+        "roofline": roofline, "cpu_baseline": cpu, "errors": errors,
+        "paper_projection": "up to 5.2x over FP32 for a 32x-density BF16 unit (projection, not a target)",
+    }
+    out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
+    res = {}
+    for kappa in (1e4,):
+        t0 = time.perf_counter()
+        A, b = workloads.conditioned_system_torch(n, kappa, 7, dev)
+        log(f"[bench] generated n={n} kappa={kappa:g} system in {time.perf_counter() - t0:.1f}s")
+        LU = A.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ipiv, info = bfx.lu_factor(LU, 6)
+        torch.cuda.synchronize()
+        t_lu = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        x, r = bfx.ir_solve(A, LU, ipiv, b)
+        torch.cuda.synchronize()
+        t_ir = time.perf_counter() - t0
+        res[f"n{n}_kappa{kappa:g}"] = {"lu_ms": round(t_lu * 1e3, 2), "ir_ms": round(t_ir * 1e3, 2),
+                                       "solves_per_s": round(1.0 / (t_lu + t_ir), 3),
+                                       "lu_tflops_fp32eq": round(2 / 3 * n ** 3 / t_lu / 1e12, 2),
+                                       "iters": r["iters"], "status": r["status"],
+                                       "eta": r["eta"], "info": int(info.item())}
+        del A, b, LU, x
+    return res
+
+
+if __name__ == "__main__":
+    main()

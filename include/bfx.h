@@ -1,0 +1,200 @@
+/*
+ * bfx -- FP32-accurate linear algebra from BF16 pieces on AMD MI355X (gfx950).
+ *
+ * C ABI of libbfx.so.  Method: G. Henry, P. T. P. Tang, A. Heinecke,
+ * "Leveraging the bfloat16 Artificial Intelligence Datatype For
+ * Higher-Precision Computations" (2019).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major FP32 with a leading dimension (elements between
+ *     consecutive rows), as PyTorch lays them out.
+ *   - Every pointer named A, B, C, a, b*, x, ipiv, info, ws is a DEVICE pointer
+ *     unless the argument documentation says "host".  The caller owns all of
+ *     them; the library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     calls are asynchronous on that stream; no call synchronises the device
+ *     except where documented.
+ *   - Return value: BFX_OK (0); -i when the i-th argument (1-based) is
+ *     invalid, in the style of LAPACK's xerbla; BFX_E_HIP when the HIP runtime
+ *     reported an error (the message is in bfx_last_error_string()).
+ *   - Numerical status (a zero pivot, refinement that did not converge) is not
+ *     an error return: it is written to device memory (info, bfx_ir_result).
+ *   - No exception crosses this interface.  Entry points without a plan are
+ *     reentrant; a plan must be launched from one stream at a time.
+ *
+ * Number conversion used throughout (Sec. I, Sec. II-A): FP32 -> BF16 rounds to
+ * nearest, ties to even; a finite value that would round past the largest
+ * BF16 saturates to +-0x7F7F; NaN becomes the quiet NaN 0x7FC0 of its sign;
+ * subnormals are kept (no flush to zero).
+ */
+#ifndef BFX_H
+#define BFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BFX_OK 0
+#define BFX_E_HIP (-1000)       /* HIP runtime error; see bfx_last_error_string */
+#define BFX_E_WORKSPACE (-1001) /* workspace pointer NULL or too small */
+#define BFX_E_INTERNAL (-1002)  /* a kernel's own bounded wait expired */
+
+/* Library version, as 10000*major + 100*minor + patch. */
+int bfx_version(void);
+
+/* Text of the last error recorded by this thread (never NULL). */
+const char *bfx_last_error_string(void);
+
+/* ------------------------------------------------------------------------ */
+/* Split (Sec. II-A): b0 = (B16)a, b1 = (B16)(a - b0), b2 = (B16)(a - b0 - b1) */
+/* ------------------------------------------------------------------------ */
+/* a:  n FP32 values (device).  nterms: 2 or 3.
+ * b0, b1, b2: n BF16 bit patterns each (device, uint16); b2 is ignored and may
+ * be NULL when nterms == 2.  b0 + b1 + b2 == a exactly for a = +-0 and
+ * 2^-110 <= |a| <= FLT_MAX (Sec. II-F); for Inf/NaN, b1 = b2 = +0.
+ * Errors: -2 if n < 0, -3 if nterms not in {2,3}, -1/-4/-5/-6 for a NULL
+ * required pointer (only checked when n > 0). */
+int bfx_split_f32(const float *a, int64_t n, int nterms, uint16_t *b0,
+                  uint16_t *b1, uint16_t *b2, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Split-BF16 GEMM (Sec. II-D, II-G, IV-A):                                  */
+/*   C = alpha * (A x B) + beta * C,  A: M x K, B: K x N, C: M x N.          */
+/* Both operands are split into BF16 terms inside the kernel; the partial    */
+/* products run on BF16 MFMA with FP32 accumulation, bins added smallest     */
+/* first.  variant = number of BF16 products per scalar product:             */
+/*   3 -> Z0 + Z1            (two terms each)                                */
+/*   6 -> Z0 + (Z1 + Z2)     (three terms, the paper's six-product sum)      */
+/*   9 -> Z0 + (Z1 + (Z2 + (Z3 + Z4)))  (all nine products)                  */
+/*   1 -> Z0 (one term each)                                                 */
+/* beta == 0: C is not read (it may hold NaN).  lda >= max(1,K),             */
+/* ldb >= max(1,N), ldc >= max(1,N).  ws/ws_bytes: device workspace of at    */
+/* least bfx_gemm_ws_size(...) bytes (NULL allowed when that is 0); the      */
+/* library uses it for split-K partial sums of long inner dimensions.        */
+/* Accuracy: |C - alpha A B| <= 2K 2^-24 |alpha| |A||B| componentwise for    */
+/* variants 6 and 9 (K >= 8), plus 3*2^-16 |alpha||A||B| for variant 3.      */
+/* Errors: -1 variant, -2/-3/-4 negative sizes, -6/-8/-11 NULL operands,     */
+/* -7/-9/-12 leading dimensions, -14 workspace too small (BFX_E_WORKSPACE is */
+/* not used for this case so the argument is named).                         */
+int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+             const float *A, int64_t lda, const float *B, int64_t ldb,
+             float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
+             void *stream);
+
+/* Workspace bytes bfx_gemm needs for this shape (0 when no split-K). */
+size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K);
+
+/* Plain FP32 GEMM on the vector ALU, one rounding per FMA (Sec. II-C): the   */
+/* comparator the split variants are measured against.  Same argument        */
+/* meanings and errors as bfx_gemm without variant/workspace (so indices     */
+/* shift down by one).                                                       */
+int bfx_sgemm_fp32(int64_t M, int64_t N, int64_t K, float alpha,
+                   const float *A, int64_t lda, const float *B, int64_t ldb,
+                   float beta, float *C, int64_t ldc, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched uneven GEMMs in one persistent launch (many independent          */
+/* instances of the Sec. IV-A GEMM).                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct bfx_gemm_desc {
+    int64_t M, N, K;
+    const float *A; int64_t lda;   /* device */
+    const float *B; int64_t ldb;   /* device */
+    float *C; int64_t ldc;         /* device */
+    float alpha, beta;
+} bfx_gemm_desc;
+
+typedef struct bfx_plan bfx_plan;
+
+/* Build a plan for `count` problems (descs: HOST array, copied).  The plan
+ * picks a tile shape per problem from the tuning table at `tune_table`
+ * (a JSON file written by the autotuner; NULL or "" = built-in defaults),
+ * orders the tiles longest-first, uploads the work list, and captures
+ * "reset the work counter + one persistent kernel" into a HIP graph on first
+ * launch.  The plan owns its device buffers until bfx_plan_destroy.
+ * Errors: -1 variant, -2 count < 0, -3 descs NULL, -4 out NULL, -(100+i)
+ * when descriptor i is invalid (sizes, NULL pointers, leading dims). */
+int bfx_gemm_batched_plan_create(int variant, int64_t count,
+                                 const bfx_gemm_desc *descs,
+                                 const char *tune_table, bfx_plan **out);
+
+/* Launch the plan's graph on `stream` (the only host->device crossing). */
+int bfx_plan_launch(bfx_plan *plan, void *stream);
+
+/* Same work as bfx_plan_launch, as one kernel launch per problem (the
+ * baseline the persistent launch is measured against). */
+int bfx_plan_launch_per_problem(bfx_plan *plan, void *stream);
+
+/* Number of tiles and of problems in the plan (host ints). */
+int bfx_plan_info(const bfx_plan *plan, int64_t *tiles, int64_t *problems);
+
+int bfx_plan_destroy(bfx_plan *plan);
+
+/* ------------------------------------------------------------------------ */
+/* LU with partial pivoting (SGETRF semantics, Sec. I and IV-A): in place,   */
+/* P A = L U with L unit lower (below the diagonal) and U upper.  The panel, */
+/* the row interchanges and the triangular solve are FP32; every trailing    */
+/* update A22 -= L21 U12 is the split GEMM with `variant` products.          */
+/* ipiv: n int32 (device), ipiv[i] = 0-based row interchanged with row i.    */
+/* info: one int32 (device): 0, or c+1 for the first column c whose pivot is */
+/* exactly zero (the factorisation is completed regardless).                 */
+/* ws: device workspace of bfx_lu_ws_size(n) bytes.                          */
+/* Synchronisation: the host waits for each panel's pivot block before the   */
+/* next panel is started only through stream order; the call returns after  */
+/* queueing all work.                                                        */
+/* Errors: -1 variant, -2 n < 0, -3 A NULL, -4 lda < max(1,n), -5 ipiv NULL, */
+/* -6 info NULL, -8 workspace too small.                                     */
+int bfx_lu_factor(int variant, int64_t n, float *A, int64_t lda,
+                  int32_t *ipiv, int32_t *info, void *ws, size_t ws_bytes,
+                  void *stream);
+
+size_t bfx_lu_ws_size(int64_t n);
+
+/* ------------------------------------------------------------------------ */
+/* Iterative refinement in residual form (Sec. III):                          */
+/*   x0 = LUsolve32(b);  repeat  r = b - A x (FP64, A promoted exactly),      */
+/*   eta = |r|_inf / (|A|_inf |x|_inf + |b|_inf), stop when eta <= tol;       */
+/*   s = |r|_inf, d = s * LUsolve32(r / s) (FP32 solves), x += d (FP64).      */
+/* ------------------------------------------------------------------------ */
+typedef struct bfx_ir_opts {
+    double tol;        /* normwise backward error target (default 1e-14) */
+    int32_t max_iter;  /* maximum number of corrections (default 30) */
+    int32_t reserved;
+} bfx_ir_opts;
+
+typedef struct bfx_ir_result {
+    int32_t iters;     /* corrections applied */
+    int32_t status;    /* 0 converged, 1 max_iter reached, 2 stagnated
+                          (eta did not decrease twice in a row),
+                          3 non-finite residual */
+    double eta;        /* backward error of the returned x */
+} bfx_ir_result;
+
+/* A: the FP32 matrix that was factored (n x n, lda), LU/ipiv: the output of
+ * bfx_lu_factor (ldlu), b: n FP64 (device), x: n FP64 (device, output),
+ * opts: HOST pointer (NULL = defaults), res: HOST pointer (written before
+ * return).  This call synchronises `stream` once per refinement step to read
+ * the convergence test.  ws: device workspace of bfx_ir_ws_size(n) bytes.
+ * Errors: -1 n, -2 A, -3 lda, -4 LU, -5 ldlu, -6 ipiv, -7 b, -8 x,
+ * -9 opts (tol < 0 or max_iter < 0), -10 res, -12 workspace. */
+int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
+                 int64_t ldlu, const int32_t *ipiv, const double *b, double *x,
+                 const bfx_ir_opts *opts, bfx_ir_result *res, void *ws,
+                 size_t ws_bytes, void *stream);
+
+size_t bfx_ir_ws_size(int64_t n);
+
+/* FP32 solve with an LU from bfx_lu_factor: rhs (n FP32, device) is
+ * overwritten by (LU)^-1 P rhs.  ws: bfx_ir_ws_size(n) bytes.  Errors as
+ * bfx_ir_solve for the shared arguments. */
+int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu,
+                     const int32_t *ipiv, float *rhs, void *ws,
+                     size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFX_H */

@@ -1,0 +1,179 @@
+"""Torch-facing wrappers over the libbfx C ABI: argument checks and marshalling
+only.  Every computation runs in the HIP kernels of libbfx.so; tensors supply
+device memory and the current HIP stream."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import GemmDesc, IrOpts, IrResult, check, lib
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def _rows(t: torch.Tensor, name: str):
+    """Row-major 2-D view with unit column stride; returns the leading dimension."""
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    M, N = t.shape
+    if M == 0 or N == 0 or M == 1:
+        return max(N, 1)
+    if N > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return t.stride(0)
+
+
+def _ws(nbytes: int, device):
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def split(a: torch.Tensor, nterms: int = 3):
+    """Sec. II-A split; returns nterms int16 tensors holding BF16 bit patterns."""
+    _dev(a, torch.float32, "a")
+    a = a.contiguous()
+    outs = [torch.empty(a.shape, dtype=torch.int16, device=a.device) for _ in range(nterms)]
+    b2 = outs[2].data_ptr() if nterms == 3 else None
+    check(lib.bfx_split_f32(a.data_ptr(), a.numel(), nterms, outs[0].data_ptr(),
+                            outs[1].data_ptr(), b2, _stream()), "bfx_split_f32")
+    return tuple(outs)
+
+
+def gemm_ws_size(variant: int, M: int, N: int, K: int) -> int:
+    return lib.bfx_gemm_ws_size(variant, M, N, K)
+
+
+def gemm(variant: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
+         alpha: float = 1.0, beta: float = 0.0, ws: torch.Tensor | None = None):
+    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,9}."""
+    _dev(A, torch.float32, "A")
+    _dev(B, torch.float32, "B")
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+        beta = 0.0
+    _dev(C, torch.float32, "C")
+    need = gemm_ws_size(variant, M, N, K)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, A.device)
+    check(lib.bfx_gemm(variant, M, N, K, alpha, A.data_ptr(), _rows(A, "A"),
+                       B.data_ptr(), _rows(B, "B"), beta, C.data_ptr(), _rows(C, "C"),
+                       ws.data_ptr() if ws is not None else None, need, _stream()),
+          "bfx_gemm")
+    return C
+
+
+def sgemm_fp32(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
+               alpha: float = 1.0, beta: float = 0.0):
+    """Plain FP32 vector-ALU GEMM (the comparator)."""
+    _dev(A, torch.float32, "A")
+    _dev(B, torch.float32, "B")
+    M, K = A.shape
+    _, N = B.shape
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+        beta = 0.0
+    check(lib.bfx_sgemm_fp32(M, N, K, alpha, A.data_ptr(), _rows(A, "A"), B.data_ptr(),
+                             _rows(B, "B"), beta, C.data_ptr(), _rows(C, "C"), _stream()),
+          "bfx_sgemm_fp32")
+    return C
+
+
+class BatchedGemmPlan:
+    """One persistent, graph-captured launch over many independent GEMMs."""
+
+    def __init__(self, variant: int, problems, tune_table: str | None = None):
+        self._keep = problems
+        descs = (GemmDesc * len(problems))()
+        for i, (A, B, C, alpha, beta) in enumerate(problems):
+            M, K = A.shape
+            N = B.shape[1]
+            descs[i] = GemmDesc(M, N, K, A.data_ptr(), _rows(A, "A"), B.data_ptr(),
+                                _rows(B, "B"), C.data_ptr(), _rows(C, "C"), alpha, beta)
+        h = ctypes.c_void_p()
+        tt = tune_table.encode() if tune_table else None
+        check(lib.bfx_gemm_batched_plan_create(variant, len(problems), descs, tt,
+                                                ctypes.byref(h)), "plan_create")
+        self._h = h
+
+    def launch(self):
+        check(lib.bfx_plan_launch(self._h, _stream()), "bfx_plan_launch")
+
+    def launch_per_problem(self):
+        check(lib.bfx_plan_launch_per_problem(self._h, _stream()), "launch_per_problem")
+
+    def info(self):
+        t = ctypes.c_int64()
+        p = ctypes.c_int64()
+        check(lib.bfx_plan_info(self._h, ctypes.byref(t), ctypes.byref(p)), "plan_info")
+        return t.value, p.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.bfx_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lu_factor(A: torch.Tensor, variant: int = 6):
+    """In-place LU with partial pivoting; returns (A, ipiv int32, info int32 tensor)."""
+    _dev(A, torch.float32, "A")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    need = lib.bfx_lu_ws_size(n)
+    ws = _ws(need, A.device)
+    check(lib.bfx_lu_factor(variant, n, A.data_ptr(), _rows(A, "A"), ipiv.data_ptr(),
+                            info.data_ptr(), ws.data_ptr() if ws is not None else None,
+                            need, _stream()), "bfx_lu_factor")
+    return A, ipiv[:n], info
+
+
+def lu_solve_f32(LU: torch.Tensor, ipiv: torch.Tensor, rhs: torch.Tensor):
+    n = LU.shape[0]
+    _dev(rhs, torch.float32, "rhs")
+    need = lib.bfx_ir_ws_size(n)
+    ws = _ws(need, LU.device)
+    check(lib.bfx_lu_solve_f32(n, LU.data_ptr(), _rows(LU, "LU"), ipiv.data_ptr(),
+                               rhs.data_ptr(), ws.data_ptr() if ws is not None else None,
+                               need, _stream()), "bfx_lu_solve_f32")
+    return rhs
+
+
+def ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Tensor,
+             tol: float = 1e-14, max_iter: int = 30, x: torch.Tensor | None = None):
+    """Residual-form iterative refinement; returns (x, dict(iters, status, eta))."""
+    n = A.shape[0]
+    _dev(b, torch.float64, "b")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+    need = lib.bfx_ir_ws_size(n)
+    ws = _ws(need, A.device)
+    opts = IrOpts(tol, max_iter, 0)
+    res = IrResult()
+    check(lib.bfx_ir_solve(n, A.data_ptr(), _rows(A, "A"), LU.data_ptr(), _rows(LU, "LU"),
+                           ipiv.data_ptr(), b.data_ptr(), x.data_ptr(), ctypes.byref(opts),
+                           ctypes.byref(res), ws.data_ptr() if ws is not None else None,
+                           need, _stream()), "bfx_ir_solve")
+    return x, dict(iters=res.iters, status=res.status, eta=res.eta)

@@ -1,0 +1,326 @@
+// Many independent split-BF16 GEMMs in one persistent, graph-captured launch.
+//
+// plan_create: validates the descriptors, picks a tile shape per problem from
+// the tuning table (by M/N bucket; built-in default otherwise), expands every
+// problem into output tiles, orders the tiles by estimated cost, longest first
+// (LPT), and uploads descriptors and the tile list.  plan_launch: on first use
+// captures "reset the work counter + one persistent kernel" into a HIP graph,
+// then replays the graph on the caller's stream.  The persistent kernel keeps
+// one workgroup per resident slot; each takes the next tile index with an
+// atomic add and runs the shared tile engine until the list is exhausted, so
+// every workgroup reaches the exit.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "gemm_tile.hpp"
+
+namespace bfx {
+
+namespace {
+enum { CFG_64x64 = 0, CFG_128x128 = 1, CFG_128x64 = 2, CFG_64x128 = 3, NCFG = 4 };
+const int cfg_bm[NCFG] = {64, 128, 128, 64};
+const int cfg_bn[NCFG] = {64, 128, 64, 128};
+
+struct TileItem {
+    int32_t prob, tm, tn, cfg;
+};
+
+int bucket(int64_t x) { return x <= 64 ? 0 : x <= 128 ? 1 : x <= 256 ? 2 : 3; }
+}  // namespace
+
+__global__ void __launch_bounds__(64) plan_zero_counter(uint32_t *c) {
+    if (threadIdx.x == 0) *c = 0u;
+}
+
+// WIDE = false: only the 64x64 tile is compiled in (fewer registers, more
+// resident workgroups); WIDE = true: all four tile shapes.
+template <int V, bool WIDE>
+__global__ void __launch_bounds__(256, 1)
+persistent_gemm_kernel(const bfx_gemm_desc *__restrict__ probs,
+                       const TileItem *__restrict__ tiles, int64_t ntiles, uint32_t *counter) {
+    extern __shared__ __align__(16) uint16_t smem[];
+    __shared__ int64_t s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t idx = s_idx;
+        __syncthreads();
+        if (idx >= ntiles) break;
+        const TileItem t = tiles[idx];
+        const bfx_gemm_desc d = probs[t.prob];
+        GemmParams p;
+        p.M = d.M; p.N = d.N; p.K = d.K;
+        p.A = d.A; p.lda = d.lda; p.B = d.B; p.ldb = d.ldb; p.C = d.C; p.ldc = d.ldc;
+        p.alpha = d.alpha; p.beta = d.beta;
+        p.k_per_split = d.K; p.splits = 1; p.partial = nullptr;
+        p.vecA = ((uintptr_t)d.A % 16 == 0) && (d.lda % 4 == 0);
+        p.vecB = ((uintptr_t)d.B % 16 == 0) && (d.ldb % 4 == 0);
+        if constexpr (!WIDE) {
+            gemm_tile<V, 64, 64, 2, 2>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
+        } else {
+            switch (t.cfg) {
+                case CFG_64x64:
+                    gemm_tile<V, 64, 64, 2, 2>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
+                    break;
+                case CFG_128x128:
+                    gemm_tile<V, 128, 128, 2, 2>(p, (int64_t)t.tm * 128, (int64_t)t.tn * 128, 0, d.K, 0, smem);
+                    break;
+                case CFG_128x64:
+                    gemm_tile<V, 128, 64, 2, 2>(p, (int64_t)t.tm * 128, (int64_t)t.tn * 64, 0, d.K, 0, smem);
+                    break;
+                default:
+                    gemm_tile<V, 64, 128, 2, 2>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 128, 0, d.K, 0, smem);
+                    break;
+            }
+        }
+    }
+}
+
+}  // namespace bfx
+
+struct bfx_plan {
+    int variant = 6;
+    int64_t count = 0, ntiles = 0;
+    bool wide = false;
+    size_t lds = 0;
+    int grid = 0;
+    std::vector<bfx_gemm_desc> h_probs;
+    bfx_gemm_desc *d_probs = nullptr;
+    bfx::TileItem *d_tiles = nullptr;
+    uint32_t *d_counter = nullptr;
+    void *d_ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *kernel = nullptr;
+};
+
+namespace bfx {
+namespace {
+
+// Tuning table: {"arch": ..., "variant": V, "entries": [{"m": 64, "n": 128,
+// "tile": 2}, ...]} where m/n are bucket upper bounds (64, 128, 256, 512) and
+// tile indexes cfg_bm/cfg_bn.  Unknown keys are ignored.
+bool parse_table(const char *path, int variant, int table[4][4]) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    auto int_after = [&](size_t from, size_t to, const char *key, long &out) {
+        const std::string k = std::string("\"") + key + "\"";
+        size_t p = s.find(k, from);
+        if (p == std::string::npos || p >= to) return false;
+        p = s.find(':', p + k.size());
+        if (p == std::string::npos || p >= to) return false;
+        out = std::strtol(s.c_str() + p + 1, nullptr, 10);
+        return true;
+    };
+    long v = variant;
+    const size_t ent = s.find("\"entries\"");
+    if (ent == std::string::npos) return false;
+    int_after(0, ent, "variant", v);
+    if (v != variant) return false;
+    size_t pos = ent;
+    bool any = false;
+    for (;;) {
+        const size_t a = s.find('{', pos);
+        if (a == std::string::npos) break;
+        const size_t b = s.find('}', a);
+        if (b == std::string::npos) break;
+        long m, n, t;
+        if (int_after(a, b, "m", m) && int_after(a, b, "n", n) && int_after(a, b, "tile", t) &&
+            t >= 0 && t < NCFG) {
+            table[bucket(m)][bucket(n)] = (int)t;
+            any = true;
+        }
+        pos = b + 1;
+    }
+    return any;
+}
+
+int default_cfg(int64_t M, int64_t N) {
+    if (M >= 256 && N >= 256) return CFG_128x128;
+    if (M >= 256 && N > 64) return CFG_128x64;
+    if (N >= 256 && M > 64) return CFG_64x128;
+    return CFG_64x64;
+}
+
+template <int V>
+const void *pick_kernel(bool wide) {
+    return wide ? (const void *)persistent_gemm_kernel<V, true>
+                : (const void *)persistent_gemm_kernel<V, false>;
+}
+
+template <int V>
+size_t lds_for(bool wide) {
+    return wide ? tile_lds_bytes<V, 128, 128>() : tile_lds_bytes<V, 64, 64>();
+}
+
+void plan_free(bfx_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_probs) (void)hipFree(p->d_probs);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_ws) (void)hipFree(p->d_ws);
+    delete p;
+}
+
+}  // namespace
+}  // namespace bfx
+
+extern "C" int bfx_gemm_batched_plan_create(int variant, int64_t count, const bfx_gemm_desc *descs,
+                                            const char *tune_table, bfx_plan **out) {
+    using namespace bfx;
+    if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && !descs) return -3;
+    if (!out) return -4;
+    *out = nullptr;
+    for (int64_t i = 0; i < count; ++i) {
+        const bfx_gemm_desc &d = descs[i];
+        const bool bad = d.M < 0 || d.N < 0 || d.K < 0 || d.lda < (d.K > 1 ? d.K : 1) ||
+                         d.ldb < (d.N > 1 ? d.N : 1) || d.ldc < (d.N > 1 ? d.N : 1) ||
+                         (d.M > 0 && d.N > 0 && (!d.C || (d.K > 0 && (!d.A || !d.B))));
+        if (bad) {
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "bfx_gemm_batched_plan_create: descriptor %lld invalid",
+                          (long long)i);
+            set_error(buf);
+            return (int)(-(100 + (i < 1000000 ? i : 1000000)));
+        }
+    }
+    int table[4][4];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) table[a][b] = -1;
+    if (tune_table && tune_table[0]) parse_table(tune_table, variant, table);
+
+    bfx_plan *p = new bfx_plan();
+    p->variant = variant;
+    p->count = count;
+    p->h_probs.assign(descs, descs + count);
+    std::vector<TileItem> tiles;
+    std::vector<double> cost;
+    for (int64_t i = 0; i < count; ++i) {
+        const bfx_gemm_desc &d = descs[i];
+        if (d.M == 0 || d.N == 0) continue;
+        int cfg = table[bucket(d.M)][bucket(d.N)];
+        if (cfg < 0) cfg = default_cfg(d.M, d.N);
+        if (cfg != CFG_64x64) p->wide = true;
+        const int64_t tm = ceil_div(d.M, cfg_bm[cfg]), tn = ceil_div(d.N, cfg_bn[cfg]);
+        const double c = (double)cfg_bm[cfg] * cfg_bn[cfg] * (double)(ceil_div(d.K, BK) + 2);
+        for (int64_t a = 0; a < tm; ++a)
+            for (int64_t b = 0; b < tn; ++b) {
+                tiles.push_back(TileItem{(int32_t)i, (int32_t)a, (int32_t)b, cfg});
+                cost.push_back(c);
+            }
+        const size_t ws = gemm_ws_bytes(variant, d.M, d.N, d.K);
+        if (ws > p->ws_bytes) p->ws_bytes = ws;
+    }
+    std::vector<size_t> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<TileItem> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    p->ntiles = (int64_t)sorted.size();
+
+    int rc = BFX_OK;
+    auto fail = [&](hipError_t e, const char *what) {
+        rc = hip_fail(e, what);
+        plan_free(p);
+        return rc;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_probs, sizeof(bfx_gemm_desc) * (count > 0 ? count : 1))) != hipSuccess)
+        return fail(e, "hipMalloc(plan descs)");
+    if ((e = hipMalloc(&p->d_tiles, sizeof(TileItem) * (sorted.empty() ? 1 : sorted.size()))) != hipSuccess)
+        return fail(e, "hipMalloc(plan tiles)");
+    if ((e = hipMalloc(&p->d_counter, 256)) != hipSuccess) return fail(e, "hipMalloc(plan counter)");
+    if (p->ws_bytes && (e = hipMalloc(&p->d_ws, p->ws_bytes)) != hipSuccess)
+        return fail(e, "hipMalloc(plan workspace)");
+    if (count > 0 && (e = hipMemcpy(p->d_probs, descs, sizeof(bfx_gemm_desc) * count,
+                                    hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "hipMemcpy(plan descs)");
+    if (!sorted.empty() && (e = hipMemcpy(p->d_tiles, sorted.data(), sizeof(TileItem) * sorted.size(),
+                                          hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "hipMemcpy(plan tiles)");
+
+    switch (variant) {
+        case 1: p->kernel = pick_kernel<1>(p->wide); p->lds = lds_for<1>(p->wide); break;
+        case 3: p->kernel = pick_kernel<3>(p->wide); p->lds = lds_for<3>(p->wide); break;
+        case 6: p->kernel = pick_kernel<6>(p->wide); p->lds = lds_for<6>(p->wide); break;
+        default: p->kernel = pick_kernel<9>(p->wide); p->lds = lds_for<9>(p->wide); break;
+    }
+    if ((e = hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds)) !=
+        hipSuccess)
+        return fail(e, "hipFuncSetAttribute(persistent)");
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return fail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return fail(e, "hipDeviceGetAttribute");
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p->kernel, 256, p->lds)) != hipSuccess)
+        return fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (per_cu < 1) per_cu = 1;
+    p->grid = cus * per_cu;
+    if ((e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) != hipSuccess)
+        return fail(e, "hipStreamCreate(plan)");
+    *out = p;
+    return BFX_OK;
+}
+
+extern "C" int bfx_plan_launch(bfx_plan *p, void *stream) {
+    using namespace bfx;
+    if (!p) return -1;
+    if (p->ntiles == 0) return BFX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->exec) {
+        BFX_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+        hipLaunchKernelGGL(plan_zero_counter, dim3(1), dim3(64), 0, p->cap, p->d_counter);
+        void *args[] = {&p->d_probs, &p->d_tiles, &p->ntiles, &p->d_counter};
+        hipError_t el = hipLaunchKernel(p->kernel, dim3(p->grid), dim3(256), args, p->lds, p->cap);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(p->cap, &g);
+        if (el != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(el, "persistent kernel capture");
+        }
+        if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+        p->graph = g;
+        BFX_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    }
+    BFX_HIP(hipGraphLaunch(p->exec, s));
+    return BFX_OK;
+}
+
+extern "C" int bfx_plan_launch_per_problem(bfx_plan *p, void *stream) {
+    using namespace bfx;
+    if (!p) return -1;
+    for (const bfx_gemm_desc &d : p->h_probs) {
+        const int rc = gemm_launch(p->variant, d.M, d.N, d.K, d.alpha, d.A, d.lda, d.B, d.ldb,
+                                   d.beta, d.C, d.ldc, p->d_ws, p->ws_bytes, (hipStream_t)stream);
+        if (rc != BFX_OK) return rc;
+    }
+    return BFX_OK;
+}
+
+extern "C" int bfx_plan_info(const bfx_plan *p, int64_t *tiles, int64_t *problems) {
+    if (!p) return -1;
+    if (tiles) *tiles = p->ntiles;
+    if (problems) *problems = p->count;
+    return BFX_OK;
+}
+
+extern "C" int bfx_plan_destroy(bfx_plan *p) {
+    if (!p) return -1;
+    bfx::plan_free(p);
+    return BFX_OK;
+}

@@ -1,0 +1,163 @@
+// Split-BF16 GEMM entry points (Sec. II-D, II-G, IV-A): one-problem launch,
+// split-K for long inner dimensions with a deterministic fixed-order
+// reduction, and the host-side tile / split policy.  The tile engine itself
+// is in gemm_tile.hpp.
+#include "gemm_tile.hpp"
+
+namespace bfx {
+
+template <int V, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(WM *WN * 64, 1)
+gemm_split_kernel(GemmParams p) {
+    extern __shared__ __align__(16) uint16_t smem[];
+    const int64_t tiles_m = ceil_div(p.M, BM), tiles_n = ceil_div(p.N, BN);
+    const int64_t tiles = tiles_m * tiles_n;
+    const int64_t total = tiles * p.splits;
+    const int64_t id = xcd_remap(blockIdx.x, total);
+    const int64_t split = id / tiles;
+    const int64_t t = id % tiles;
+    // grouped order: 8 tile rows per group, column-major inside the group
+    constexpr int GROUP = 8;
+    const int64_t group = t / (GROUP * tiles_n);
+    const int64_t first_m = group * GROUP;
+    const int64_t gsz = (tiles_m - first_m < GROUP) ? tiles_m - first_m : GROUP;
+    const int64_t in_g = t % (GROUP * tiles_n);
+    const int64_t m0 = (first_m + in_g % gsz) * BM;
+    const int64_t n0 = (in_g / gsz) * BN;
+    const int64_t kb = split * p.k_per_split;
+    const int64_t ke = (kb + p.k_per_split < p.K) ? kb + p.k_per_split : p.K;
+    gemm_tile<V, BM, BN, WM, WN>(p, m0, n0, kb, ke, split, smem);
+}
+
+// Fixed-order reduction of split-K partials, then the epilogue.
+__global__ void __launch_bounds__(256)
+splitk_reduce_kernel(const float *__restrict__ partial, int splits, int64_t M,
+                     int64_t N, float alpha, float beta, float *C, int64_t ldc) {
+    const int64_t MN = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        float h = 0.0f, l = 0.0f;
+        for (int s = 0; s < splits; ++s) {
+            h += partial[(int64_t)(2 * s) * MN + e];
+            l += partial[(int64_t)(2 * s + 1) * MN + e];
+        }
+        const float X = h + l;
+        const int64_t row = e / N, col = e % N;
+        float *c = C + row * ldc + col;
+        *c = (beta == 0.0f) ? alpha * X : fmaf(alpha, X, beta * *c);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Host side: tile choice and split-K policy.
+// --------------------------------------------------------------------------
+template <int V, int BM, int BN, int WM, int WN>
+static int launch_tiles(const GemmParams &p, hipStream_t s) {
+    const size_t lds = tile_lds_bytes<V, BM, BN>();
+    auto kern = gemm_split_kernel<V, BM, BN, WM, WN>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        BFX_HIP(hipFuncSetAttribute((const void *)kern,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    const int64_t blocks = ceil_div(p.M, BM) * ceil_div(p.N, BN) * p.splits;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WM * WN * 64), lds, s, p);
+    BFX_LAUNCH_CHECK("gemm_split_kernel launch");
+    return BFX_OK;
+}
+
+// Split-K is used when the output has too few tiles to fill the GPU and K is
+// long: splits chosen so that about 4 workgroups run per CU, each covering at
+// least 8 K-steps.
+static int choose_splits(int64_t M, int64_t N, int64_t K, int BM, int BN) {
+    const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
+    const int64_t target = 1024;
+    if (tiles >= 256 || K < 16 * BK) return 1;
+    int64_t s = ceil_div(target, tiles);
+    const int64_t max_s = K / (8 * BK);
+    if (s > max_s) s = max_s;
+    if (s < 1) s = 1;
+    return (int)s;
+}
+
+static void tile_for(int64_t M, int64_t N, int &BM, int &BN) {
+    if (M <= 64 || N <= 64) { BM = 64; BN = 64; }
+    else { BM = 128; BN = 128; }
+}
+
+size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K) {
+    int BM, BN;
+    tile_for(M, N, BM, BN);
+    const int s = choose_splits(M, N, K, BM, BN);
+    if (s <= 1) return 0;
+    return (size_t)s * 2 * (size_t)M * (size_t)N * sizeof(float);
+}
+
+template <int V>
+static int dispatch_variant(GemmParams &p, int BM, int BN, hipStream_t s) {
+    if (BM == 64) return launch_tiles<V, 64, 64, 2, 2>(p, s);
+    return launch_tiles<V, 128, 128, 2, 2>(p, s);
+}
+
+int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+                const float *A, int64_t lda, const float *B, int64_t ldb,
+                float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
+                hipStream_t stream) {
+    if (M == 0 || N == 0) return BFX_OK;
+    int BM, BN;
+    tile_for(M, N, BM, BN);
+    GemmParams p;
+    p.M = M; p.N = N; p.K = K;
+    p.A = A; p.lda = lda; p.B = B; p.ldb = ldb; p.C = C; p.ldc = ldc;
+    p.alpha = alpha; p.beta = beta;
+    p.splits = choose_splits(M, N, K, BM, BN);
+    p.k_per_split = ceil_div(ceil_div(K > 0 ? K : 1, p.splits), BK) * BK;
+    p.splits = (int)ceil_div(K > 0 ? K : 1, p.k_per_split);
+    p.partial = (float *)ws;
+    p.vecA = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+    p.vecB = ((uintptr_t)B % 16 == 0) && (ldb % 4 == 0);
+    if (p.splits > 1 && (size_t)p.splits * 2 * M * N * sizeof(float) > ws_bytes)
+        return -14;
+    int rc;
+    switch (variant) {
+        case 1: rc = dispatch_variant<1>(p, BM, BN, stream); break;
+        case 3: rc = dispatch_variant<3>(p, BM, BN, stream); break;
+        case 6: rc = dispatch_variant<6>(p, BM, BN, stream); break;
+        case 9: rc = dispatch_variant<9>(p, BM, BN, stream); break;
+        default: return -1;
+    }
+    if (rc != BFX_OK || p.splits <= 1) return rc;
+    int64_t blocks = ceil_div(M * N, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       p.partial, p.splits, M, N, alpha, beta, C, ldc);
+    BFX_LAUNCH_CHECK("splitk_reduce_kernel launch");
+    return BFX_OK;
+}
+
+}  // namespace bfx
+
+extern "C" size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    return bfx::gemm_ws_bytes(variant, M, N, K);
+}
+
+extern "C" int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+                        const float *A, int64_t lda, const float *B, int64_t ldb,
+                        float beta, float *C, int64_t ldc, void *ws,
+                        size_t ws_bytes, void *stream) {
+    if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
+    if (M < 0) return -2;
+    if (N < 0) return -3;
+    if (K < 0) return -4;
+    if (lda < (K > 1 ? K : 1)) return -7;
+    if (ldb < (N > 1 ? N : 1)) return -9;
+    if (ldc < (N > 1 ? N : 1)) return -12;
+    if (M == 0 || N == 0) return BFX_OK;
+    if (K > 0 && !A) return -6;
+    if (K > 0 && !B) return -8;
+    if (!C) return -11;
+    return bfx::gemm_launch(variant, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws,
+                            ws_bytes, (hipStream_t)stream);
+}

@@ -1,0 +1,416 @@
+// Iterative refinement in residual form (Sec. III) and the FP32 LU solve.
+//
+//   x0 = LUsolve32(b);  repeat: r = b - A x (FP64, A promoted exactly),
+//   eta = |r|_inf / (|A|_inf |x|_inf + |b|_inf), stop when eta <= tol;
+//   s = |r|_inf, d = s * LUsolve32(r / s), x += d (FP64).
+//
+// Only the cubic LU is low precision; every quadratic step is FP64 except the
+// two FP32 triangular solves with the stored factors.  Kernels:
+//   residual_kernel  one workgroup per row, FP64 FMA, |r|_inf by atomicMax on
+//                    the bit pattern of a non-negative double (order-free);
+//   trsv_kernel      blocked triangular solve without a global barrier: each
+//                    workgroup takes the next block row from a ticket counter,
+//                    waits (bounded) on the completion flags of the blocks it
+//                    depends on, adds their contribution, solves its 64 x 64
+//                    diagonal block in one wave and publishes its flag;
+//   perm_kernel      the row permutation of ipiv, composed once per solve.
+// The host reads |r|_inf and |x|_inf once per step to apply the stopping rule.
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace bfx {
+
+namespace {
+constexpr int TB = 64;
+constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
+
+enum { S_NORMA = 0, S_NORMB = 1, S_RN = 2, S_XN = 3, S_NSCAL = 8 };
+
+struct IrWs {
+    int32_t *perm;
+    float *w;
+    double *r;
+    int32_t *flags;   // [nblk]
+    uint32_t *ticket; // [4]
+    unsigned long long *scal;  // [S_NSCAL]
+    int32_t *err;
+};
+
+size_t ir_ws_layout(IrWs *w, void *base, int64_t n) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const int64_t nb = ceil_div(n > 0 ? n : 1, TB);
+    const size_t o_perm = take(sizeof(int32_t) * (n > 0 ? n : 1));
+    const size_t o_w = take(sizeof(float) * (n > 0 ? n : 1));
+    const size_t o_r = take(sizeof(double) * (n > 0 ? n : 1));
+    const size_t o_f = take(sizeof(int32_t) * nb);
+    const size_t o_t = take(sizeof(uint32_t) * 4);
+    const size_t o_s = take(sizeof(unsigned long long) * S_NSCAL);
+    const size_t o_e = take(sizeof(int32_t) * 4);
+    if (w && base) {
+        char *b = (char *)base;
+        w->perm = (int32_t *)(b + o_perm);
+        w->w = (float *)(b + o_w);
+        w->r = (double *)(b + o_r);
+        w->flags = (int32_t *)(b + o_f);
+        w->ticket = (uint32_t *)(b + o_t);
+        w->scal = (unsigned long long *)(b + o_s);
+        w->err = (int32_t *)(b + o_e);
+    }
+    return off;
+}
+}  // namespace
+
+__device__ __forceinline__ void atomic_max_abs(unsigned long long *dst, double v) {
+    // |v| as a non-negative double orders like its bit pattern (NaN above Inf)
+    atomicMax(dst, (unsigned long long)__double_as_longlong(fabs(v)));
+}
+
+__global__ void __launch_bounds__(256) zero_i32(int32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
+// Compose the interchanges ipiv[0..n) into perm: (P v)[i] = v[perm[i]].
+// Sequential by nature (each interchange may move an earlier one's row); one
+// thread applies them to an LDS copy when it fits.
+__global__ void __launch_bounds__(64) perm_kernel(const int32_t *ipiv, int64_t n, int32_t *perm,
+                                                  int use_lds) {
+    extern __shared__ int32_t sp[];
+    int32_t *v = use_lds ? sp : perm;
+    for (int64_t i = threadIdx.x; i < n; i += 64) v[i] = (int32_t)i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t p = ipiv[i];
+            if (p != i) {
+                const int32_t t = v[i];
+                v[i] = v[p];
+                v[p] = t;
+            }
+        }
+    }
+    __syncthreads();
+    if (use_lds)
+        for (int64_t i = threadIdx.x; i < n; i += 64) perm[i] = v[i];
+}
+
+// w[i] = (float)(src[perm[i]] / div)   (src FP64)
+__global__ void __launch_bounds__(256)
+gather_f64_to_f32(const double *src, const int32_t *perm, double div, float *w, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        w[i] = (float)(src[perm[i]] / div);
+}
+
+__global__ void __launch_bounds__(256)
+gather_f32(const float *src, const int32_t *perm, float *w, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        w[i] = src[perm[i]];
+}
+
+__global__ void __launch_bounds__(256) copy_f32(const float *src, float *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+// x = (double) w   (init)   or   x += s * (double) w   (update)
+__global__ void __launch_bounds__(256)
+update_x(double *x, const float *w, double s, int init, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        x[i] = init ? (double)w[i] : fma(s, (double)w[i], x[i]);
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum_256(T v, T *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T s = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return s;
+}
+
+// r_i = b_i - sum_j A_ij x_j in FP64; |r|_inf into scal[S_RN].
+__global__ void __launch_bounds__(256)
+residual_kernel(const float *A, int64_t lda, int64_t n, const double *b, const double *x,
+                double *r, unsigned long long *scal, int vec) {
+    __shared__ double red[4];
+    const int64_t row = blockIdx.x;
+    const float *a = A + row * lda;
+    double s = 0.0;
+    if (vec) {
+        for (int64_t j = 4 * threadIdx.x; j + 3 < n; j += 1024) {
+            const float4 v = *reinterpret_cast<const float4 *>(a + j);
+            s = fma((double)v.x, x[j], s);
+            s = fma((double)v.y, x[j + 1], s);
+            s = fma((double)v.z, x[j + 2], s);
+            s = fma((double)v.w, x[j + 3], s);
+        }
+        for (int64_t j = (n & ~int64_t(3)) + threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+    } else {
+        for (int64_t j = threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+    }
+    s = block_sum_256(s, red);
+    if (threadIdx.x == 0) {
+        const double ri = b[row] - s;
+        r[row] = ri;
+        atomic_max_abs(scal + S_RN, ri);
+    }
+}
+
+// |A|_inf = max_i sum_j |A_ij| (FP64) into scal[S_NORMA].
+__global__ void __launch_bounds__(256)
+mat_norm_kernel(const float *A, int64_t lda, int64_t n, unsigned long long *scal) {
+    __shared__ double red[4];
+    const float *a = A + (int64_t)blockIdx.x * lda;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) s += fabs((double)a[j]);
+    s = block_sum_256(s, red);
+    if (threadIdx.x == 0) atomic_max_abs(scal + S_NORMA, s);
+}
+
+__global__ void __launch_bounds__(256)
+vec_absmax_kernel(const double *v, int64_t n, unsigned long long *dst) {
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double a = fabs(v[i]);
+        if (a > m || a != a) m = a;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(m, off);
+        if (o > m || o != o) m = o;
+    }
+    if ((threadIdx.x & 63) == 0) atomic_max_abs(dst, m);
+}
+
+// Blocked triangular solve with the LU factors, in place on y (FP32).
+// lower = 1: unit lower L (forward); lower = 0: upper U (backward, divides).
+__global__ void __launch_bounds__(256)
+trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, uint32_t *ticket,
+            int32_t *err, int lower) {
+    __shared__ int s_blk;
+    __shared__ float Ld[TB][TB + 1];
+    __shared__ float rhs[TB];
+    const int t = threadIdx.x, lane = t & 63;
+    const int64_t nblk = ceil_div(n, TB);
+    if (t == 0) s_blk = (int)atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t blk = lower ? s_blk : nblk - 1 - s_blk;
+    const int64_t r0 = blk * TB;
+    const int rows = (int)((n - r0 < TB) ? n - r0 : TB);
+    // diagonal block to LDS (independent of other blocks)
+    for (int e = t; e < TB * TB; e += 256) {
+        const int i = e / TB, c = e % TB;
+        Ld[i][c] = (i < rows && c < rows) ? LU[(r0 + i) * ld + r0 + c] : 0.0f;
+    }
+    // off-diagonal contributions: thread (rr = t/4, sub = t%4) covers 16 columns
+    const int rr = t >> 2, sub = t & 3;
+    float acc = 0.0f;
+    const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
+    for (int64_t d = 0; d < nb_dep; ++d) {
+        const int64_t jb = lower ? d : blk + 1 + d;
+        if (t == 0) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(flags + jb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                if (++spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        __threadfence();
+        const int64_t c0 = jb * TB + sub * 16;
+        if (rr < rows) {
+            const float *lrow = LU + (r0 + rr) * ld;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (c0 + k < n) acc = fmaf(lrow[c0 + k], y[c0 + k], acc);
+        }
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (sub == 0 && rr < rows) rhs[rr] = y[r0 + rr] - acc;
+    __syncthreads();
+    if (t < 64) {
+        float v = (lane < rows) ? rhs[lane] : 0.0f;
+        if (lower) {
+            for (int c = 0; c < rows; ++c) {
+                const float yc = __shfl(v, c);
+                if (lane > c) v = fmaf(-Ld[lane][c], yc, v);
+            }
+        } else {
+            for (int c = rows - 1; c >= 0; --c) {
+                if (lane == c) v = v / Ld[c][c];
+                const float yc = __shfl(v, c);
+                if (lane < c) v = fmaf(-Ld[lane][c], yc, v);
+            }
+        }
+        if (lane < rows) y[r0 + lane] = v;
+        __threadfence();
+        if (t == 0) __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t b = ceil_div(n, 256);
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// In-place FP32 solve of (LU) y = y on the workspace vector ws.w.
+static int lu_solve_ws(int64_t n, const float *LU, int64_t ldlu, const IrWs &w, hipStream_t s) {
+    const int64_t nb = ceil_div(n, TB);
+    for (int lower = 1; lower >= 0; --lower) {
+        hipLaunchKernelGGL(zero_i32, dim3(grid_for(nb)), dim3(256), 0, s, w.flags, nb);
+        hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.ticket, 4);
+        hipLaunchKernelGGL(trsv_kernel, dim3((unsigned)nb), dim3(256), 0, s, LU, ldlu, n, w.w,
+                           w.flags, w.ticket, w.err, lower);
+        BFX_LAUNCH_CHECK("trsv_kernel");
+    }
+    return BFX_OK;
+}
+
+static int compose_perm(int64_t n, const int32_t *ipiv, const IrWs &w, hipStream_t s) {
+    const size_t lds = sizeof(int32_t) * (size_t)n;
+    const int use_lds = lds <= 160 * 1024 - 1024;
+    if (use_lds) {
+        static size_t attr = 0;
+        if (attr < lds) {
+            BFX_HIP(hipFuncSetAttribute((const void *)perm_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr = lds;
+        }
+    }
+    hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(64), use_lds ? lds : 0, s, ipiv, n, w.perm, use_lds);
+    BFX_LAUNCH_CHECK("perm_kernel");
+    return BFX_OK;
+}
+
+static int check_err(const IrWs &w, hipStream_t s) {
+    int32_t e = 0;
+    BFX_HIP(hipMemcpyAsync(&e, w.err, sizeof e, hipMemcpyDeviceToHost, s));
+    BFX_HIP(hipStreamSynchronize(s));
+    if (e) {
+        set_error("triangular solve: a bounded wait on a block flag expired");
+        return BFX_E_INTERNAL;
+    }
+    return BFX_OK;
+}
+
+static double bits_to_double(unsigned long long u) {
+    double d;
+    memcpy(&d, &u, sizeof d);
+    return d;
+}
+
+}  // namespace bfx
+
+extern "C" size_t bfx_ir_ws_size(int64_t n) {
+    return bfx::ir_ws_layout(nullptr, nullptr, n < 0 ? 0 : n);
+}
+
+extern "C" int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu, const int32_t *ipiv,
+                                float *rhs, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0) return -1;
+    if (n > 0 && !LU) return -2;
+    if (ldlu < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && !ipiv) return -4;
+    if (n > 0 && !rhs) return -5;
+    if (!ws || ws_bytes < bfx_ir_ws_size(n)) return -7;
+    if (n == 0) return BFX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    bfx::IrWs w;
+    bfx::ir_ws_layout(&w, ws, n);
+    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, w.err, 4);
+    int rc = bfx::compose_perm(n, ipiv, w, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(bfx::gather_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, rhs, w.perm, w.w, n);
+    rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(bfx::copy_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, w.w, rhs, n);
+    BFX_LAUNCH_CHECK("copy_f32");
+    return bfx::check_err(w, s);
+}
+
+extern "C" int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
+                            int64_t ldlu, const int32_t *ipiv, const double *b, double *x,
+                            const bfx_ir_opts *opts, bfx_ir_result *res, void *ws,
+                            size_t ws_bytes, void *stream) {
+    bfx_ir_opts o = {1e-14, 30, 0};
+    if (opts) o = *opts;
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && !LU) return -4;
+    if (ldlu < (n > 1 ? n : 1)) return -5;
+    if (n > 0 && !ipiv) return -6;
+    if (n > 0 && !b) return -7;
+    if (n > 0 && !x) return -8;
+    if (!(o.tol >= 0.0) || o.max_iter < 0) return -9;
+    if (!res) return -10;
+    if (!ws || ws_bytes < bfx_ir_ws_size(n)) return -12;
+    res->iters = 0;
+    res->status = 0;
+    res->eta = 0.0;
+    if (n == 0) return BFX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    bfx::IrWs w;
+    bfx::ir_ws_layout(&w, ws, n);
+    const unsigned g = bfx::grid_for(n);
+    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, w.err, 4);
+    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.scal, 2 * bfx::S_NSCAL);
+    hipLaunchKernelGGL(bfx::mat_norm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.scal);
+    hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(g), dim3(256), 0, s, b, n, w.scal + bfx::S_NORMB);
+    int rc = bfx::compose_perm(n, ipiv, w, s);
+    if (rc) return rc;
+    // x0 = LUsolve32(b)
+    hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(g), dim3(256), 0, s, b, w.perm, 1.0, w.w, n);
+    rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(bfx::update_x, dim3(g), dim3(256), 0, s, x, w.w, 0.0, 1, n);
+    BFX_LAUNCH_CHECK("ir init");
+
+    const int vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+    unsigned long long h[bfx::S_NSCAL];
+    double prev_eta = INFINITY, eta = 0.0;
+    int it = 0, rises = 0, status = 1;
+    for (;;) {
+        hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)(w.scal + bfx::S_RN), 4);
+        hipLaunchKernelGGL(bfx::residual_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, b, x,
+                           w.r, w.scal, vec);
+        hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(g), dim3(256), 0, s, x, n, w.scal + bfx::S_XN);
+        BFX_LAUNCH_CHECK("residual");
+        BFX_HIP(hipMemcpyAsync(h, w.scal, sizeof h, hipMemcpyDeviceToHost, s));
+        BFX_HIP(hipStreamSynchronize(s));
+        const double normA = bfx::bits_to_double(h[bfx::S_NORMA]);
+        const double normb = bfx::bits_to_double(h[bfx::S_NORMB]);
+        const double rn = bfx::bits_to_double(h[bfx::S_RN]);
+        const double xn = bfx::bits_to_double(h[bfx::S_XN]);
+        const double den = normA * xn + normb;
+        eta = den > 0.0 ? rn / den : rn;
+        rises = (eta >= prev_eta) ? rises + 1 : 0;
+        prev_eta = eta;
+        if (!std::isfinite(eta)) { status = 3; break; }
+        if (eta <= o.tol) { status = 0; break; }
+        if (it >= o.max_iter) { status = 1; break; }
+        if (rises >= 2) { status = 2; break; }
+        hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(g), dim3(256), 0, s, w.r, w.perm, rn,
+                           w.w, n);
+        rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(bfx::update_x, dim3(g), dim3(256), 0, s, x, w.w, rn, 0, n);
+        BFX_LAUNCH_CHECK("ir update");
+        ++it;
+    }
+    res->iters = it;
+    res->status = status;
+    res->eta = eta;
+    return bfx::check_err(w, s);
+}

@@ -1,0 +1,187 @@
+"""GPU split GEMM (bfx_gemm) and FP32 comparator (bfx_sgemm_fp32) vs the oracle.
+
+Bar: every entry within the paper's componentwise bound of the exact product
+(FP64 of FP32 inputs) and within twice that bound of the oracle; exactly equal
+where the result is exact in any order (integers, identity operands); the
+FP32 comparator bit-identical to the oracle's FMA chain."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.gpu_util import absref, dev, gemm_bound, host, ref64
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(256, 256, 256), (200, 130, 77), (129, 257, 33), (17, 300, 5), (1, 1, 1),
+          (64, 64, 1000), (300, 40, 600), (3, 5, 4096), (130, 130, 128)]
+
+
+def _check_bound(variant, A, B, C, Corc=None, alpha=1.0):
+    K = A.shape[1]
+    z = alpha * ref64(A, B)
+    zh = abs(alpha) * absref(A, B)
+    bnd = gemm_bound(variant, K) * zh + 1e-38
+    err = np.abs(C.astype(np.float64) - z)
+    worst = float(np.max(err / bnd)) if err.size else 0.0
+    assert np.all(err <= bnd), f"variant {variant}: max err/bound {worst}"
+    if Corc is not None:
+        d = np.abs(C.astype(np.float64) - Corc.astype(np.float64))
+        assert np.all(d <= 2 * bnd)
+    return worst
+
+
+@pytest.mark.parametrize("variant", [1, 3, 6, 9])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gemm_parity_uniform(bfx, orc, variant, shape):
+    M, N, K = shape
+    A = workloads.uniform((M, K), M * 7 + K)
+    B = workloads.uniform((K, N), N * 11 + K)
+    C = host(bfx.gemm(variant, dev(A), dev(B)))
+    Co = orc.gemm(variant, A, B)
+    if variant == 1:
+        # one BF16 term: same products as the oracle, only the order differs
+        d = np.abs(C.astype(np.float64) - Co)
+        assert np.all(d <= 2 * K * 2.0 ** -24 * absref(A, B) + 1e-38)
+    else:
+        _check_bound(variant, A, B, C, Co)
+
+
+@pytest.mark.parametrize("gen", ["normal", "wide", "gauss_exp"])
+@pytest.mark.parametrize("variant", [3, 6, 9])
+def test_gemm_parity_distributions(bfx, orc, gen, variant):
+    f = getattr(workloads, gen)
+    A = f((160, 300), 21)
+    B = f((300, 144), 22)
+    C = host(bfx.gemm(variant, dev(A), dev(B)))
+    _check_bound(variant, A, B, C, orc.gemm(variant, A, B))
+
+
+@pytest.mark.parametrize("variant", [1, 3, 6, 9])
+def test_gemm_integers_exact(bfx, orc, variant):
+    g = np.random.default_rng(5)
+    A = g.integers(-8, 9, (150, 70)).astype(np.float32)
+    B = g.integers(-8, 9, (70, 190)).astype(np.float32)
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    np.testing.assert_array_equal(host(bfx.gemm(variant, dev(A), dev(B))), exact)
+
+
+@pytest.mark.parametrize("variant", [6, 9])
+def test_gemm_identity_exact(bfx, variant):
+    """a0 + (a1 + a2) rebuilds a exactly in any summation order: A x I == A."""
+    A = workloads.normal((190, 160), 6)
+    I = np.eye(160, dtype=np.float32)
+    np.testing.assert_array_equal(host(bfx.gemm(variant, dev(A), dev(I))), A)
+    I2 = np.eye(190, dtype=np.float32)
+    np.testing.assert_array_equal(host(bfx.gemm(variant, dev(I2), dev(A))), A)
+
+
+def test_gemm_alpha_beta(bfx, orc):
+    A = workloads.uniform((140, 90), 7)
+    B = workloads.uniform((90, 150), 8)
+    C0 = workloads.uniform((140, 150), 9)
+    got = host(bfx.gemm(6, dev(A), dev(B), dev(C0), alpha=-1.0, beta=1.0))
+    exact = C0.astype(np.float64) - ref64(A, B)
+    bnd = gemm_bound(6, 90) * absref(A, B) + 2.0 ** -24 * np.abs(exact) + 1e-38
+    assert np.all(np.abs(got - exact) <= bnd)
+    Cn = np.full((140, 150), np.nan, np.float32)
+    got = host(bfx.gemm(6, dev(A), dev(B), dev(Cn), alpha=2.0, beta=0.0))
+    assert np.all(np.isfinite(got))
+    _check_bound(6, A, B, got, alpha=2.0)
+
+
+def test_gemm_strided_and_unaligned(bfx, orc):
+    A = workloads.normal((100, 131), 10)
+    B = workloads.normal((131, 97), 11)
+    tA = dev(np.pad(A, ((0, 0), (0, 5))))[:, :131]      # lda = 136
+    tB = dev(np.pad(B, ((0, 0), (0, 3))))[:, :97]       # ldb = 100
+    C = host(bfx.gemm(6, tA, tB))
+    _check_bound(6, A, B, C, orc.gemm(6, A, B))
+    tA2 = dev(np.pad(A, ((0, 0), (0, 2))))[:, :131]     # lda = 133: scalar loads
+    C2 = host(bfx.gemm(6, tA2, dev(B)))
+    _check_bound(6, A, B, C2)
+
+
+def test_gemm_nonfinite_pattern(bfx, orc):
+    A = workloads.uniform((70, 64), 12)
+    B = workloads.uniform((64, 66), 13)
+    A[3, 10] = np.inf
+    B[20, 5] = np.nan
+    A[50, 7] = 3e38        # saturating split, finite
+    for v in (3, 6, 9):
+        C = host(bfx.gemm(v, dev(A), dev(B)))
+        Co = orc.gemm(v, A, B)
+        np.testing.assert_array_equal(np.isfinite(C), np.isfinite(Co))
+        np.testing.assert_array_equal(np.isnan(C), np.isnan(Co))
+
+
+def test_gemm_K0(bfx):
+    A = np.zeros((5, 0), np.float32)
+    B = np.zeros((0, 7), np.float32)
+    C = host(bfx.gemm(6, dev(A), dev(B)))
+    assert np.all(C == 0)
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 256), (200, 130, 77), (1, 1, 1), (129, 257, 33),
+                                   (64, 64, 1000)])
+def test_sgemm_bitwise_equals_oracle(bfx, orc, shape):
+    M, N, K = shape
+    A = workloads.normal((M, K), 40 + M)
+    B = workloads.normal((K, N), 41 + N)
+    np.testing.assert_array_equal(host(bfx.sgemm_fp32(dev(A), dev(B))), orc.sgemm(A, B))
+    C0 = workloads.normal((M, N), 42)
+    np.testing.assert_array_equal(host(bfx.sgemm_fp32(dev(A), dev(B), dev(C0), 0.5, -2.0)),
+                                  orc.sgemm(A, B, C0, 0.5, -2.0))
+
+
+# ---- full-size workloads: sampled entries checked against the oracle ----------
+
+def _sampled(bfx, orc, A, B, variant, nsample, seed):
+    C = host(bfx.gemm(variant, dev(A), dev(B)))
+    g = np.random.default_rng(seed)
+    r = g.integers(0, A.shape[0], nsample)
+    c = g.integers(0, B.shape[1], nsample)
+    orc_vals = orc.gemm_entries(variant, A, B, r, c)
+    z = np.einsum("ij,ji->i", A[r].astype(np.float64), B[:, c].astype(np.float64))
+    zh = np.einsum("ij,ji->i", np.abs(A[r].astype(np.float64)), np.abs(B[:, c].astype(np.float64)))
+    bnd = gemm_bound(variant, A.shape[1]) * zh + 1e-38
+    got = C[r, c].astype(np.float64)
+    assert np.all(np.abs(got - z) <= bnd), float(np.max(np.abs(got - z) / bnd))
+    assert np.all(np.abs(orc_vals - z) <= bnd)
+    assert np.all(np.abs(got - orc_vals) <= 2 * bnd)
+    assert np.all(np.isfinite(C))
+    return C
+
+
+@pytest.mark.parametrize("gen", ["normal", "wide"])
+def test_gemm_8192_sampled(bfx, orc, gen):
+    f = getattr(workloads, gen)
+    A = f((8192, 8192), 100)
+    B = f((8192, 8192), 101)
+    for v in (3, 6, 9):
+        _sampled(bfx, orc, A, B, v, 256, 7 + v)
+
+
+@pytest.mark.parametrize("cancel", [False, True])
+def test_gemm_long_k_splitk(bfx, orc, cancel):
+    """64 x 64 x 2^20 (split-K path): all 4096 entries against the FP64 product,
+    a sample against the oracle."""
+    K = 1 << 20
+    if cancel:
+        A, B = workloads.cancellation(64, K, 200)
+    else:
+        A = workloads.uniform((64, K), 201)
+        B = workloads.uniform((K, 64), 202)
+    z = ref64(A, B)
+    zh = absref(A, B)
+    for v in (3, 6, 9):
+        assert bfx.gemm_ws_size(v, 64, 64, K) > 0
+        C = host(bfx.gemm(v, dev(A), dev(B)))
+        bnd = gemm_bound(v, K) * zh
+        assert np.all(np.abs(C - z) <= bnd)
+    g = np.random.default_rng(3)
+    r = g.integers(0, 64, 24)
+    c = g.integers(0, 64, 24)
+    o = orc.gemm_entries(6, A, B, r, c)
+    C6 = host(bfx.gemm(6, dev(A), dev(B)))
+    assert np.all(np.abs(C6[r, c] - o) <= 2 * gemm_bound(6, K) * zh[r, c])

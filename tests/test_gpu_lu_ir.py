@@ -1,0 +1,161 @@
+"""GPU LU (bfx_lu_factor), FP32 LU solve and iterative refinement (bfx_ir_solve)
+against the oracle and LAPACK.
+
+LU has several correct answers once summation orders differ (near-tie pivots
+can flip), so beyond one panel it is judged by what is unique: a valid
+permutation, the componentwise backward error of Gaussian elimination, the
+agreement of pivots with the oracle (reported, required above 95%), and the
+refinement result.  Up to one panel (n <= 128) the GPU performs exactly the
+oracle's operations, so there the factors must be bit-identical."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import workloads
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def perm_from_ipiv(ipiv, n):
+    p = np.arange(n)
+    for i, q in enumerate(ipiv):
+        p[[i, q]] = p[[q, i]]
+    return p
+
+
+def backward_ok(A, LU, ipiv, slack=2.0):
+    n = A.shape[0]
+    p = perm_from_ipiv(ipiv, n)
+    L = np.tril(LU.astype(np.float64), -1) + np.eye(n)
+    U = np.triu(LU.astype(np.float64))
+    R = np.abs(A.astype(np.float64)[p] - L @ U)
+    scale = np.abs(L) @ np.abs(U)
+    ratio = R / (n * 2.0 ** -24 * scale + 1e-300)
+    return float(ratio.max()) <= slack, float(ratio.max())
+
+
+def gpu_lu(bfx, A, variant=6):
+    t = dev(A)
+    _, ipiv, info = bfx.lu_factor(t, variant)
+    return host(t), host(ipiv), int(host(info)[0])
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 100, 128])
+def test_lu_single_panel_bitwise(bfx, orc, n):
+    A = workloads.normal((n, n), 500 + n)
+    LU, ipiv, info = gpu_lu(bfx, A)
+    LUo, ipo, info_o = orc.lu(A, 6, 128)
+    assert info == info_o == 0
+    np.testing.assert_array_equal(ipiv, ipo)
+    np.testing.assert_array_equal(LU, LUo)
+
+
+@pytest.mark.parametrize("n", [129, 300, 513, 1000])
+@pytest.mark.parametrize("variant", [6, 9])
+def test_lu_multi_panel(bfx, orc, n, variant):
+    A = workloads.uniform((n, n), 600 + n)
+    LU, ipiv, info = gpu_lu(bfx, A, variant)
+    assert info == 0
+    assert np.all(ipiv >= np.arange(n)) and np.all(ipiv < n)
+    ok, ratio = backward_ok(A, LU, ipiv)
+    assert ok, ratio
+    LUo, ipo, _ = orc.lu(A, variant, 128)
+    agree = float(np.mean(ipiv == ipo))
+    assert agree > 0.95, agree
+    if agree == 1.0:
+        tol = 64 * n * 2.0 ** -24 * np.abs(LUo).max()
+        assert np.max(np.abs(LU - LUo)) <= tol
+
+
+def test_lu_pivots_match_lapack(bfx):
+    n = 700
+    A = workloads.normal((n, n), 31)
+    LU, ipiv, info = gpu_lu(bfx, A)
+    _, piv64 = sla.lu_factor(A.astype(np.float64))
+    assert float(np.mean(ipiv == piv64)) > 0.95
+
+
+def test_lu_diagonally_dominant_no_pivoting(bfx):
+    n = 520
+    A = workloads.uniform((n, n), 32)
+    A += np.diag(np.abs(A).sum(axis=0) + 1).astype(np.float32)
+    LU, ipiv, info = gpu_lu(bfx, A)
+    np.testing.assert_array_equal(ipiv, np.arange(n))
+    assert backward_ok(A, LU, ipiv)[0]
+
+
+@pytest.mark.parametrize("n,col", [(20, 6), (300, 200)])
+def test_lu_singular_info(bfx, n, col):
+    A = workloads.uniform((n, n), 33)
+    A[:, col] = 0
+    LU, ipiv, info = gpu_lu(bfx, A)
+    assert info == col + 1
+    assert np.all(np.isfinite(LU[:, :col]))
+
+
+def test_lu_solve_f32_matches_oracle(bfx, orc):
+    n = 333
+    A = workloads.normal((n, n), 34)
+    LUo, ipo, _ = orc.lu(A, 6, 128)
+    b = workloads.normal((n,), 35)
+    got = host(bfx.lu_solve_f32(dev(LUo), dev(ipo), dev(b)))
+    exp = orc.lu_solve(LUo, ipo, b)
+    x64 = sla.lu_solve((LUo.astype(np.float64), ipo), b.astype(np.float64))
+    assert np.max(np.abs(got - x64)) <= 1e-3 * np.max(np.abs(x64))
+    assert np.max(np.abs(got - exp)) <= 1e-3 * np.max(np.abs(x64))
+
+
+def _ir(bfx, A, b, tol=1e-14, max_iter=30):
+    tA = dev(A)
+    tLU = tA.clone()
+    _, ipiv, info = bfx.lu_factor(tLU, 6)
+    x, res = bfx.ir_solve(tA, tLU, ipiv, dev(b), tol=tol, max_iter=max_iter)
+    return host(x), res, int(host(info)[0])
+
+
+@pytest.mark.parametrize("kappa", [1e1, 1e2, 1e3, 1e4])
+def test_ir_table_n50(bfx, orc, kappa):
+    """IR table, FP32 rows: n = 50, kappa up to 1e4, all converge in a few steps."""
+    its = []
+    for s in range(5):
+        A, b, xt = workloads.conditioned_system(50, kappa, 700 + s)
+        x, res, info = _ir(bfx, A, b)
+        assert res["status"] == 0 and res["eta"] <= 1e-14, res
+        r = b - A.astype(np.float64) @ x
+        eta = np.abs(r).max() / (np.abs(A.astype(np.float64)).sum(1).max() * np.abs(x).max()
+                                 + np.abs(b).max())
+        assert eta <= 1.01e-14
+        its.append(res["iters"])
+        LU, ipiv, _ = orc.lu(A, 6, 128)
+        ro = orc.ir(A, LU, ipiv, b)
+        assert abs(ro["iters"] - res["iters"]) <= 2
+        xr = np.linalg.solve(A.astype(np.float64), b)
+        assert np.max(np.abs(x - xr)) <= 50 * kappa * 2.0 ** -52 * np.max(np.abs(xr))
+    assert np.mean(its) <= 5
+
+
+@pytest.mark.parametrize("n,kappa", [(1000, 1e4), (2048, 1e1)])
+def test_ir_larger(bfx, n, kappa):
+    A, b, xt = workloads.conditioned_system(n, kappa, 800 + n)
+    x, res, info = _ir(bfx, A, b)
+    assert res["status"] == 0 and res["eta"] <= 1e-14, res
+    assert np.max(np.abs(x - xt)) <= 100 * kappa * 2.0 ** -52 * np.max(np.abs(xt)) * np.sqrt(n)
+
+
+def test_ir_status_codes(bfx):
+    A, b, _ = workloads.conditioned_system(64, 1e4, 5)
+    x, res, _ = _ir(bfx, A, b, max_iter=0)
+    assert res["status"] == 1 and res["iters"] == 0
+    As = A.copy()
+    As[:, 3] = 0
+    x, res, info = _ir(bfx, As, b, max_iter=5)
+    assert info > 0 and res["status"] == 3
+
+
+def test_ir_high_kappa_reported(bfx):
+    """kappa = 1e12: classic LU-IR with an FP32-accurate LU stalls (reported)."""
+    A, b, _ = workloads.conditioned_system(256, 1e12, 6)
+    x, res, _ = _ir(bfx, A, b)
+    assert res["status"] in (1, 2) and res["eta"] > 1e-14

@@ -110,3 +110,31 @@ def conditioned_system(n: int, kappa: float, seed: int):
 
 def batch_sizes(count: int, seed: int, lo: int = 64, hi: int = 1024) -> np.ndarray:
     return rng(seed).integers(lo, hi + 1, size=count).astype(np.int64)
+
+
+def conditioned_system_torch(n: int, kappa: float, seed: int, device):
+    """Large-n version of `conditioned_system` generated on the GPU: Gaussian
+    matrices from torch's seeded device generator, Householder QR (sign of
+    diag(R) folded in), A = U diag(s) V^T in FP64 rounded to FP32,
+    x_true ~ N(0,1), b = A32 x_true in FP64.  Returns (A32, b64) on `device`."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar_t():
+        Z = torch.randn(n, n, dtype=torch.float64, device=device, generator=g)
+        Q, R = torch.linalg.qr(Z)
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        del Z, R
+        return Q * d[None, :]
+
+    U = haar_t()
+    V = haar_t()
+    s = kappa ** (-torch.arange(n, dtype=torch.float64, device=device) / max(n - 1, 1))
+    A = ((U * s[None, :]) @ V.T.contiguous()).to(torch.float32)
+    del U, V
+    x_true = torch.randn(n, dtype=torch.float64, device=device, generator=g)
+    b = A.to(torch.float64) @ x_true
+    return A.contiguous(), b
