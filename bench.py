@@ -41,6 +41,9 @@ def parse():
                     help="only the timed step, roofline and CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: one 1 GiB device-to-device copy (calibration "
+                         "of the HBM byte counters) followed by one x6 GEMM, no timing")
     return ap.parse_args()
 
 
@@ -94,6 +97,20 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     n = args.size
+    if args.pmc_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)          # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
+        tA = torch.from_numpy(workloads.normal((n, n), 100)).to(dev)
+        tB = torch.from_numpy(workloads.normal((n, n), 101)).to(dev)
+        tC = torch.empty((n, n), dtype=torch.float32, device=dev)
+        bfx.gemm(6, tA, tB, tC)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": "done", "copy_bytes": 1 << 30, "gemm": [n, n, n]}))
+        return
     log(f"[bench] generating {n}x{n} N(0,1) operands")
     A = workloads.normal((n, n), 100)
     B = workloads.normal((n, n), 101)
@@ -124,7 +141,7 @@ def main():
     achieved = bf16_flop / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": "gemm_split_kernel<6,128,128,2,2>",
+                "traffic": None, "kernel": "gemm_fast_kernel<6>",
                 "algorithmic_flop_per_launch": bf16_flop, "avg_launch_ms": round(avg_ms, 4)}
 
     import oracle as orc
@@ -221,6 +238,11 @@ def main():
         except Exception as e:  # report, do not hide
             extras["solves"] = {"error": repr(e)}
         log(f"[bench] solves {extras['solves']}")
+        try:
+            extras["batched_solves_512"] = bench_batched_solves(torch, bfx, workloads, dev, stream)
+        except Exception as e:
+            extras["batched_solves_512"] = {"error": repr(e)}
+        log(f"[bench] batched solves {extras['batched_solves_512']}")
 
     # ---------------- CPU baseline: the oracle on a row sample ----------------
     cores = orc.num_threads()
@@ -275,6 +297,38 @@ def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
                                        "eta": r["eta"], "info": int(info.item())}
         del A, b, LU, x
     return res
+
+
+def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512, kappa=1e4):
+    t0 = time.perf_counter()
+    systems, sizes = workloads.batch_systems_torch(count, kappa, 11, dev)
+    log(f"[bench] generated {count} systems (n in [64,1024]) in {time.perf_counter() - t0:.1f}s")
+    probs = [(A, b, torch.empty(b.shape[0], dtype=torch.float64, device=dev)) for (A, b) in systems]
+    plan = bfx.BatchedSolvePlan(6, probs)
+    plan.launch()
+    res = plan.results()
+    ms, _ = time_launches(torch, plan.launch, 3, stream)
+    conv = sum(1 for r in res if r["status"] == 0)
+    out = {"ms": round(ms, 3), "solves_per_s": round(count / (ms * 1e-3), 1),
+           "converged": conv, "count": count, "kappa": kappa,
+           "max_eta": max(r["eta"] for r in res),
+           "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+           "lu_flop_fp32eq": float(sum(2.0 / 3.0 * int(n) ** 3 for n in sizes))}
+    plan.close()
+    sub = probs[:64]
+    plan2 = bfx.BatchedSolvePlan(6, sub)
+    plan2.launch_per_problem()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan2.launch_per_problem()
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / len(sub)
+    plan2.close()
+    out["per_problem_ms_each"] = round(per * 1e3, 3)
+    out["per_problem_extrapolated_ms"] = round(per * 1e3 * count, 1)
+    out["speedup_vs_per_problem"] = round(per * 1e3 * count / ms, 1)
+    del probs, systems
+    return out
 
 
 if __name__ == "__main__":

@@ -194,6 +194,45 @@ int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu,
                      const int32_t *ipiv, float *rhs, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Many independent solves A x = b in one persistent, graph-captured launch:  */
+/* split-BF16 blocked LU (Sec. I, IV-A) + FP64-residual refinement (Sec. III) */
+/* for each problem, one workgroup per problem, longest problems first.       */
+/* ------------------------------------------------------------------------ */
+typedef struct bfx_solve_desc {
+    int64_t n;                     /* 1 <= n <= 1024 */
+    const float *A; int64_t lda;   /* device, row-major FP32 n x n, not modified */
+    const double *b;               /* device, n FP64 */
+    double *x;                     /* device, n FP64, output */
+} bfx_solve_desc;
+
+typedef struct bfx_solve_plan bfx_solve_plan;
+
+/* descs: HOST array (copied).  opts: HOST pointer (NULL = tol 1e-14,
+ * max_iter 30).  The plan owns the factor storage (sum of n^2 FP32), the
+ * pivots and the per-problem results until bfx_solve_plan_destroy.  The
+ * stopping rule and status codes are those of bfx_ir_solve.
+ * Errors: -1 variant, -2 count < 0, -3 descs NULL, -4 opts invalid, -5 out
+ * NULL, -(100+i) when descriptor i is invalid. */
+int bfx_lu_ir_batched_plan_create(int variant, int64_t count,
+                                  const bfx_solve_desc *descs,
+                                  const bfx_ir_opts *opts, bfx_solve_plan **out);
+
+/* All solves as one graph replay on `stream` (asynchronous). */
+int bfx_solve_plan_launch(bfx_solve_plan *plan, void *stream);
+
+/* Same solves with bfx_lu_factor + bfx_ir_solve per problem (the baseline the
+ * persistent launch is measured against; synchronises after each problem). */
+int bfx_solve_plan_launch_per_problem(bfx_solve_plan *plan, void *stream);
+
+/* Synchronises the device and copies the per-problem refinement results and
+ * LU info (HOST arrays of `count` entries, in descriptor order; either may be
+ * NULL). */
+int bfx_solve_plan_results(const bfx_solve_plan *plan, bfx_ir_result *results,
+                           int32_t *info);
+
+int bfx_solve_plan_destroy(bfx_solve_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

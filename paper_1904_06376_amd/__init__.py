@@ -5,8 +5,8 @@ Henry, Tang & Heinecke, "Leveraging the bfloat16 Artificial Intelligence
 Datatype For Higher-Precision Computations" (2019).
 """
 from ._lib import EXPORTED, BfxError, lib  # noqa: F401  (fails loudly if unbuilt)
-from .api import (BatchedGemmPlan, gemm, gemm_ws_size, ir_solve, lu_factor,  # noqa: F401
-                  lu_solve_f32, sgemm_fp32, split)
+from .api import (BatchedGemmPlan, BatchedSolvePlan, gemm, gemm_ws_size,  # noqa: F401
+                  ir_solve, lu_factor, lu_solve_f32, sgemm_fp32, split)
 
-__all__ = ["split", "gemm", "gemm_ws_size", "sgemm_fp32", "BatchedGemmPlan",
+__all__ = ["split", "gemm", "gemm_ws_size", "sgemm_fp32", "BatchedGemmPlan", "BatchedSolvePlan",
            "lu_factor", "lu_solve_f32", "ir_solve", "BfxError", "EXPORTED"]

@@ -33,6 +33,10 @@ class GemmDesc(ctypes.Structure):
                 ("alpha", c_f32), ("beta", c_f32)]
 
 
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("A", c_vp), ("lda", c_i64), ("b", c_vp), ("x", c_vp)]
+
+
 class IrOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
@@ -63,6 +67,12 @@ SIGNATURES = {
                       c_vp], c_int),
     "bfx_ir_ws_size": ([c_i64], c_size),
     "bfx_lu_solve_f32": ([c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_size, c_vp], c_int),
+    "bfx_lu_ir_batched_plan_create": ([c_int, c_i64, ctypes.POINTER(SolveDesc),
+                                       ctypes.POINTER(IrOpts), ctypes.POINTER(c_vp)], c_int),
+    "bfx_solve_plan_launch": ([c_vp, c_vp], c_int),
+    "bfx_solve_plan_launch_per_problem": ([c_vp, c_vp], c_int),
+    "bfx_solve_plan_results": ([c_vp, ctypes.POINTER(IrResult), ctypes.POINTER(ctypes.c_int32)], c_int),
+    "bfx_solve_plan_destroy": ([c_vp], c_int),
 }
 
 EXPORTED = []

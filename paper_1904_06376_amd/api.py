@@ -7,7 +7,7 @@ import ctypes
 
 import torch
 
-from ._lib import GemmDesc, IrOpts, IrResult, check, lib
+from ._lib import GemmDesc, IrOpts, IrResult, SolveDesc, check, lib
 
 
 def _stream() -> int:
@@ -177,3 +177,48 @@ def ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Ten
                            ctypes.byref(res), ws.data_ptr() if ws is not None else None,
                            need, _stream()), "bfx_ir_solve")
     return x, dict(iters=res.iters, status=res.status, eta=res.eta)
+
+
+class BatchedSolvePlan:
+    """Many LU + refinement solves in one persistent, graph-captured launch.
+
+    problems: list of (A float32 n x n, b float64 n, x float64 n) GPU tensors."""
+
+    def __init__(self, variant: int, problems, tol: float = 1e-14, max_iter: int = 30):
+        self._keep = problems
+        descs = (SolveDesc * len(problems))()
+        for i, (A, b, x) in enumerate(problems):
+            _dev(A, torch.float32, "A")
+            _dev(b, torch.float64, "b")
+            _dev(x, torch.float64, "x")
+            descs[i] = SolveDesc(A.shape[0], A.data_ptr(), _rows(A, "A"), b.data_ptr(), x.data_ptr())
+        opts = IrOpts(tol, max_iter, 0)
+        h = ctypes.c_void_p()
+        check(lib.bfx_lu_ir_batched_plan_create(variant, len(problems), descs, ctypes.byref(opts),
+                                                 ctypes.byref(h)), "solve_plan_create")
+        self._h = h
+        self.count = len(problems)
+
+    def launch(self):
+        check(lib.bfx_solve_plan_launch(self._h, _stream()), "bfx_solve_plan_launch")
+
+    def launch_per_problem(self):
+        check(lib.bfx_solve_plan_launch_per_problem(self._h, _stream()), "solve_per_problem")
+
+    def results(self):
+        res = (IrResult * max(self.count, 1))()
+        info = (ctypes.c_int32 * max(self.count, 1))()
+        check(lib.bfx_solve_plan_results(self._h, res, info), "bfx_solve_plan_results")
+        return [dict(iters=r.iters, status=r.status, eta=r.eta, info=int(i))
+                for r, i in zip(list(res)[: self.count], list(info)[: self.count])]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.bfx_solve_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,6 +2,8 @@
 // split-K for long inner dimensions with a deterministic fixed-order
 // reduction, and the host-side tile / split policy.  The tile engine itself
 // is in gemm_tile.hpp.
+#include <cstdlib>
+
 #include "gemm_tile.hpp"
 
 namespace bfx {
@@ -29,6 +31,29 @@ gemm_split_kernel(GemmParams p) {
     gemm_tile<V, BM, BN, WM, WN>(p, m0, n0, kb, ke, split, smem);
 }
 
+// Aligned 128 x 128 tiles (see gemm_tile_fast).
+template <int V>
+__global__ void __launch_bounds__(256, 1)
+gemm_fast_kernel(GemmParams p) {
+    extern __shared__ __align__(16) uint16_t smem[];
+    const int64_t tiles_m = p.M / 128, tiles_n = p.N / 128;
+    const int64_t tiles = tiles_m * tiles_n;
+    const int64_t total = tiles * p.splits;
+    const int64_t id = xcd_remap(blockIdx.x, total);
+    const int64_t split = id / tiles;
+    const int64_t t = id % tiles;
+    constexpr int GROUP = 8;
+    const int64_t group = t / (GROUP * tiles_n);
+    const int64_t first_m = group * GROUP;
+    const int64_t gsz = (tiles_m - first_m < GROUP) ? tiles_m - first_m : GROUP;
+    const int64_t in_g = t % (GROUP * tiles_n);
+    const int64_t m0 = (first_m + in_g % gsz) * 128;
+    const int64_t n0 = (in_g / gsz) * 128;
+    const int64_t kb = split * p.k_per_split;
+    const int64_t ke = (kb + p.k_per_split < p.K) ? kb + p.k_per_split : p.K;
+    gemm_tile_fast<V>(p, m0, n0, kb, ke, split, smem);
+}
+
 // Fixed-order reduction of split-K partials, then the epilogue.
 __global__ void __launch_bounds__(256)
 splitk_reduce_kernel(const float *__restrict__ partial, int splits, int64_t M,
@@ -50,6 +75,12 @@ splitk_reduce_kernel(const float *__restrict__ partial, int splits, int64_t M,
 
 // --------------------------------------------------------------------------
 // Host side: tile choice and split-K policy.
+// BFX_GEMM_GENERAL=1 in the environment disables the aligned fast path (used
+// by tests to exercise the general engine on aligned shapes).
+static const bool g_force_general = [] {
+    const char *e = getenv("BFX_GEMM_GENERAL");
+    return e && e[0] == '1';
+}();
 // --------------------------------------------------------------------------
 template <int V, int BM, int BN, int WM, int WN>
 static int launch_tiles(const GemmParams &p, hipStream_t s) {
@@ -95,7 +126,34 @@ size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K) {
 }
 
 template <int V>
+static int launch_fast(const GemmParams &p, hipStream_t s) {
+    const size_t lds = tile_lds_bytes<V, 128, 128>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        BFX_HIP(hipFuncSetAttribute((const void *)gemm_fast_kernel<V>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    const int64_t blocks = (p.M / 128) * (p.N / 128) * p.splits;
+    hipLaunchKernelGGL(gemm_fast_kernel<V>, dim3((unsigned)blocks), dim3(256), lds, s, p);
+    BFX_LAUNCH_CHECK("gemm_fast_kernel launch");
+    return BFX_OK;
+}
+
+// The aligned fast path applies when every tile is full, every K range is a
+// whole number of 32-steps and rows are 16-byte aligned.
+// Buffer offsets are 32-bit: 128 rows of A and one split's K rows of B must
+// each span less than 2^31 bytes.
+static bool fast_ok(const GemmParams &p) {
+    return p.M % 128 == 0 && p.N % 128 == 0 && p.K % BK == 0 && p.K > 0 &&
+           p.k_per_split % BK == 0 && p.vecA && p.vecB && ((uintptr_t)p.C % 4 == 0) &&
+           128 * p.lda * 4 < (int64_t(1) << 31) &&
+           p.k_per_split * p.ldb * 4 < (int64_t(1) << 31);
+}
+
+template <int V>
 static int dispatch_variant(GemmParams &p, int BM, int BN, hipStream_t s) {
+    if (BM == 128 && fast_ok(p) && !g_force_general) return launch_fast<V>(p, s);
     if (BM == 64) return launch_tiles<V, 64, 64, 2, 2>(p, s);
     return launch_tiles<V, 128, 128, 2, 2>(p, s);
 }

@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(256)
 trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, uint32_t *ticket,
             int32_t *err, int lower) {
     __shared__ int s_blk;
+    __shared__ int64_t s_known;
     __shared__ float Ld[TB][TB + 1];
     __shared__ float rhs[TB];
     const int t = threadIdx.x, lane = t & 63;
@@ -209,22 +210,40 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
         const int i = e / TB, c = e % TB;
         Ld[i][c] = (i < rows && c < rows) ? LU[(r0 + i) * ld + r0 + c] : 0.0f;
     }
-    // off-diagonal contributions: thread (rr = t/4, sub = t%4) covers 16 columns
+    // Off-diagonal contributions: thread (rr = t/4, sub = t%4) covers 16
+    // columns.  Dependencies are visited in completion order (ascending for
+    // L, descending for U).  A block only completes after every block before
+    // it in that order, so one acquire of a flag covers all earlier blocks and
+    // thread 0 waits only when the next block is not yet known complete.
     const int rr = t >> 2, sub = t & 3;
     float acc = 0.0f;
     const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
+    int64_t known = 0;  // dependencies known complete
     for (int64_t d = 0; d < nb_dep; ++d) {
-        const int64_t jb = lower ? d : blk + 1 + d;
-        if (t == 0) {
-            unsigned spins = 0;
-            while (__hip_atomic_load(flags + jb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                if (++spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
-                __builtin_amdgcn_s_sleep(1);
+        const int64_t jb = lower ? d : nblk - 1 - d;
+        if (d >= known) {
+            if (t == 0) {
+                unsigned spins = 0;
+                while (__hip_atomic_load(flags + jb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                    if (++spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                // extend over dependencies that are already complete: scan with
+                // relaxed loads, then one acquire on the furthest one found
+                int64_t e = d + 1;
+                while (e < nb_dep &&
+                       __hip_atomic_load(flags + (lower ? e : nblk - 1 - e), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) != 0)
+                    ++e;
+                if (e > d + 1)
+                    (void)__hip_atomic_load(flags + (lower ? e - 1 : nblk - e), __ATOMIC_ACQUIRE,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+                s_known = e;
             }
+            __syncthreads();
+            known = s_known;
         }
-        __syncthreads();
-        __threadfence();
         const int64_t c0 = jb * TB + sub * 16;
         if (rr < rows) {
             const float *lrow = LU + (r0 + rr) * ld;
@@ -252,8 +271,11 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
             }
         }
         if (lane < rows) y[r0 + lane] = v;
+    }
+    __syncthreads();
+    if (t == 0) {
         __threadfence();
-        if (t == 0) __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

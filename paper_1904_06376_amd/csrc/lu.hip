@@ -214,31 +214,38 @@ laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *
     }
 }
 
-// U12 = L11^{-1} A12: each thread solves one column of A12 by forward
-// substitution, s = a_i - sum_{p<i} L_ip x_p as an FMA chain in increasing p.
-__global__ void __launch_bounds__(256)
+// U12 = L11^{-1} A12.  Each 128-thread workgroup copies 128 columns of A12
+// and L11 into LDS; each thread then solves its own column by forward
+// substitution in row order, s = a_r - sum_{p<r} L_rp x_p as one FMA chain in
+// increasing p (the unblocked algorithm's order), and the block is copied back.
+constexpr int TRSM_COLS = 128;
+__global__ void __launch_bounds__(TRSM_COLS)
 trsm_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w) {
-    extern __shared__ float L[];  // [PNB][PNB], zero-padded beyond w
-    for (int e = threadIdx.x; e < PNB * PNB; e += 256) {
+    extern __shared__ float sm[];
+    float *L = sm;                    // [PNB][PNB]
+    float *X = sm + PNB * PNB;        // [PNB][TRSM_COLS + 1]
+    constexpr int XLD = TRSM_COLS + 1;
+    const int t = threadIdx.x;
+    const int64_t c0 = j + w + (int64_t)blockIdx.x * TRSM_COLS;
+    const int ncols = (int)((n - c0 < TRSM_COLS) ? n - c0 : TRSM_COLS);
+    for (int e = t; e < PNB * PNB; e += TRSM_COLS) {
         const int i = e / PNB, p = e % PNB;
         L[e] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
     }
+    for (int i = 0; i < w; ++i)
+        if (t < ncols) X[i * XLD + t] = A[(j + i) * lda + c0 + t];
     __syncthreads();
-    const int64_t col = j + w + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (col >= n) return;
-    float x[PNB];
-#pragma unroll
-    for (int i = 0; i < PNB; ++i) x[i] = (i < w) ? A[(j + i) * lda + col] : 0.0f;
-#pragma unroll
-    for (int i = 1; i < PNB; ++i) {
-        float s = x[i];
-#pragma unroll
-        for (int p = 0; p < i; ++p) s = fmaf(-L[i * PNB + p], x[p], s);
-        x[i] = s;
+    if (t < ncols) {
+        for (int i = 1; i < w; ++i) {
+            float s = X[i * XLD + t];
+            const float *li = L + i * PNB;
+            for (int p = 0; p < i; ++p) s = fmaf(-li[p], X[p * XLD + t], s);
+            X[i * XLD + t] = s;
+        }
     }
-#pragma unroll
-    for (int i = 0; i < PNB; ++i)
-        if (i < w) A[(j + i) * lda + col] = x[i];
+    __syncthreads();
+    for (int i = 1; i < w; ++i)
+        if (t < ncols) A[(j + i) * lda + c0 + t] = X[i * XLD + t];
 }
 
 static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv,
@@ -252,7 +259,7 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
                                     PROWS * (PNB + 1) * (int)sizeof(float)));
         BFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    PNB * PNB * (int)sizeof(float)));
+                                    (PNB * PNB + PNB * (TRSM_COLS + 1)) * (int)sizeof(float)));
         attr = true;
     }
     BFX_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
@@ -276,8 +283,8 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         }
         const int64_t rest = n - j - jb;
         if (rest <= 0) continue;
-        hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(rest, 256)), dim3(256),
-                           PNB * PNB * sizeof(float), s, A, lda, n, j, jb);
+        hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(rest, TRSM_COLS)), dim3(TRSM_COLS),
+                           (PNB * PNB + PNB * (TRSM_COLS + 1)) * sizeof(float), s, A, lda, n, j, jb);
         BFX_LAUNCH_CHECK("trsm_kernel");
         float *A21 = A + (j + jb) * lda + j;
         float *A12 = A + j * lda + (j + jb);

@@ -1,0 +1,90 @@
+"""Batched LU + refinement in one persistent launch (bfx_lu_ir_batched_plan_*):
+every problem converges to eta <= 1e-14 (recomputed in numpy), agrees with
+LAPACK's FP64 solve within the conditioning, takes about as many refinement
+steps as the oracle, matches the one-problem-at-a-time path, and replays
+bit-identically."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 17, 64, 100, 128, 129, 200, 255, 333, 512, 700, 1024]
+
+
+def _systems(sizes, kappa, seed):
+    return [workloads.conditioned_system(n, kappa, seed + i) for i, n in enumerate(sizes)]
+
+
+def _eta(A, b, x):
+    A = A.astype(np.float64)
+    r = b - A @ x
+    return np.abs(r).max() / (np.abs(A).sum(1).max() * np.abs(x).max() + np.abs(b).max())
+
+
+@pytest.mark.parametrize("kappa", [1e1, 1e4])
+def test_batched_solves_converge(bfx, orc, kappa):
+    systems = _systems(SIZES, kappa, 900)
+    probs = [(dev(A), dev(b), torch.empty(len(b), dtype=torch.float64, device="cuda"))
+             for (A, b, _) in systems]
+    plan = bfx.BatchedSolvePlan(6, probs)
+    plan.launch()
+    res = plan.results()
+    for (A, b, xt), (_, _, tx), r, n in zip(systems, probs, res, SIZES):
+        x = host(tx)
+        assert r["status"] == 0 and r["info"] == 0, (n, r)
+        assert r["eta"] <= 1e-14 and _eta(A, b, x) <= 1.01e-14, (n, r)
+        xr = np.linalg.solve(A.astype(np.float64), b)
+        assert np.max(np.abs(x - xr)) <= 100 * kappa * 2.0 ** -52 * max(n, 1) ** 0.5 * np.max(np.abs(xr))
+        if n <= 333:
+            LU, ipiv, _ = orc.lu(A, 6, 32)
+            ro = orc.ir(A, LU, ipiv, b)
+            assert ro["status"] == 0 and abs(ro["iters"] - r["iters"]) <= 2, (n, ro, r)
+    plan.close()
+
+
+def test_batched_solves_match_per_problem_and_replay(bfx):
+    sizes = [64, 200, 513, 1000]
+    systems = _systems(sizes, 1e3, 950)
+    probs = [(dev(A), dev(b), torch.empty(len(b), dtype=torch.float64, device="cuda"))
+             for (A, b, _) in systems]
+    plan = bfx.BatchedSolvePlan(6, probs)
+    plan.launch_per_problem()
+    per = [host(p[2]).copy() for p in probs]
+    res_pp = plan.results()
+    plan.launch()
+    first = [host(p[2]).copy() for p in probs]
+    res = plan.results()
+    for (A, b, _), a, c, r1, r2 in zip(systems, per, first, res_pp, res):
+        assert r1["status"] == 0 and r2["status"] == 0
+        assert _eta(A, b, a) <= 1.01e-14 and _eta(A, b, c) <= 1.01e-14
+    for _ in range(3):
+        for p in probs:
+            p[2].fill_(float("nan"))
+        _ = torch.randn(100, device="cuda").sum().item()
+        plan.launch()
+        torch.cuda.synchronize()
+        for p, f in zip(probs, first):
+            np.testing.assert_array_equal(host(p[2]), f)
+    plan.close()
+
+
+def test_batched_solves_singular_and_limits(bfx):
+    A, b, _ = workloads.conditioned_system(80, 10.0, 960)
+    As = A.copy()
+    As[:, 5] = 0
+    probs = [(dev(As), dev(b), torch.empty(80, dtype=torch.float64, device="cuda")),
+             (dev(A), dev(b), torch.empty(80, dtype=torch.float64, device="cuda"))]
+    plan = bfx.BatchedSolvePlan(6, probs, max_iter=0)
+    plan.launch()
+    r = plan.results()
+    assert r[0]["info"] == 6 and r[0]["status"] == 3
+    assert r[1]["status"] == 1 and r[1]["iters"] == 0
+    plan.close()
+    big = torch.zeros((1025, 1025), dtype=torch.float32, device="cuda")
+    with pytest.raises(Exception):
+        bfx.BatchedSolvePlan(6, [(big, torch.zeros(1025, dtype=torch.float64, device="cuda"),
+                                  torch.zeros(1025, dtype=torch.float64, device="cuda"))])

@@ -115,6 +115,44 @@ def test_gemm_nonfinite_pattern(bfx, orc):
         np.testing.assert_array_equal(np.isnan(C), np.isnan(Co))
 
 
+@pytest.mark.parametrize("variant", [1, 3, 6, 9])
+def test_gemm_fast_path_nonfinite_and_saturating(bfx, orc, variant):
+    """128-aligned shapes take the branch-free fast path; values whose first
+    BF16 term would be Inf/NaN are re-split exactly out of band."""
+    A = workloads.uniform((256, 128), 14)
+    B = workloads.uniform((128, 256), 15)
+    A[5, 3] = np.inf
+    A[200, 100] = -np.inf
+    B[64, 77] = np.nan
+    A[130, 31] = 3.3e38      # rounds past the largest BF16: saturating split
+    B[127, 255] = -3.39e38
+    C = host(bfx.gemm(variant, dev(A), dev(B)))
+    Co = orc.gemm(variant, A, B)
+    np.testing.assert_array_equal(np.isfinite(C), np.isfinite(Co))
+    np.testing.assert_array_equal(np.isnan(C), np.isnan(Co))
+    fin = np.isfinite(Co)
+    A2 = np.where(np.isfinite(A), A, 0).astype(np.float32)
+    B2 = np.where(np.isfinite(B), B, 0).astype(np.float32)
+    zh = absref(A2, B2)
+    bnd = gemm_bound(variant, 128) * zh + 1e-30
+    assert np.all(np.abs(C[fin] - Co[fin]) <= 2 * bnd[fin])
+
+
+@pytest.mark.parametrize("variant", [3, 6, 9])
+def test_gemm_fast_vs_general_engine(bfx, orc, variant):
+    """The same aligned product through the fast path and (with lda not a
+    multiple of 4) through the general engine: both within the bound."""
+    A = workloads.normal((384, 256), 16)
+    B = workloads.normal((256, 512), 17)
+    Cf = host(bfx.gemm(variant, dev(A), dev(B)))
+    tA = dev(np.pad(A, ((0, 0), (0, 1))))[:, :256]
+    Cg = host(bfx.gemm(variant, tA, dev(B)))
+    bnd = gemm_bound(variant, 256) * absref(A, B)
+    z = ref64(A, B)
+    assert np.all(np.abs(Cf - z) <= bnd) and np.all(np.abs(Cg - z) <= bnd)
+    assert np.all(np.abs(Cf - Cg) <= 2 * bnd)
+
+
 def test_gemm_K0(bfx):
     A = np.zeros((5, 0), np.float32)
     B = np.zeros((0, 7), np.float32)

@@ -138,3 +138,13 @@ def conditioned_system_torch(n: int, kappa: float, seed: int, device):
     x_true = torch.randn(n, dtype=torch.float64, device=device, generator=g)
     b = A.to(torch.float64) @ x_true
     return A.contiguous(), b
+
+
+def batch_systems_torch(count: int, kappa: float, seed: int, device, lo: int = 64, hi: int = 1024):
+    """`count` conditioned systems with n ~ U{lo..hi} (same recipe as
+    `conditioned_system_torch`, one seed per problem).  Returns a list of
+    (A32, b64) device tensors and the sizes."""
+    sizes = batch_sizes(count, seed, lo, hi)
+    out = [conditioned_system_torch(int(n), kappa, seed * 100003 + i, device)
+           for i, n in enumerate(sizes)]
+    return out, sizes
