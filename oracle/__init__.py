@@ -62,6 +62,11 @@ def lib():
                              ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(_int), _f64p]
         L.orc_ir.restype = _int
+        L.orc_gmres_ir.argtypes = [_i64, _f32p, _i64, _f32p, _i64, _i32p, _f64p, _f64p,
+                                   ctypes.c_double, _int, _int, ctypes.c_double,
+                                   ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_int), _f64p]
+        L.orc_gmres_ir.restype = _int
         L.orc_residual.argtypes = [_i64, _f32p, _i64, _f64p, _f64p, _f64p]
         L.orc_residual.restype = None
         L.orc_inf_norm_mat.argtypes = [_i64, _f32p, _i64]
@@ -224,4 +229,27 @@ def ir(A, LU, ipiv, b, tol: float = 1e-14, max_iter: int = 30):
     if rc:
         raise ValueError(rc)
     return dict(x=x, iters=it.value, eta=eta.value, status=st.value,
+                eta_hist=hist[: it.value + 1])
+
+
+def gmres_ir(A, LU, ipiv, b, tol: float = 1e-14, max_iter: int = 30, restart: int = 50,
+             inner_tol: float = 1e-8):
+    """Refinement with LU-preconditioned FP64 GMRES as the correction solver
+    (Sec. III, Sec. IV-B).  Returns dict(x, iters, inner, eta, status, eta_hist)."""
+    A = _c32(A)
+    LU = _c32(LU)
+    n = A.shape[0]
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros(n, np.float64)
+    it = ctypes.c_int(0)
+    inner = ctypes.c_int(0)
+    eta = ctypes.c_double(0.0)
+    st = ctypes.c_int(0)
+    hist = np.full(max_iter + 1, np.nan)
+    rc = lib().orc_gmres_ir(n, A, max(n, 1), LU, max(n, 1), np.ascontiguousarray(ipiv, np.int32),
+                            b, x, tol, max_iter, restart, inner_tol, ctypes.byref(it),
+                            ctypes.byref(inner), ctypes.byref(eta), ctypes.byref(st), hist)
+    if rc:
+        raise ValueError(rc)
+    return dict(x=x, iters=it.value, inner=inner.value, eta=eta.value, status=st.value,
                 eta_hist=hist[: it.value + 1])

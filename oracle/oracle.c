@@ -579,6 +579,151 @@ int orc_ir(int64_t n, const float *A, int64_t lda, const float *LU,
     return 0;
 }
 
+
+/* ------------------------------------------------------------------ */
+/* Sec. III / Sec. IV-B: iterative refinement whose correction equation */
+/* A d = r is solved by GMRES preconditioned with the low-precision LU   */
+/* (left preconditioning, M = LU), all of GMRES in FP64: the matrix-     */
+/* vector product uses A promoted exactly, the preconditioner applies    */
+/* the FP32 factors in FP64 arithmetic (row interchanges, unit lower and */
+/* upper substitution), Arnoldi with modified Gram-Schmidt, Givens       */
+/* rotations on the Hessenberg matrix.  One GMRES cycle of at most       */
+/* `restart` steps per refinement step, stopped when the preconditioned  */
+/* residual falls below inner_tol times its initial norm.                */
+/* Outer loop and status codes as orc_ir; inner_out = total GMRES steps. */
+/* ------------------------------------------------------------------ */
+static void lu_apply_f64(int64_t n, const float *LU, int64_t lda, const int32_t *ipiv,
+                         double *v)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t p = ipiv[i];
+        if (p != i) { double t = v[i]; v[i] = v[p]; v[p] = t; }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = v[i];
+        for (int64_t p = 0; p < i; ++p) s = fma(-(double)LU[i * lda + p], v[p], s);
+        v[i] = s;
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = v[i];
+        for (int64_t p = i + 1; p < n; ++p) s = fma(-(double)LU[i * lda + p], v[p], s);
+        v[i] = s / (double)LU[i * lda + i];
+    }
+}
+
+static double dot64(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s = fma(a[i], b[i], s);
+    return s;
+}
+
+int orc_gmres_ir(int64_t n, const float *A, int64_t lda, const float *LU,
+                 int64_t ldlu, const int32_t *ipiv, const double *b, double *x,
+                 double tol, int max_iter, int restart, double inner_tol,
+                 int *iters_out, int *inner_out, double *eta_out, int *status_out,
+                 double *eta_hist)
+{
+    if (n < 0) return -1;
+    if (max_iter < 0) return -11;
+    if (restart < 1) return -12;
+    int m = restart;
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *V = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1) * (size_t)(m + 1));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *H = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * (size_t)m);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)m);
+    double *g = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+    double *y = (double *)malloc(sizeof(double) * (size_t)m);
+    float *f = (float *)malloc(sizeof(float) * (size_t)(n ? n : 1));
+    if (!r || !V || !w || !H || !cs || !sn || !g || !y || !f) {
+        free(r); free(V); free(w); free(H); free(cs); free(sn); free(g); free(y); free(f);
+        return -100;
+    }
+    double normA = orc_inf_norm_mat(n, A, lda);
+    double normb = inf_norm_vec(n, b);
+    for (int64_t i = 0; i < n; ++i) f[i] = (float)b[i];
+    orc_lu_solve(n, LU, ldlu, ipiv, f);
+    for (int64_t i = 0; i < n; ++i) x[i] = (double)f[i];
+    int status, it = 0, rises = 0, inner_total = 0;
+    double eta, prev_eta = INFINITY;
+    for (;;) {
+        orc_residual(n, A, lda, b, x, r);
+        double rn = inf_norm_vec(n, r);
+        double den = normA * inf_norm_vec(n, x) + normb;
+        eta = den > 0.0 ? rn / den : rn;
+        if (eta_hist) eta_hist[it] = eta;
+        rises = (eta >= prev_eta) ? rises + 1 : 0;
+        prev_eta = eta;
+        if (!isfinite(eta)) { status = 3; break; }
+        if (eta <= tol) { status = 0; break; }
+        if (it >= max_iter) { status = 1; break; }
+        if (rises >= 2) { status = 2; break; }
+        /* GMRES on M^{-1} A d = M^{-1} r, d0 = 0 */
+        for (int64_t i = 0; i < n; ++i) V[i] = r[i];
+        lu_apply_f64(n, LU, ldlu, ipiv, V);
+        double beta = sqrt(dot64(n, V, V));
+        int k = 0;
+        if (beta > 0.0) {
+            for (int64_t i = 0; i < n; ++i) V[i] /= beta;
+            for (int j = 0; j <= m; ++j) g[j] = 0.0;
+            g[0] = beta;
+            for (k = 0; k < m; ++k) {
+                double *vk = V + (size_t)k * n;
+                /* w = M^{-1} A v_k */
+                for (int64_t i = 0; i < n; ++i) {
+                    double s = 0.0;
+                    for (int64_t c = 0; c < n; ++c) s = fma((double)A[i * lda + c], vk[c], s);
+                    w[i] = s;
+                }
+                lu_apply_f64(n, LU, ldlu, ipiv, w);
+                /* modified Gram-Schmidt */
+                for (int j = 0; j <= k; ++j) {
+                    double h = dot64(n, w, V + (size_t)j * n);
+                    H[j * m + k] = h;
+                    for (int64_t i = 0; i < n; ++i) w[i] = fma(-h, V[(size_t)j * n + i], w[i]);
+                }
+                double hn = sqrt(dot64(n, w, w));
+                H[(k + 1) * m + k] = hn;
+                /* earlier rotations on the new column, then a new rotation */
+                for (int j = 0; j < k; ++j) {
+                    double a = H[j * m + k], c2 = H[(j + 1) * m + k];
+                    H[j * m + k] = cs[j] * a + sn[j] * c2;
+                    H[(j + 1) * m + k] = -sn[j] * a + cs[j] * c2;
+                }
+                double a = H[k * m + k], c2 = H[(k + 1) * m + k];
+                double rho = hypot(a, c2);
+                cs[k] = rho > 0.0 ? a / rho : 1.0;
+                sn[k] = rho > 0.0 ? c2 / rho : 0.0;
+                H[k * m + k] = rho;
+                H[(k + 1) * m + k] = 0.0;
+                g[k + 1] = -sn[k] * g[k];
+                g[k] = cs[k] * g[k];
+                ++inner_total;
+                if (hn > 0.0 && k + 1 < m + 1)
+                    for (int64_t i = 0; i < n; ++i) V[(size_t)(k + 1) * n + i] = w[i] / hn;
+                if (fabs(g[k + 1]) <= inner_tol * beta || hn == 0.0) { ++k; break; }
+            }
+            /* y = H(1:k,1:k) \ g(1:k); d = V y */
+            for (int j = k - 1; j >= 0; --j) {
+                double s = g[j];
+                for (int q = j + 1; q < k; ++q) s -= H[j * m + q] * y[q];
+                y[j] = s / H[j * m + j];
+            }
+            for (int j = 0; j < k; ++j)
+                for (int64_t i = 0; i < n; ++i) x[i] = fma(y[j], V[(size_t)j * n + i], x[i]);
+        }
+        ++it;
+    }
+    *iters_out = it;
+    *inner_out = inner_total;
+    *eta_out = eta;
+    *status_out = status;
+    free(r); free(V); free(w); free(H); free(cs); free(sn); free(g); free(y); free(f);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

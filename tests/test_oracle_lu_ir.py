@@ -161,3 +161,57 @@ def test_ir_high_kappa_lu_ir_does_not_reach_fp64(orc):
     LU, ipiv, _ = orc.lu(A, 6, 16)
     res = orc.ir(A, LU, ipiv, b, tol=1e-14, max_iter=30)
     assert res["status"] in (1, 2) and res["eta"] > 1e-14
+
+
+@pytest.mark.parametrize("n", [10, 50, 100])
+def test_gmres_table_diagonally_dominant(orc, n):
+    """Sec. IV-B GMRES table: row- and column-diagonally dominant unsymmetric
+    matrices with an FP32-level LU as preconditioner all converge (FP32 rows:
+    100% converged, 2.0 iterations on average)."""
+    its = []
+    for s in range(10):
+        g = np.random.default_rng(2000 + 17 * n + s)
+        A = g.uniform(-1, 1, (n, n))
+        d = np.maximum(np.abs(A).sum(0), np.abs(A).sum(1)) + 1.0
+        A = (A + np.diag(d * np.sign(g.uniform(-1, 1, n)))).astype(np.float32)
+        b = A.astype(np.float64) @ g.normal(size=n)
+        LU, ipiv, _ = orc.lu(A, 6, 16)
+        np.testing.assert_array_equal(ipiv, np.arange(n))   # dominance: no pivoting
+        res = orc.gmres_ir(A, LU, ipiv, b)
+        assert res["status"] == 0 and res["eta"] <= 1e-14
+        its.append(res["iters"])
+    assert np.mean(its) <= 2.0
+
+
+@pytest.mark.parametrize("kappa", [1e8, 1e10])
+def test_gmres_ir_beyond_lu_ir(orc, kappa):
+    """Sec. III: GMRES with the low-precision LU as preconditioner reaches an
+    FP64-level backward error in one or two refinement steps where plain LU-IR
+    needs many or fails; the solution agrees with LAPACK's FP64 solve to
+    within the conditioning."""
+    n = 150
+    A, b, _ = workloads.conditioned_system(n, kappa, 77)
+    LU, ipiv, _ = orc.lu(A, 6, 32)
+    g = orc.gmres_ir(A, LU, ipiv, b, restart=n)
+    assert g["status"] == 0 and g["eta"] <= 1e-14 and g["iters"] <= 3, g
+    r = b - A.astype(np.float64) @ g["x"]
+    eta = np.abs(r).max() / (np.abs(A.astype(np.float64)).sum(1).max() * np.abs(g["x"]).max() + np.abs(b).max())
+    assert eta <= 1.01e-14
+    xr = np.linalg.solve(A.astype(np.float64), b)
+    sv = np.linalg.svd(A.astype(np.float64), compute_uv=False)
+    k32 = sv[0] / sv[-1]
+    assert np.max(np.abs(g["x"] - xr)) <= 10 * k32 * 2.0 ** -52 * np.sqrt(n) * np.max(np.abs(xr))
+    ir = orc.ir(A, LU, ipiv, b)
+    assert ir["status"] != 0 or ir["iters"] > g["iters"]
+
+
+def test_gmres_full_krylov_space_is_exact(orc):
+    """With restart >= n the Krylov space of the preconditioned operator spans
+    R^n, so one GMRES cycle solves the correction equation to rounding level
+    even for a singular-value spread far beyond 1/2^-24."""
+    n = 40
+    A, b, _ = workloads.conditioned_system(n, 1e12, 78)
+    LU, ipiv, _ = orc.lu(A, 6, 8)
+    g = orc.gmres_ir(A, LU, ipiv, b, restart=n, inner_tol=0.0)
+    assert g["status"] == 0 and g["eta"] <= 1e-14 and g["iters"] <= 2
+    assert g["inner"] <= 2 * n
