@@ -25,6 +25,28 @@ sys.path.insert(0, ROOT)
 
 BF16_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
 HBM_PEAK_GBS = 8000.0
+PMC_RECORD = os.path.join(ROOT, "profiles", "gemm_fast_x6_8192_hbm_bytes.json")
+
+
+def gemm_source_sha1():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1904_06376_amd", "csrc")
+    src = b"".join(open(os.path.join(d, n), "rb").read()
+                   for n in ("common.hpp", "gemm_tile.hpp", "gemm.hip"))
+    return hashlib.sha1(src).hexdigest()
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the x6 kernel from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by a 1 GiB copy), or None when the
+    GEMM sources changed since the counters were taken."""
+    try:
+        rec = json.load(open(PMC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha1") != gemm_source_sha1():
+        return None
+    return rec.get("traffic_bytes")
 
 
 def log(*a):
@@ -141,7 +163,7 @@ def main():
     achieved = bf16_flop / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": "gemm_fast_kernel<6>",
+                "traffic": measured_traffic(), "kernel": "gemm_fast_kernel<6,128,128>",
                 "algorithmic_flop_per_launch": bf16_flop, "avg_launch_ms": round(avg_ms, 4)}
 
     import oracle as orc

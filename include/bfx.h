@@ -187,6 +187,43 @@ int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
 
 size_t bfx_ir_ws_size(int64_t n);
 
+/* ------------------------------------------------------------------------ */
+/* Refinement with GMRES as the correction solver (Sec. III, Sec. IV-B):      */
+/* each step solves A d = r with GMRES on M^{-1} A d = M^{-1} r, M = the      */
+/* low-precision LU, in FP64 (the preconditioner applies the FP32 factors in  */
+/* FP64 arithmetic); one GMRES cycle of at most `restart` steps per           */
+/* refinement step, stopped when the preconditioned residual falls below      */
+/* inner_tol times its initial norm.  The residual, update, stopping rule and */
+/* status codes are those of bfx_ir_solve.  This is the variant that reaches  */
+/* an FP64-level backward error when kappa(A) * 2^-24 is well above 1.        */
+/* ------------------------------------------------------------------------ */
+typedef struct bfx_gmres_opts {
+    double tol;         /* backward error target (default 1e-14) */
+    int32_t max_iter;   /* refinement steps (default 30) */
+    int32_t restart;    /* GMRES steps per refinement step (default 50) */
+    double inner_tol;   /* relative GMRES tolerance (default 1e-8) */
+} bfx_gmres_opts;
+
+typedef struct bfx_gmres_result {
+    int32_t iters;      /* refinement steps */
+    int32_t inner;      /* total GMRES steps */
+    int32_t status;     /* as bfx_ir_result */
+    int32_t reserved;
+    double eta;
+} bfx_gmres_result;
+
+/* Arguments as bfx_ir_solve (opts/res are HOST pointers; this call
+ * synchronises `stream` once per GMRES step).  ws: bfx_gmres_ir_ws_size(n,
+ * restart) bytes.  Errors as bfx_ir_solve; -9 also for restart < 1 or a
+ * negative inner_tol. */
+int bfx_gmres_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
+                       int64_t ldlu, const int32_t *ipiv, const double *b,
+                       double *x, const bfx_gmres_opts *opts,
+                       bfx_gmres_result *res, void *ws, size_t ws_bytes,
+                       void *stream);
+
+size_t bfx_gmres_ir_ws_size(int64_t n, int restart);
+
 /* FP32 solve with an LU from bfx_lu_factor: rhs (n FP32, device) is
  * overwritten by (LU)^-1 P rhs.  ws: bfx_ir_ws_size(n) bytes.  Errors as
  * bfx_ir_solve for the shared arguments. */

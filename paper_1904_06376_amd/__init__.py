@@ -6,7 +6,8 @@ Datatype For Higher-Precision Computations" (2019).
 """
 from ._lib import EXPORTED, BfxError, lib  # noqa: F401  (fails loudly if unbuilt)
 from .api import (BatchedGemmPlan, BatchedSolvePlan, gemm, gemm_ws_size,  # noqa: F401
-                  ir_solve, lu_factor, lu_solve_f32, sgemm_fp32, split)
+                  gmres_ir_solve, ir_solve, lu_factor, lu_solve_f32, sgemm_fp32,
+                  split)
 
 __all__ = ["split", "gemm", "gemm_ws_size", "sgemm_fp32", "BatchedGemmPlan", "BatchedSolvePlan",
-           "lu_factor", "lu_solve_f32", "ir_solve", "BfxError", "EXPORTED"]
+           "lu_factor", "lu_solve_f32", "ir_solve", "gmres_ir_solve", "BfxError", "EXPORTED"]

@@ -41,6 +41,16 @@ class IrOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("tol", c_f64), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("inner_tol", c_f64)]
+
+
+class GmresResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("inner", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eta", c_f64)]
+
+
 class IrResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("eta", c_f64)]
 
@@ -66,6 +76,10 @@ SIGNATURES = {
                       ctypes.POINTER(IrOpts), ctypes.POINTER(IrResult), c_vp, c_size,
                       c_vp], c_int),
     "bfx_ir_ws_size": ([c_i64], c_size),
+    "bfx_gmres_ir_solve": ([c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp,
+                            ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresResult), c_vp,
+                            c_size, c_vp], c_int),
+    "bfx_gmres_ir_ws_size": ([c_i64, c_int], c_size),
     "bfx_lu_solve_f32": ([c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_size, c_vp], c_int),
     "bfx_lu_ir_batched_plan_create": ([c_int, c_i64, ctypes.POINTER(SolveDesc),
                                        ctypes.POINTER(IrOpts), ctypes.POINTER(c_vp)], c_int),

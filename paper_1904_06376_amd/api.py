@@ -7,7 +7,7 @@ import ctypes
 
 import torch
 
-from ._lib import GemmDesc, IrOpts, IrResult, SolveDesc, check, lib
+from ._lib import GemmDesc, GmresOpts, GmresResult, IrOpts, IrResult, SolveDesc, check, lib
 
 
 def _stream() -> int:
@@ -177,6 +177,26 @@ def ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Ten
                            ctypes.byref(res), ws.data_ptr() if ws is not None else None,
                            need, _stream()), "bfx_ir_solve")
     return x, dict(iters=res.iters, status=res.status, eta=res.eta)
+
+
+def gmres_ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Tensor,
+                   tol: float = 1e-14, max_iter: int = 30, restart: int = 50,
+                   inner_tol: float = 1e-8, x: torch.Tensor | None = None):
+    """Refinement with LU-preconditioned FP64 GMRES as the correction solver;
+    returns (x, dict(iters, inner, status, eta))."""
+    n = A.shape[0]
+    _dev(b, torch.float64, "b")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+    need = lib.bfx_gmres_ir_ws_size(n, restart)
+    ws = _ws(need, A.device)
+    opts = GmresOpts(tol, max_iter, restart, inner_tol)
+    res = GmresResult()
+    check(lib.bfx_gmres_ir_solve(n, A.data_ptr(), _rows(A, "A"), LU.data_ptr(), _rows(LU, "LU"),
+                                 ipiv.data_ptr(), b.data_ptr(), x.data_ptr(), ctypes.byref(opts),
+                                 ctypes.byref(res), ws.data_ptr() if ws is not None else None,
+                                 need, _stream()), "bfx_gmres_ir_solve")
+    return x, dict(iters=res.iters, inner=res.inner, status=res.status, eta=res.eta)
 
 
 class BatchedSolvePlan:

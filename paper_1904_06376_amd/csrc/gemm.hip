@@ -31,12 +31,12 @@ gemm_split_kernel(GemmParams p) {
     gemm_tile<V, BM, BN, WM, WN>(p, m0, n0, kb, ke, split, smem);
 }
 
-// Aligned 128 x 128 tiles (see gemm_tile_fast).
-template <int V>
-__global__ void __launch_bounds__(256, 1)
+// Aligned tiles (see gemm_tile_fast), 512 threads: 4 MFMA + 4 helper waves.
+template <int V, int BM, int BN>
+__global__ void __launch_bounds__(512, 1)
 gemm_fast_kernel(GemmParams p) {
     extern __shared__ __align__(16) uint16_t smem[];
-    const int64_t tiles_m = p.M / 128, tiles_n = p.N / 128;
+    const int64_t tiles_m = p.M / BM, tiles_n = p.N / BN;
     const int64_t tiles = tiles_m * tiles_n;
     const int64_t total = tiles * p.splits;
     const int64_t id = xcd_remap(blockIdx.x, total);
@@ -47,26 +47,38 @@ gemm_fast_kernel(GemmParams p) {
     const int64_t first_m = group * GROUP;
     const int64_t gsz = (tiles_m - first_m < GROUP) ? tiles_m - first_m : GROUP;
     const int64_t in_g = t % (GROUP * tiles_n);
-    const int64_t m0 = (first_m + in_g % gsz) * 128;
-    const int64_t n0 = (in_g / gsz) * 128;
+    const int64_t m0 = (first_m + in_g % gsz) * BM;
+    const int64_t n0 = (in_g / gsz) * BN;
     const int64_t kb = split * p.k_per_split;
     const int64_t ke = (kb + p.k_per_split < p.K) ? kb + p.k_per_split : p.K;
-    gemm_tile_fast<V>(p, m0, n0, kb, ke, split, smem);
+    gemm_tile_fast<V, BM, BN>(p, m0, n0, kb, ke, split, smem);
 }
 
-// Fixed-order reduction of split-K partials, then the epilogue.
+// Fixed-order reduction of split-K partials, then the epilogue.  Each
+// workgroup owns 64 consecutive outputs; its 4 waves sum interleaved slices of
+// the splits (wave w takes splits w, w+4, ...) in increasing order, and the
+// four slice sums are added in a fixed order: deterministic for a given
+// split count.
 __global__ void __launch_bounds__(256)
 splitk_reduce_kernel(const float *__restrict__ partial, int splits, int64_t M,
                      int64_t N, float alpha, float beta, float *C, int64_t ldc) {
+    __shared__ float sh[4][64], sl[4][64];
     const int64_t MN = M * N;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        float h = 0.0f, l = 0.0f;
-        for (int s = 0; s < splits; ++s) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    float h = 0.0f, l = 0.0f;
+    if (e < MN)
+        for (int s = w; s < splits; s += 4) {
             h += partial[(int64_t)(2 * s) * MN + e];
             l += partial[(int64_t)(2 * s + 1) * MN + e];
         }
-        const float X = h + l;
+    sh[w][lane] = h;
+    sl[w][lane] = l;
+    __syncthreads();
+    if (w == 0 && e < MN) {
+        const float H = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+        const float L = (sl[0][lane] + sl[1][lane]) + (sl[2][lane] + sl[3][lane]);
+        const float X = H + L;
         const int64_t row = e / N, col = e % N;
         float *c = C + row * ldc + col;
         *c = (beta == 0.0f) ? alpha * X : fmaf(alpha, X, beta * *c);
@@ -103,7 +115,7 @@ static int launch_tiles(const GemmParams &p, hipStream_t s) {
 // least 8 K-steps.
 static int choose_splits(int64_t M, int64_t N, int64_t K, int BM, int BN) {
     const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
-    const int64_t target = 1024;
+    const int64_t target = 512;
     if (tiles >= 256 || K < 16 * BK) return 1;
     int64_t s = ceil_div(target, tiles);
     const int64_t max_s = K / (8 * BK);
@@ -125,17 +137,17 @@ size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K) {
     return (size_t)s * 2 * (size_t)M * (size_t)N * sizeof(float);
 }
 
-template <int V>
+template <int V, int BM, int BN>
 static int launch_fast(const GemmParams &p, hipStream_t s) {
-    const size_t lds = tile_lds_bytes<V, 128, 128>();
+    const size_t lds = tile_lds_bytes<V, BM, BN>();
     static bool attr_set = false;
     if (!attr_set) {
-        BFX_HIP(hipFuncSetAttribute((const void *)gemm_fast_kernel<V>,
+        BFX_HIP(hipFuncSetAttribute((const void *)gemm_fast_kernel<V, BM, BN>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    const int64_t blocks = (p.M / 128) * (p.N / 128) * p.splits;
-    hipLaunchKernelGGL(gemm_fast_kernel<V>, dim3((unsigned)blocks), dim3(256), lds, s, p);
+    const int64_t blocks = (p.M / BM) * (p.N / BN) * p.splits;
+    hipLaunchKernelGGL((gemm_fast_kernel<V, BM, BN>), dim3((unsigned)blocks), dim3(512), lds, s, p);
     BFX_LAUNCH_CHECK("gemm_fast_kernel launch");
     return BFX_OK;
 }
@@ -144,16 +156,19 @@ static int launch_fast(const GemmParams &p, hipStream_t s) {
 // whole number of 32-steps and rows are 16-byte aligned.
 // Buffer offsets are 32-bit: 128 rows of A and one split's K rows of B must
 // each span less than 2^31 bytes.
-static bool fast_ok(const GemmParams &p) {
-    return p.M % 128 == 0 && p.N % 128 == 0 && p.K % BK == 0 && p.K > 0 &&
+static bool fast_ok(const GemmParams &p, int BM, int BN) {
+    return p.M % BM == 0 && p.N % BN == 0 && p.K % BK == 0 && p.K > 0 &&
            p.k_per_split % BK == 0 && p.vecA && p.vecB && ((uintptr_t)p.C % 4 == 0) &&
-           128 * p.lda * 4 < (int64_t(1) << 31) &&
+           BM * p.lda * 4 < (int64_t(1) << 31) &&
            p.k_per_split * p.ldb * 4 < (int64_t(1) << 31);
 }
 
 template <int V>
 static int dispatch_variant(GemmParams &p, int BM, int BN, hipStream_t s) {
-    if (BM == 128 && fast_ok(p) && !g_force_general) return launch_fast<V>(p, s);
+    if (!g_force_general && fast_ok(p, BM, BN)) {
+        if (BM == 128) return launch_fast<V, 128, 128>(p, s);
+        return launch_fast<V, 64, 64>(p, s);
+    }
     if (BM == 64) return launch_tiles<V, 64, 64, 2, 2>(p, s);
     return launch_tiles<V, 128, 128, 2, 2>(p, s);
 }
@@ -186,8 +201,7 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
         default: return -1;
     }
     if (rc != BFX_OK || p.splits <= 1) return rc;
-    int64_t blocks = ceil_div(M * N, 256);
-    if (blocks > 4096) blocks = 4096;
+    const int64_t blocks = ceil_div(M * N, 64);
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
                        p.partial, p.splits, M, N, alpha, beta, C, ldc);
     BFX_LAUNCH_CHECK("splitk_reduce_kernel launch");

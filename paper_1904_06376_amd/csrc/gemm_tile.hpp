@@ -253,29 +253,28 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int64_t m0, int64
 
 
 // ---------------------------------------------------------------------------
-// Aligned fast path: 128 x 128 tile, 4 waves (2 x 2, 64 x 64 each), K a
-// multiple of 32, rows 16-byte aligned, no bounds checks.  Differences from
-// gemm_tile:
-//   * loads: one thread per A row / B column and 16 k values (4 x 16-byte
-//     loads of A, 16 coalesced 4-byte loads of B), so every LDS store is a
-//     conflict-free 16-byte store of 8 BF16 (rows are 80 bytes apart);
-//   * a three-stage register ring issues global loads two K-steps ahead;
+// Aligned fast path: BM x BN tile (128 x 128 or 64 x 64), 4 waves (2 x 2),
+// K a multiple of 32, rows 16-byte aligned, no bounds checks.  Differences
+// from gemm_tile:
+//   * loads: one thread per A row / B column and BM*32/256 consecutive k
+//     values (16-byte loads of A, coalesced 4-byte loads of B) through buffer
+//     resources with SGPR offsets, so every LDS store is a conflict-free
+//     16-byte store of 8 BF16 (rows are 80 bytes apart);
+//   * global loads are issued two K-steps ahead (two register stages);
 //   * the split is branch-free (hardware RNE); the rare values for which it is
-//     not exact (Inf/NaN, or a BF16 term that rounds to Inf) are detected from
+//     not exact (Inf/NaN, or a first term that rounds to Inf) are detected from
 //     the first plane and re-split exactly afterwards, outside the MFMA block,
-//     so loads, split and MFMA of one K-step form a single basic block.
+//     from a second read of global memory, so loads, split and MFMA of one
+//     K-step form a single basic block.
 // ---------------------------------------------------------------------------
-namespace fastpath {
-constexpr int BM = 128, BN = 128, NT = 256;
-}
 
-// Packed BF16 pairs of 16 consecutive values -> P planes x 8 dwords.  `flag`
-// collects (per 16-bit half, unsigned max) the magnitude of every first term:
-// a half >= 0x7F80 marks an Inf/NaN first term.
-template <int P>
-__device__ __forceinline__ void split16_fast(const float *v, uint32_t out[][8], uint32_t &flag) {
+// Packed BF16 pairs of KPT consecutive values -> P planes x KPT/2 dwords.
+// `flag` collects (per 16-bit half, unsigned max) the magnitude of every
+// first term: a half >= 0x7F80 marks an Inf/NaN first term.
+template <int P, int KPT>
+__device__ __forceinline__ void split_run_fast(const float *v, uint32_t out[][KPT / 2], uint32_t &flag) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < KPT / 2; ++i) {
         uint32_t t[3];
         split_pair_fast<P>(v[2 * i], v[2 * i + 1], t);
 #pragma unroll
@@ -286,190 +285,194 @@ __device__ __forceinline__ void split16_fast(const float *v, uint32_t out[][8], 
     }
 }
 
-template <int P>
-__device__ __forceinline__ void split16_exact(const float *v, uint32_t out[][8]) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        uint32_t t[3];
-        split_pair_exact<P>(v[2 * i], v[2 * i + 1], t);
-#pragma unroll
-        for (int pl = 0; pl < P; ++pl) out[pl][i] = t[pl];
-    }
-}
-
 __device__ __forceinline__ bool flag_bad(uint32_t flag) {
     return (flag & 0xffffu) >= 0x7f80u || (flag >> 16) >= 0x7f80u;
 }
 
-template <int V>
+// Wave-specialised aligned tile: 512 threads.  Waves 0-3 (one per SIMD) only
+// read BF16 fragments from LDS, run the MFMAs and write the epilogue; waves
+// 4-7 (one per SIMD) only load FP32 tiles (two K-steps ahead), split them and
+// store the planes.  Every SIMD thus runs one wave of each kind and overlaps
+// the split's VALU work with the other wave's matrix work.  Both kinds pass
+// the same barrier once per K-step; the LDS planes are double-buffered.
+template <int V, int BM, int BN>
 __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, int64_t n0,
                                                int64_t kb, int64_t ke, int64_t split,
                                                uint16_t *smem) {
     using PR = Prods<V>;
-    using namespace fastpath;
     constexpr int P = PR::P;
     constexpr int PLANE = (BM + BN) * LDK;
-    constexpr int TM = 4, TN = 4;
+    constexpr int TM = BM / 32, TN = BN / 32;          // 16x16 tiles per MFMA wave (2 x 2 waves)
+    constexpr int KPT = BM * BK / 256;                  // k values per helper thread
+    static_assert(BM == BN && KPT % 8 == 0, "square tiles with >= 8 k values per helper thread");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
     const int KT = (int)((ke - kb) / BK);
 
-    const int lrow = tid & 127, kh = tid >> 7;
+    if (wave < 4) {
+        // ------------------------------ MFMA waves ------------------------------
+        const int wm = wave >> 1, wn = wave & 1;
+        bfx_f32x4 hi[TM][TN], lo[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                hi[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+                lo[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        const int r16 = lane & 15, kg = lane >> 4;
+        for (int s = 0; s < KT; ++s) {
+            __syncthreads();  // buffer s&1 holds step s
+            const uint16_t *base = smem + (s & 1) * P * PLANE;
+            bfx_bf16x8 af[P][TM];
+#pragma unroll
+            for (int pl = 0; pl < P; ++pl)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(
+                        base + pl * PLANE + (wm * (BM / 2) + i * 16 + r16) * LDK + kg * 8);
+            // B fragments one plane at a time (plane 2, 1, 0): within each B
+            // plane the lo products are issued smallest bin first.
+#pragma unroll
+            for (int jp = P - 1; jp >= 0; --jp) {
+                bfx_bf16x8 bf[TN];
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(
+                        base + jp * PLANE + (BM + wn * (BN / 2) + j * 16 + r16) * LDK + kg * 8);
+#pragma unroll
+                for (int q = 0; q < PR::n; ++q) {
+                    if (PR::bj[q] != jp) continue;
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PR::ai[q]][i], bf[j],
+                                                                                lo[i][j], 0, 0, 0);
+                }
+                if (jp == 0) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[j],
+                                                                                hi[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // matches the helpers' final barrier
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t row = m0 + wm * (BM / 2) + i * 16 + kg * 4 + e;
+                    const int64_t col = n0 + wn * (BN / 2) + j * 16 + r16;
+                    if (p.splits > 1) {
+                        float *dst = p.partial + (split * 2) * p.M * p.N + row * p.N + col;
+                        dst[0] = hi[i][j][e];
+                        dst[p.M * p.N] = lo[i][j][e];
+                    } else {
+                        const float X = hi[i][j][e] + lo[i][j][e];
+                        float *c = p.C + row * p.ldc + col;
+                        *c = (p.beta == 0.0f) ? p.alpha * X : fmaf(p.alpha, X, p.beta * *c);
+                    }
+                }
+        return;
+    }
+
+    // ------------------------------ helper waves ------------------------------
+    const int h = tid - 256;
+    const int arow = h % BM, aq = h / BM;   // A row, k group
+    const int bcol = h % BN, bq = h / BN;   // B column, k group
     // Buffer resources over this tile's A rows and B columns: loads take one
     // VGPR offset per thread and SGPR offsets per step (no 64-bit addresses).
     const int lda = (int)p.lda, ldb = (int)p.ldb;
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(p.A + m0 * p.lda + kb), (short)0, 128 * lda * 4, 0x00020000);
+        (void *)(p.A + m0 * p.lda + kb), (short)0, BM * lda * 4, 0x00020000);
     const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(p.B + kb * p.ldb + n0), (short)0, (int)(ke - kb) * ldb * 4, 0x00020000);
-    const int voA = (lrow * lda + kh * 16) * 4;
-    const int voB = (kh * 16 * ldb + lrow) * 4;
+    const int voA = (arow * lda + aq * KPT) * 4;
+    const int voB = (bq * KPT * ldb + bcol) * 4;
 
-    float ra[2][16], rb[2][16];
+    float ra[2][KPT], rb[2][KPT];
     auto issue = [&](int st, int step) {
         const int soA = step * BK * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < KPT / 4; ++q) {
             const bfx_f32x4 v = __builtin_bit_cast(
                 bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA + 16 * q, soA, 0));
             ra[st][4 * q] = v[0]; ra[st][4 * q + 1] = v[1]; ra[st][4 * q + 2] = v[2]; ra[st][4 * q + 3] = v[3];
         }
         const int soB = step * BK * ldb * 4;
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < KPT; ++j)
             rb[st][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, voB, soB + j * ldb * 4, 0));
     };
-    auto put = [&](uint16_t *base, int row, const uint32_t pl8[][8]) {
+    auto put = [&](uint16_t *base, int row, int kg0, const uint32_t pl8[][KPT / 2]) {
 #pragma unroll
         for (int pl = 0; pl < P; ++pl) {
-            uint16_t *d = base + pl * PLANE + row * LDK + kh * 16;
-            *reinterpret_cast<uint4 *>(d) = make_uint4(pl8[pl][0], pl8[pl][1], pl8[pl][2], pl8[pl][3]);
-            *reinterpret_cast<uint4 *>(d + 8) = make_uint4(pl8[pl][4], pl8[pl][5], pl8[pl][6], pl8[pl][7]);
+            uint16_t *d = base + pl * PLANE + row * LDK + kg0 * KPT;
+#pragma unroll
+            for (int c = 0; c < KPT / 8; ++c)
+                *reinterpret_cast<uint4 *>(d + 8 * c) =
+                    make_uint4(pl8[pl][4 * c], pl8[pl][4 * c + 1], pl8[pl][4 * c + 2], pl8[pl][4 * c + 3]);
         }
     };
     auto stage = [&](int st, int buf) {
         uint16_t *base = smem + buf * P * PLANE;
-        uint32_t flag = 0, pa[3][8], pb[3][8];
-        split16_fast<P>(ra[st], pa, flag);
-        split16_fast<P>(rb[st], pb, flag);
-        put(base, lrow, pa);
-        put(base, BM + lrow, pb);
+        uint32_t flag = 0, pa[3][KPT / 2], pb[3][KPT / 2];
+        split_run_fast<P, KPT>(ra[st], pa, flag);
+        split_run_fast<P, KPT>(rb[st], pb, flag);
+        put(base, arow, aq, pa);
+        put(base, BM + bcol, bq, pb);
         return flag;
     };
-    // Rare path: re-read this thread's 32 values of K-step `step` (still in
-    // L2) and split them exactly, one BF16 store at a time.
+    // Rare path: re-read this thread's values of K-step `step` (still in L2)
+    // and split them exactly, one BF16 store at a time.
     auto fixup = [&](int step, int buf) {
         uint16_t *base = smem + buf * P * PLANE;
 #pragma unroll 1
-        for (int e = 0; e < 32; ++e) {
-            const uint32_t bits = (e < 16)
-                ? __builtin_amdgcn_raw_buffer_load_b32(rA, voA + 4 * e, step * BK * 4, 0)
-                : __builtin_amdgcn_raw_buffer_load_b32(rB, voB, (step * BK + (e - 16)) * ldb * 4, 0);
-            const float v = __builtin_bit_cast(float, bits);
-            uint32_t h[3];
-            split3_exact(v, h[0], h[1], h[2]);
-            const int row = (e < 16) ? lrow : BM + lrow;
-            const int k = kh * 16 + (e & 15);
+        for (int e = 0; e < 2 * KPT; ++e) {
+            const bool isA = e < KPT;
+            const int q = isA ? e : e - KPT;
+            const uint32_t bits = isA
+                ? __builtin_amdgcn_raw_buffer_load_b32(rA, voA + 4 * q, step * BK * 4, 0)
+                : __builtin_amdgcn_raw_buffer_load_b32(rB, voB, (step * BK + q) * ldb * 4, 0);
+            uint32_t hh[3];
+            split3_exact(__builtin_bit_cast(float, bits), hh[0], hh[1], hh[2]);
+            const int row = isA ? arow : BM + bcol;
+            const int k = (isA ? aq : bq) * KPT + q;
 #pragma unroll
-            for (int pl = 0; pl < P; ++pl) base[pl * PLANE + row * LDK + k] = (uint16_t)h[pl];
+            for (int pl = 0; pl < P; ++pl) base[pl * PLANE + row * LDK + k] = (uint16_t)hh[pl];
         }
     };
-
-    bfx_f32x4 hi[TM][TN], lo[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            hi[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
-            lo[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-    const int r16 = lane & 15, kg = lane >> 4;
-    // MFMA over one LDS buffer.  A fragments of every plane stay in registers;
-    // B fragments are read one plane at a time (plane 2, 1, 0), so the issue
-    // order is bins smallest first within each B plane.
-    auto compute = [&](int buf) {
-        const uint16_t *base = smem + buf * P * PLANE;
-        bfx_bf16x8 af[P][TM];
-#pragma unroll
-        for (int pl = 0; pl < P; ++pl)
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-                af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(
-                    base + pl * PLANE + (wm * 64 + i * 16 + r16) * LDK + kg * 8);
-#pragma unroll
-        for (int jp = P - 1; jp >= 0; --jp) {
-            bfx_bf16x8 bf[TN];
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-                bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(
-                    base + jp * PLANE + (BM + wn * 64 + j * 16 + r16) * LDK + kg * 8);
-#pragma unroll
-            for (int q = 0; q < PR::n; ++q) {
-                if (PR::bj[q] != jp) continue;
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PR::ai[q]][i], bf[j],
-                                                                            lo[i][j], 0, 0, 0);
-            }
-            if (jp == 0) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[j], hi[i][j], 0, 0, 0);
-            }
-        }
-    };
-
-    // One K-step t: split step t+1 (register stage SP) into LDS buffer
-    // (t+1)&1, reuse its registers for the loads of step t+3, MFMA on buffer
-    // t&1; loads therefore have two K-steps to arrive.
-#define BFX_FAST_ITER(t, SP)                                               \
+    // Step t+1 is split into buffer (t+1)&1 while the MFMA waves work on step
+    // t; its registers then receive the loads of step t+3.
+#define BFX_HELPER_STEP(t, SP)                                             \
     {                                                                      \
-        const uint32_t flag = stage(SP, ((t) + 1) & 1);                    \
-        issue(SP, ((t) + 3 < KT) ? (t) + 3 : KT - 1);                      \
-        compute((t) & 1);                                                  \
-        if (flag_bad(flag) && (t) + 1 < KT) fixup((t) + 1, ((t) + 1) & 1); \
         __syncthreads();                                                   \
+        if ((t) + 1 < KT) {                                                \
+            const uint32_t flag = stage(SP, ((t) + 1) & 1);                \
+            issue(SP, ((t) + 3 < KT) ? (t) + 3 : KT - 1);                  \
+            if (flag_bad(flag)) fixup((t) + 1, ((t) + 1) & 1);             \
+        }                                                                  \
     }
-
     if (KT > 0) {
         issue(0, 0);
         issue(1, KT > 1 ? 1 : KT - 1);
-        {
-            const uint32_t flag = stage(0, 0);
-            issue(0, KT > 2 ? 2 : KT - 1);
-            if (flag_bad(flag)) fixup(0, 0);
+        const uint32_t flag = stage(0, 0);
+        issue(0, KT > 2 ? 2 : KT - 1);
+        if (flag_bad(flag)) fixup(0, 0);
+        int s = 0;
+        for (; s + 1 < KT; s += 2) {
+            BFX_HELPER_STEP(s, 1);
+            BFX_HELPER_STEP(s + 1, 0);
         }
-        __syncthreads();
-        for (int s = 0; s < KT; s += 2) {
-            BFX_FAST_ITER(s, 1);
-            if (s + 1 >= KT) break;
-            BFX_FAST_ITER(s + 1, 0);
-        }
+        if (s < KT) BFX_HELPER_STEP(s, 1);
     }
-#undef BFX_FAST_ITER
-
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t row = m0 + wm * 64 + i * 16 + kg * 4 + e;
-                const int64_t col = n0 + wn * 64 + j * 16 + r16;
-                if (p.splits > 1) {
-                    float *dst = p.partial + (split * 2) * p.M * p.N + row * p.N + col;
-                    dst[0] = hi[i][j][e];
-                    dst[p.M * p.N] = lo[i][j][e];
-                } else {
-                    const float X = hi[i][j][e] + lo[i][j][e];
-                    float *c = p.C + row * p.ldc + col;
-                    *c = (p.beta == 0.0f) ? p.alpha * X : fmaf(p.alpha, X, p.beta * *c);
-                }
-            }
+#undef BFX_HELPER_STEP
+    __syncthreads();
 }
 
 }  // namespace bfx

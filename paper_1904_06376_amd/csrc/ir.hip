@@ -15,8 +15,10 @@
 //                    diagonal block in one wave and publishes its flag;
 //   perm_kernel      the row permutation of ipiv, composed once per solve.
 // The host reads |r|_inf and |x|_inf once per step to apply the stopping rule.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.hpp"
 
@@ -189,15 +191,18 @@ vec_absmax_kernel(const double *v, int64_t n, unsigned long long *dst) {
     if ((threadIdx.x & 63) == 0) atomic_max_abs(dst, m);
 }
 
-// Blocked triangular solve with the LU factors, in place on y (FP32).
-// lower = 1: unit lower L (forward); lower = 0: upper U (backward, divides).
+// Blocked triangular solve with the FP32 LU factors, in place on y; T is the
+// arithmetic and vector type (float for LU-IR, double for the GMRES
+// preconditioner).  lower = 1: unit lower L (forward); lower = 0: upper U
+// (backward, divides).
+template <typename T>
 __global__ void __launch_bounds__(256)
-trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, uint32_t *ticket,
+trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32_t *ticket,
             int32_t *err, int lower) {
     __shared__ int s_blk;
     __shared__ int64_t s_known;
-    __shared__ float Ld[TB][TB + 1];
-    __shared__ float rhs[TB];
+    __shared__ T Ld[TB][TB + 1];
+    __shared__ T rhs[TB];
     const int t = threadIdx.x, lane = t & 63;
     const int64_t nblk = ceil_div(n, TB);
     if (t == 0) s_blk = (int)atomicAdd(ticket, 1u);
@@ -208,7 +213,7 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
     // diagonal block to LDS (independent of other blocks)
     for (int e = t; e < TB * TB; e += 256) {
         const int i = e / TB, c = e % TB;
-        Ld[i][c] = (i < rows && c < rows) ? LU[(r0 + i) * ld + r0 + c] : 0.0f;
+        Ld[i][c] = (i < rows && c < rows) ? (T)LU[(r0 + i) * ld + r0 + c] : (T)0;
     }
     // Off-diagonal contributions: thread (rr = t/4, sub = t%4) covers 16
     // columns.  Dependencies are visited in completion order (ascending for
@@ -216,7 +221,7 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
     // it in that order, so one acquire of a flag covers all earlier blocks and
     // thread 0 waits only when the next block is not yet known complete.
     const int rr = t >> 2, sub = t & 3;
-    float acc = 0.0f;
+    T acc = 0;
     const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
     int64_t known = 0;  // dependencies known complete
     for (int64_t d = 0; d < nb_dep; ++d) {
@@ -249,7 +254,7 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
             const float *lrow = LU + (r0 + rr) * ld;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (c0 + k < n) acc = fmaf(lrow[c0 + k], y[c0 + k], acc);
+                if (c0 + k < n) acc = fma((T)lrow[c0 + k], y[c0 + k], acc);
         }
     }
     acc += __shfl_xor(acc, 1);
@@ -257,17 +262,17 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
     if (sub == 0 && rr < rows) rhs[rr] = y[r0 + rr] - acc;
     __syncthreads();
     if (t < 64) {
-        float v = (lane < rows) ? rhs[lane] : 0.0f;
+        T v = (lane < rows) ? rhs[lane] : (T)0;
         if (lower) {
             for (int c = 0; c < rows; ++c) {
-                const float yc = __shfl(v, c);
-                if (lane > c) v = fmaf(-Ld[lane][c], yc, v);
+                const T yc = __shfl(v, c);
+                if (lane > c) v = fma(-Ld[lane][c], yc, v);
             }
         } else {
             for (int c = rows - 1; c >= 0; --c) {
                 if (lane == c) v = v / Ld[c][c];
-                const float yc = __shfl(v, c);
-                if (lane < c) v = fmaf(-Ld[lane][c], yc, v);
+                const T yc = __shfl(v, c);
+                if (lane < c) v = fma(-Ld[lane][c], yc, v);
             }
         }
         if (lane < rows) y[r0 + lane] = v;
@@ -279,6 +284,67 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, float *y, int32_t *flags, ui
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// GMRES-IR pieces (all FP64 vectors).
+// ---------------------------------------------------------------------------
+// y = A x, A promoted exactly, one workgroup per row, fixed-order reduction.
+__global__ void __launch_bounds__(256)
+matvec_kernel(const float *A, int64_t lda, int64_t n, const double *x, double *y, int vec) {
+    __shared__ double red[4];
+    const int64_t row = blockIdx.x;
+    const float *a = A + row * lda;
+    double s = 0.0;
+    if (vec) {
+        for (int64_t j = 4 * threadIdx.x; j + 3 < n; j += 1024) {
+            const float4 v = *reinterpret_cast<const float4 *>(a + j);
+            s = fma((double)v.x, x[j], s);
+            s = fma((double)v.y, x[j + 1], s);
+            s = fma((double)v.z, x[j + 2], s);
+            s = fma((double)v.w, x[j + 3], s);
+        }
+        for (int64_t j = (n & ~int64_t(3)) + threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+    } else {
+        for (int64_t j = threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+    }
+    s = block_sum_256(s, red);
+    if (threadIdx.x == 0) y[row] = s;
+}
+
+__global__ void __launch_bounds__(256)
+gather_f64(const double *v, const int32_t *perm, double *out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = v[perm[i]];
+}
+
+// h[j] = <w, V_j>, j < k: one workgroup per j, fixed-order tree (deterministic).
+__global__ void __launch_bounds__(256)
+dots_kernel(const double *V, int64_t ldv, const double *w, int64_t n, double *h) {
+    __shared__ double red[4];
+    const double *v = V + (int64_t)blockIdx.x * ldv;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], w[i], s);
+    s = block_sum_256(s, red);
+    if (threadIdx.x == 0) h[blockIdx.x] = s;
+}
+
+// w -= sum_{j<k} h_j V_j   (init = 0)   or   x += sum_{j<k} h_j V_j   (sign = +1)
+__global__ void __launch_bounds__(256)
+combine_kernel(const double *V, int64_t ldv, const double *h, int k, double *w, int64_t n,
+               double sign) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double acc = w[i];
+        for (int j = 0; j < k; ++j) acc = fma(sign * h[j], V[(int64_t)j * ldv + i], acc);
+        w[i] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+scale_f64(const double *w, double div, double *v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        v[i] = w[i] / div;
+}
+
 static unsigned grid_for(int64_t n) {
     int64_t b = ceil_div(n, 256);
     if (b > 2048) b = 2048;
@@ -286,17 +352,24 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
-// In-place FP32 solve of (LU) y = y on the workspace vector ws.w.
-static int lu_solve_ws(int64_t n, const float *LU, int64_t ldlu, const IrWs &w, hipStream_t s) {
+// In-place solve of (LU) y = y: T = float on the workspace vector (LU-IR),
+// T = double for the GMRES preconditioner.
+template <typename T>
+static int lu_solve_vec(int64_t n, const float *LU, int64_t ldlu, T *y, const IrWs &w,
+                        hipStream_t s) {
     const int64_t nb = ceil_div(n, TB);
     for (int lower = 1; lower >= 0; --lower) {
         hipLaunchKernelGGL(zero_i32, dim3(grid_for(nb)), dim3(256), 0, s, w.flags, nb);
         hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.ticket, 4);
-        hipLaunchKernelGGL(trsv_kernel, dim3((unsigned)nb), dim3(256), 0, s, LU, ldlu, n, w.w,
+        hipLaunchKernelGGL(trsv_kernel<T>, dim3((unsigned)nb), dim3(256), 0, s, LU, ldlu, n, y,
                            w.flags, w.ticket, w.err, lower);
         BFX_LAUNCH_CHECK("trsv_kernel");
     }
     return BFX_OK;
+}
+
+static int lu_solve_ws(int64_t n, const float *LU, int64_t ldlu, const IrWs &w, hipStream_t s) {
+    return lu_solve_vec<float>(n, LU, ldlu, w.w, w, s);
 }
 
 static int compose_perm(int64_t n, const int32_t *ipiv, const IrWs &w, hipStream_t s) {
@@ -432,6 +505,194 @@ extern "C" int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float 
         ++it;
     }
     res->iters = it;
+    res->status = status;
+    res->eta = eta;
+    return bfx::check_err(w, s);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES-IR (Sec. III, Sec. IV-B): refinement whose correction equation is
+// solved by GMRES on M^{-1} A d = M^{-1} r with M the low-precision LU,
+// FP64 throughout GMRES; the preconditioner applies the FP32 factors in FP64.
+// The host keeps only the O(restart) Hessenberg least-squares state (Givens
+// rotations); vectors and every O(n) / O(n^2) step stay on the device.
+// ---------------------------------------------------------------------------
+namespace bfx {
+namespace {
+struct GmresWs {
+    IrWs ir;
+    double *V;    // (m+1) x n
+    double *z;    // n
+    double *h;    // 2*(m+1) + 8 scalars: hA, hB, |w|^2
+    double *y;    // m
+};
+size_t gmres_ws_layout(GmresWs *g, void *base, int64_t n, int m) {
+    size_t off = ir_ws_layout(g ? &g->ir : nullptr, base, n);
+    off = (off + 255) & ~size_t(255);
+    const int64_t nn = n > 0 ? n : 1;
+    const size_t o_V = off; off += ((sizeof(double) * nn * (m + 1)) + 255) & ~size_t(255);
+    const size_t o_z = off; off += ((sizeof(double) * nn) + 255) & ~size_t(255);
+    const size_t o_h = off; off += ((sizeof(double) * (2 * (m + 1) + 8)) + 255) & ~size_t(255);
+    const size_t o_y = off; off += ((sizeof(double) * (m + 1)) + 255) & ~size_t(255);
+    if (g && base) {
+        char *b = (char *)base;
+        g->V = (double *)(b + o_V);
+        g->z = (double *)(b + o_z);
+        g->h = (double *)(b + o_h);
+        g->y = (double *)(b + o_y);
+    }
+    return off;
+}
+}  // namespace
+}  // namespace bfx
+
+extern "C" size_t bfx_gmres_ir_ws_size(int64_t n, int restart) {
+    if (restart < 1) restart = 1;
+    return bfx::gmres_ws_layout(nullptr, nullptr, n < 0 ? 0 : n, restart);
+}
+
+extern "C" int bfx_gmres_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
+                                  int64_t ldlu, const int32_t *ipiv, const double *b, double *x,
+                                  const bfx_gmres_opts *opts, bfx_gmres_result *res, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    bfx_gmres_opts o = {1e-14, 30, 50, 1e-8};
+    if (opts) o = *opts;
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && !LU) return -4;
+    if (ldlu < (n > 1 ? n : 1)) return -5;
+    if (n > 0 && !ipiv) return -6;
+    if (n > 0 && !b) return -7;
+    if (n > 0 && !x) return -8;
+    if (!(o.tol >= 0.0) || o.max_iter < 0 || o.restart < 1 || !(o.inner_tol >= 0.0)) return -9;
+    if (!res) return -10;
+    const int m = o.restart;
+    if (!ws || ws_bytes < bfx_gmres_ir_ws_size(n, m)) return -12;
+    res->iters = 0;
+    res->inner = 0;
+    res->status = 0;
+    res->eta = 0.0;
+    if (n == 0) return BFX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    bfx::GmresWs g;
+    bfx::gmres_ws_layout(&g, ws, n, m);
+    const bfx::IrWs &w = g.ir;
+    const unsigned gr = bfx::grid_for(n);
+    const int vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, w.err, 4);
+    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.scal, 2 * bfx::S_NSCAL);
+    hipLaunchKernelGGL(bfx::mat_norm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.scal);
+    hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(gr), dim3(256), 0, s, b, n, w.scal + bfx::S_NORMB);
+    int rc = bfx::compose_perm(n, ipiv, w, s);
+    if (rc) return rc;
+    // x0 = LUsolve32(b)
+    hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(gr), dim3(256), 0, s, b, w.perm, 1.0, w.w, n);
+    rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(bfx::update_x, dim3(gr), dim3(256), 0, s, x, w.w, 0.0, 1, n);
+    BFX_LAUNCH_CHECK("gmres init");
+
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
+    std::vector<double> hh(2 * (m + 1) + 8);
+    unsigned long long hs[bfx::S_NSCAL];
+    double prev_eta = INFINITY, eta = 0.0;
+    int it = 0, rises = 0, status = 1, inner_total = 0;
+    auto precond = [&](double *v) -> int {   // v = M^{-1} v, via gather into z
+        hipLaunchKernelGGL(bfx::gather_f64, dim3(gr), dim3(256), 0, s, v, w.perm, g.z, n);
+        int r2 = bfx::lu_solve_vec<double>(n, LU, ldlu, g.z, w, s);
+        if (r2) return r2;
+        hipLaunchKernelGGL(bfx::scale_f64, dim3(gr), dim3(256), 0, s, g.z, 1.0, v, n);
+        BFX_LAUNCH_CHECK("gmres precond");
+        return BFX_OK;
+    };
+    for (;;) {
+        hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)(w.scal + bfx::S_RN), 4);
+        hipLaunchKernelGGL(bfx::residual_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, b, x,
+                           w.r, w.scal, vec);
+        hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(gr), dim3(256), 0, s, x, n, w.scal + bfx::S_XN);
+        BFX_LAUNCH_CHECK("gmres residual");
+        BFX_HIP(hipMemcpyAsync(hs, w.scal, sizeof hs, hipMemcpyDeviceToHost, s));
+        BFX_HIP(hipStreamSynchronize(s));
+        const double normA = bfx::bits_to_double(hs[bfx::S_NORMA]);
+        const double normb = bfx::bits_to_double(hs[bfx::S_NORMB]);
+        const double rn = bfx::bits_to_double(hs[bfx::S_RN]);
+        const double xn = bfx::bits_to_double(hs[bfx::S_XN]);
+        const double den = normA * xn + normb;
+        eta = den > 0.0 ? rn / den : rn;
+        rises = (eta >= prev_eta) ? rises + 1 : 0;
+        prev_eta = eta;
+        if (!std::isfinite(eta)) { status = 3; break; }
+        if (eta <= o.tol) { status = 0; break; }
+        if (it >= o.max_iter) { status = 1; break; }
+        if (rises >= 2) { status = 2; break; }
+        // GMRES on M^{-1} A d = M^{-1} r, d0 = 0; V_0 = M^{-1} r / beta
+        rc = precond(w.r);
+        if (rc) return rc;
+        hipLaunchKernelGGL(bfx::dots_kernel, dim3(1), dim3(256), 0, s, w.r, n, w.r, n, g.h);
+        BFX_HIP(hipMemcpyAsync(hh.data(), g.h, sizeof(double), hipMemcpyDeviceToHost, s));
+        BFX_HIP(hipStreamSynchronize(s));
+        const double beta = std::sqrt(hh[0]);
+        int k = 0;
+        if (beta > 0.0) {
+            hipLaunchKernelGGL(bfx::scale_f64, dim3(gr), dim3(256), 0, s, w.r, beta, g.V, n);
+            std::fill(gv.begin(), gv.end(), 0.0);
+            gv[0] = beta;
+            for (k = 0; k < m; ++k) {
+                double *vk = g.V + (int64_t)k * n;
+                double *wv = w.r;   // the residual is recomputed next step: reuse as w
+                hipLaunchKernelGGL(bfx::matvec_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n,
+                                   vk, wv, vec);
+                rc = precond(wv);
+                if (rc) return rc;
+                double *hA = g.h, *hB = g.h + (m + 1), *nw = g.h + 2 * (m + 1);
+                hipLaunchKernelGGL(bfx::dots_kernel, dim3(k + 1), dim3(256), 0, s, g.V, n, wv, n, hA);
+                hipLaunchKernelGGL(bfx::combine_kernel, dim3(gr), dim3(256), 0, s, g.V, n, hA, k + 1,
+                                   wv, n, -1.0);
+                hipLaunchKernelGGL(bfx::dots_kernel, dim3(k + 1), dim3(256), 0, s, g.V, n, wv, n, hB);
+                hipLaunchKernelGGL(bfx::combine_kernel, dim3(gr), dim3(256), 0, s, g.V, n, hB, k + 1,
+                                   wv, n, -1.0);
+                hipLaunchKernelGGL(bfx::dots_kernel, dim3(1), dim3(256), 0, s, wv, n, wv, n, nw);
+                BFX_LAUNCH_CHECK("gmres arnoldi");
+                BFX_HIP(hipMemcpyAsync(hh.data(), g.h, sizeof(double) * (2 * (m + 1) + 1),
+                                       hipMemcpyDeviceToHost, s));
+                BFX_HIP(hipStreamSynchronize(s));
+                const double hn = std::sqrt(hh[2 * (m + 1)]);
+                for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = hh[j] + hh[(m + 1) + j];
+                H[(size_t)(k + 1) * m + k] = hn;
+                for (int j = 0; j < k; ++j) {
+                    const double a = H[(size_t)j * m + k], c2 = H[(size_t)(j + 1) * m + k];
+                    H[(size_t)j * m + k] = cs[j] * a + sn[j] * c2;
+                    H[(size_t)(j + 1) * m + k] = -sn[j] * a + cs[j] * c2;
+                }
+                const double a = H[(size_t)k * m + k], c2 = H[(size_t)(k + 1) * m + k];
+                const double rho = std::hypot(a, c2);
+                cs[k] = rho > 0.0 ? a / rho : 1.0;
+                sn[k] = rho > 0.0 ? c2 / rho : 0.0;
+                H[(size_t)k * m + k] = rho;
+                H[(size_t)(k + 1) * m + k] = 0.0;
+                gv[k + 1] = -sn[k] * gv[k];
+                gv[k] = cs[k] * gv[k];
+                ++inner_total;
+                if (hn > 0.0)
+                    hipLaunchKernelGGL(bfx::scale_f64, dim3(gr), dim3(256), 0, s, wv, hn,
+                                       g.V + (int64_t)(k + 1) * n, n);
+                if (std::fabs(gv[k + 1]) <= o.inner_tol * beta || hn == 0.0) { ++k; break; }
+            }
+            for (int j = k - 1; j >= 0; --j) {
+                double acc = gv[j];
+                for (int q = j + 1; q < k; ++q) acc -= H[(size_t)j * m + q] * yv[q];
+                yv[j] = acc / H[(size_t)j * m + j];
+            }
+            BFX_HIP(hipMemcpyAsync(g.y, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(bfx::combine_kernel, dim3(gr), dim3(256), 0, s, g.V, n, g.y, k, x, n, 1.0);
+            BFX_LAUNCH_CHECK("gmres update");
+            BFX_HIP(hipStreamSynchronize(s));
+        }
+        ++it;
+    }
+    res->iters = it;
+    res->inner = inner_total;
     res->status = status;
     res->eta = eta;
     return bfx::check_err(w, s);

@@ -159,3 +159,45 @@ def test_ir_high_kappa_reported(bfx):
     A, b, _ = workloads.conditioned_system(256, 1e12, 6)
     x, res, _ = _ir(bfx, A, b)
     assert res["status"] in (1, 2) and res["eta"] > 1e-14
+
+
+def _gmres(bfx, A, b, **kw):
+    tA = dev(A)
+    tLU = tA.clone()
+    _, ipiv, info = bfx.lu_factor(tLU, 6)
+    x, res = bfx.gmres_ir_solve(tA, tLU, ipiv, dev(b), **kw)
+    return host(x), res
+
+
+@pytest.mark.parametrize("n,kappa", [(256, 1e8), (600, 1e8), (300, 1e10)])
+def test_gmres_ir_high_kappa(bfx, orc, n, kappa):
+    """GMRES-IR reaches eta <= 1e-14 where LU-IR needs many steps or stalls;
+    refinement steps close to the oracle's."""
+    A, b, _ = workloads.conditioned_system(n, kappa, 1100 + n)
+    x, res = _gmres(bfx, A, b, restart=min(n, 200))
+    assert res["status"] == 0 and res["eta"] <= 1e-14, res
+    r = b - A.astype(np.float64) @ x
+    eta = np.abs(r).max() / (np.abs(A.astype(np.float64)).sum(1).max() * np.abs(x).max() + np.abs(b).max())
+    assert eta <= 1.01e-14
+    LU, ipiv, _ = orc.lu(A, 6, 128)
+    ro = orc.gmres_ir(A, LU, ipiv, b, restart=min(n, 200))
+    assert ro["status"] == 0 and abs(ro["iters"] - res["iters"]) <= 1, (ro, res)
+
+
+@pytest.mark.parametrize("n", [10, 50, 100])
+def test_gmres_table_diagonally_dominant_gpu(bfx, n):
+    for s in range(3):
+        g = np.random.default_rng(3000 + 17 * n + s)
+        A = g.uniform(-1, 1, (n, n))
+        d = np.maximum(np.abs(A).sum(0), np.abs(A).sum(1)) + 1.0
+        A = (A + np.diag(d * np.sign(g.uniform(-1, 1, n)))).astype(np.float32)
+        b = A.astype(np.float64) @ g.normal(size=n)
+        x, res = _gmres(bfx, A, b)
+        assert res["status"] == 0 and res["eta"] <= 1e-14 and res["iters"] <= 2, res
+
+
+def test_gmres_full_krylov_kappa_1e12(bfx):
+    n = 128
+    A, b, _ = workloads.conditioned_system(n, 1e12, 1200)
+    x, res = _gmres(bfx, A, b, restart=n, inner_tol=0.0)
+    assert res["status"] == 0 and res["eta"] <= 1e-14, res
