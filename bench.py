@@ -225,10 +225,36 @@ def main():
             ms, _ = time_launches(torch, lambda: bfx.gemm(v, X, Y, Z, ws=ws), 10, stream)
             sk[f"x{v}"] = {"us": round(ms * 1e3, 1),
                            "GBps": round(2 * 64 * K3 * 4 / (ms * 1e-3) / 1e9, 1)}
+        bfx.sgemm_fp32(X, Y, Z)
         ms_s, _ = time_launches(torch, lambda: bfx.sgemm_fp32(X, Y, Z), 5, stream)
-        sk["fp32_vector"] = {"us": round(ms_s * 1e3, 1)}
+        sk["fp32_vector"] = {"us": round(ms_s * 1e3, 1),
+                             "GBps": round(2 * 64 * K3 * 4 / (ms_s * 1e-3) / 1e9, 1)}
+        # cancellation variant: errors against FP64, diagonal and off-diagonal apart
+        Xc, Yc = workloads.cancellation(64, K3, 203)
+        X.copy_(torch.from_numpy(Xc))
+        Y.copy_(torch.from_numpy(Yc))
+        z = Xc.astype(np.float64) @ Yc.astype(np.float64)
+        zh = np.abs(Xc).astype(np.float64) @ np.abs(Yc).astype(np.float64)
+        diag = np.eye(64, dtype=bool)
+        canc = {}
+        for v in (3, 6, 9, 0):
+            if v:
+                bfx.gemm(v, X, Y, Z, ws=ws)
+            else:
+                bfx.sgemm_fp32(X, Y, Z)
+            got = Z.cpu().numpy().astype(np.float64)
+            bnd = {3: 3 * 2.0 ** -16 + 2 * K3 * 2.0 ** -24, 6: 2 * K3 * 2.0 ** -24,
+                   9: 2 * K3 * 2.0 ** -24, 0: K3 * 2.0 ** -24}[v]
+            ratio = np.abs(got - z) / (bnd * zh)
+            rel = np.abs(got - z) / np.abs(z)
+            canc["fp32_vector" if v == 0 else f"x{v}"] = {
+                "max_err_over_bound": float(ratio.max()),
+                "max_rel_diag": float(rel[diag].max()),
+                "median_rel_offdiag": float(np.median(rel[~diag])),
+                "median_cancellation_offdiag": float(np.median(np.abs(z[~diag]) / zh[~diag]))}
+        sk["cancellation"] = canc
         extras["splitk_64x64x1M"] = sk
-        del X, Y, Z, ws
+        del X, Y, Z, ws, Xc, Yc
         log(f"[bench] split-K {sk}")
 
         # batched: 4096 uneven problems

@@ -88,12 +88,18 @@ int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,
 size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K);
 
 /* Plain FP32 GEMM on the vector ALU, one rounding per FMA (Sec. II-C): the   */
-/* comparator the split variants are measured against.  Same argument        */
-/* meanings and errors as bfx_gemm without variant/workspace (so indices     */
-/* shift down by one).                                                       */
+/* comparator the split variants are measured against.  Without split-K      */
+/* (ws size 0) every output is one FMA chain in increasing k; with split-K   */
+/* (few output tiles, long K) the chains of each K range are added in a      */
+/* fixed order.  Same argument meanings as bfx_gemm without `variant`        */
+/* (indices shift down by one); -13 when the workspace is too small.         */
 int bfx_sgemm_fp32(int64_t M, int64_t N, int64_t K, float alpha,
                    const float *A, int64_t lda, const float *B, int64_t ldb,
-                   float beta, float *C, int64_t ldc, void *stream);
+                   float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* Workspace bytes bfx_sgemm_fp32 needs for this shape (0 when no split-K). */
+size_t bfx_sgemm_ws_size(int64_t M, int64_t N, int64_t K);
 
 /* ------------------------------------------------------------------------ */
 /* Batched uneven GEMMs in one persistent launch (many independent          */
@@ -111,10 +117,15 @@ typedef struct bfx_plan bfx_plan;
 
 /* Build a plan for `count` problems (descs: HOST array, copied).  The plan
  * picks a tile shape per problem from the tuning table at `tune_table`
- * (a JSON file written by the autotuner; NULL or "" = built-in defaults),
- * orders the tiles longest-first, uploads the work list, and captures
- * "reset the work counter + one persistent kernel" into a HIP graph on first
- * launch.  The plan owns its device buffers until bfx_plan_destroy.
+ * (a JSON file written by the autotuner: "tile" 0-3 = general engine
+ * 64x64/128x128/128x64/64x128, 4-5 = wave-specialised 64x64/128x128;
+ * NULL or "" = built-in defaults), orders the tiles longest-first, uploads
+ * the work lists, and captures "reset the work counters + persistent
+ * kernels" into a HIP graph on first launch: one persistent kernel for the
+ * problems the wave-specialised engine takes (K % 4 == 0, A 16-byte aligned
+ * with lda % 4 == 0), one for the rest.  A wave-specialised tile asked for a
+ * problem it cannot take falls back to the default general tile.  The plan
+ * owns its device buffers until bfx_plan_destroy.
  * Errors: -1 variant, -2 count < 0, -3 descs NULL, -4 out NULL, -(100+i)
  * when descriptor i is invalid (sizes, NULL pointers, leading dims). */
 int bfx_gemm_batched_plan_create(int variant, int64_t count,

@@ -63,7 +63,8 @@ SIGNATURES = {
                   c_f32, c_vp, c_i64, c_vp, c_size, c_vp], c_int),
     "bfx_gemm_ws_size": ([c_int, c_i64, c_i64, c_i64], c_size),
     "bfx_sgemm_fp32": ([c_i64, c_i64, c_i64, c_f32, c_vp, c_i64, c_vp, c_i64,
-                        c_f32, c_vp, c_i64, c_vp], c_int),
+                        c_f32, c_vp, c_i64, c_vp, c_size, c_vp], c_int),
+    "bfx_sgemm_ws_size": ([c_i64, c_i64, c_i64], c_size),
     "bfx_gemm_batched_plan_create": ([c_int, c_i64, ctypes.POINTER(GemmDesc),
                                       ctypes.c_char_p, ctypes.POINTER(c_vp)], c_int),
     "bfx_plan_launch": ([c_vp, c_vp], c_int),

@@ -4,6 +4,7 @@ device memory and the current HIP stream."""
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -87,16 +88,30 @@ def sgemm_fp32(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
     if C is None:
         C = torch.empty((M, N), dtype=torch.float32, device=A.device)
         beta = 0.0
+    need = lib.bfx_sgemm_ws_size(M, N, K)
+    ws = _ws(need, A.device)
     check(lib.bfx_sgemm_fp32(M, N, K, alpha, A.data_ptr(), _rows(A, "A"), B.data_ptr(),
-                             _rows(B, "B"), beta, C.data_ptr(), _rows(C, "C"), _stream()),
+                             _rows(B, "B"), beta, C.data_ptr(), _rows(C, "C"),
+                             ws.data_ptr() if ws is not None else None, need, _stream()),
           "bfx_sgemm_fp32")
     return C
 
 
+def default_tune_table(variant: int) -> str | None:
+    """The autotuner's table shipped with the package for `variant`, if any."""
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune", f"gfx950_x{variant}.json")
+    return p if os.path.exists(p) else None
+
+
 class BatchedGemmPlan:
-    """One persistent, graph-captured launch over many independent GEMMs."""
+    """One persistent, graph-captured launch over many independent GEMMs.
+
+    tune_table: path of an autotuner table; None uses the packaged table of the
+    variant when there is one, "" the built-in defaults."""
 
     def __init__(self, variant: int, problems, tune_table: str | None = None):
+        if tune_table is None:
+            tune_table = default_tune_table(variant)
         self._keep = problems
         descs = (GemmDesc * len(problems))()
         for i, (A, B, C, alpha, beta) in enumerate(problems):

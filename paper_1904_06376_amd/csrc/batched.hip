@@ -8,7 +8,10 @@
 // then replays the graph on the caller's stream.  The persistent kernel keeps
 // one workgroup per resident slot; each takes the next tile index with an
 // atomic add and runs the shared tile engine until the list is exhausted, so
-// every workgroup reaches the exit.
+// every workgroup reaches the exit.  Problems the wave-specialised engine can
+// take (K % 4 == 0, 16-byte aligned A rows) go to one persistent kernel of
+// 512-thread workgroups, the others to one of 256-thread workgroups running
+// the general engine; both kernels sit in the same graph, one after the other.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -22,9 +25,12 @@
 namespace bfx {
 
 namespace {
-enum { CFG_64x64 = 0, CFG_128x128 = 1, CFG_128x64 = 2, CFG_64x128 = 3, NCFG = 4 };
-const int cfg_bm[NCFG] = {64, 128, 128, 64};
-const int cfg_bn[NCFG] = {64, 128, 64, 128};
+// 0-3: general engine tiles; 4-5: wave-specialised tiles.
+enum { CFG_64x64 = 0, CFG_128x128 = 1, CFG_128x64 = 2, CFG_64x128 = 3, CFG_F64 = 4, CFG_F128 = 5,
+       NCFG = 6 };
+const int cfg_bm[NCFG] = {64, 128, 128, 64, 64, 128};
+const int cfg_bn[NCFG] = {64, 128, 64, 128, 64, 128};
+bool cfg_fast(int c) { return c >= CFG_F64; }
 
 struct TileItem {
     int32_t prob, tm, tn, cfg;
@@ -34,7 +40,42 @@ int bucket(int64_t x) { return x <= 64 ? 0 : x <= 128 ? 1 : x <= 256 ? 2 : 3; }
 }  // namespace
 
 __global__ void __launch_bounds__(64) plan_zero_counter(uint32_t *c) {
-    if (threadIdx.x == 0) *c = 0u;
+    if (threadIdx.x < 2) c[threadIdx.x] = 0u;
+}
+
+__device__ __forceinline__ GemmParams desc_params(const bfx_gemm_desc &d) {
+    GemmParams p;
+    p.M = d.M; p.N = d.N; p.K = d.K;
+    p.A = d.A; p.lda = d.lda; p.B = d.B; p.ldb = d.ldb; p.C = d.C; p.ldc = d.ldc;
+    p.alpha = d.alpha; p.beta = d.beta;
+    p.k_per_split = d.K; p.splits = 1; p.partial = nullptr;
+    p.vecA = ((uintptr_t)d.A % 16 == 0) && (d.lda % 4 == 0);
+    p.vecB = ((uintptr_t)d.B % 16 == 0) && (d.ldb % 4 == 0);
+    return p;
+}
+
+// Wave-specialised persistent kernel (512 threads).  WIDE = false: only the
+// 64 x 64 tile (half the LDS, two workgroups per CU); true: 64 and 128.
+template <int V, bool WIDE>
+__global__ void __launch_bounds__(512, 1)
+persistent_fast_kernel(const bfx_gemm_desc *__restrict__ probs,
+                       const TileItem *__restrict__ tiles, int64_t ntiles, uint32_t *counter) {
+    extern __shared__ __align__(16) uint16_t smem[];
+    __shared__ int64_t s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t idx = s_idx;
+        __syncthreads();
+        if (idx >= ntiles) break;
+        const TileItem t = tiles[idx];
+        const bfx_gemm_desc d = probs[t.prob];
+        const GemmParams p = desc_params(d);
+        if (WIDE && t.cfg == CFG_F128)
+            gemm_tile_fast<V, 128, 128>(p, (int64_t)t.tm * 128, (int64_t)t.tn * 128, 0, d.K, 0, smem);
+        else
+            gemm_tile_fast<V, 64, 64>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
+    }
 }
 
 // WIDE = false: only the 64x64 tile is compiled in (fewer registers, more
@@ -53,13 +94,7 @@ persistent_gemm_kernel(const bfx_gemm_desc *__restrict__ probs,
         if (idx >= ntiles) break;
         const TileItem t = tiles[idx];
         const bfx_gemm_desc d = probs[t.prob];
-        GemmParams p;
-        p.M = d.M; p.N = d.N; p.K = d.K;
-        p.A = d.A; p.lda = d.lda; p.B = d.B; p.ldb = d.ldb; p.C = d.C; p.ldc = d.ldc;
-        p.alpha = d.alpha; p.beta = d.beta;
-        p.k_per_split = d.K; p.splits = 1; p.partial = nullptr;
-        p.vecA = ((uintptr_t)d.A % 16 == 0) && (d.lda % 4 == 0);
-        p.vecB = ((uintptr_t)d.B % 16 == 0) && (d.ldb % 4 == 0);
+        const GemmParams p = desc_params(d);
         if constexpr (!WIDE) {
             gemm_tile<V, 64, 64, 2, 2>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
         } else {
@@ -86,19 +121,21 @@ persistent_gemm_kernel(const bfx_gemm_desc *__restrict__ probs,
 struct bfx_plan {
     int variant = 6;
     int64_t count = 0, ntiles = 0;
-    bool wide = false;
-    size_t lds = 0;
-    int grid = 0;
+    // [0]: wave-specialised kernel, [1]: general engine kernel
+    int64_t n_list[2] = {0, 0};
+    bool wide[2] = {false, false};
+    size_t lds[2] = {0, 0};
+    int grid[2] = {0, 0};
+    const void *kern[2] = {nullptr, nullptr};
     std::vector<bfx_gemm_desc> h_probs;
     bfx_gemm_desc *d_probs = nullptr;
-    bfx::TileItem *d_tiles = nullptr;
-    uint32_t *d_counter = nullptr;
+    bfx::TileItem *d_tiles = nullptr;   // fast list, then general list
+    uint32_t *d_counter = nullptr;      // [0] fast, [1] general
     void *d_ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void *kernel = nullptr;
 };
 
 namespace bfx {
@@ -145,22 +182,30 @@ bool parse_table(const char *path, int variant, int table[4][4]) {
     return any;
 }
 
-int default_cfg(int64_t M, int64_t N) {
-    if (M >= 256 && N >= 256) return CFG_128x128;
-    if (M >= 256 && N > 64) return CFG_128x64;
-    if (N >= 256 && M > 64) return CFG_64x128;
+// Whether the wave-specialised engine can take the problem (as fast_ok of
+// the one-problem path, with the whole K in one range).
+bool desc_fast(const bfx_gemm_desc &d) {
+    return d.K > 0 && d.K % 4 == 0 && ((uintptr_t)d.A % 16 == 0) && d.lda % 4 == 0 &&
+           ((uintptr_t)d.B % 4 == 0) && ((uintptr_t)d.C % 4 == 0) &&
+           128 * d.lda * 4 < (int64_t(1) << 31) && d.K * d.ldb * 4 < (int64_t(1) << 31);
+}
+
+int default_cfg(const bfx_gemm_desc &d) {
+    if (desc_fast(d)) return (d.M >= 256 && d.N >= 256) ? CFG_F128 : CFG_F64;
+    if (d.M >= 256 && d.N >= 256) return CFG_128x128;
+    if (d.M >= 256 && d.N > 64) return CFG_128x64;
+    if (d.N >= 256 && d.M > 64) return CFG_64x128;
     return CFG_64x64;
 }
 
 template <int V>
-const void *pick_kernel(bool wide) {
-    return wide ? (const void *)persistent_gemm_kernel<V, true>
-                : (const void *)persistent_gemm_kernel<V, false>;
-}
-
-template <int V>
-size_t lds_for(bool wide) {
-    return wide ? tile_lds_bytes<V, 128, 128>() : tile_lds_bytes<V, 64, 64>();
+void pick(bfx_plan *p) {
+    p->kern[0] = p->wide[0] ? (const void *)persistent_fast_kernel<V, true>
+                            : (const void *)persistent_fast_kernel<V, false>;
+    p->lds[0] = p->wide[0] ? tile_lds_bytes<V, 128, 128>() : tile_lds_bytes<V, 64, 64>();
+    p->kern[1] = p->wide[1] ? (const void *)persistent_gemm_kernel<V, true>
+                            : (const void *)persistent_gemm_kernel<V, false>;
+    p->lds[1] = p->wide[1] ? tile_lds_bytes<V, 128, 128>() : tile_lds_bytes<V, 64, 64>();
 }
 
 void plan_free(bfx_plan *p) {
@@ -208,29 +253,35 @@ extern "C" int bfx_gemm_batched_plan_create(int variant, int64_t count, const bf
     p->variant = variant;
     p->count = count;
     p->h_probs.assign(descs, descs + count);
-    std::vector<TileItem> tiles;
-    std::vector<double> cost;
+    std::vector<TileItem> tiles[2];
+    std::vector<double> cost[2];
     for (int64_t i = 0; i < count; ++i) {
         const bfx_gemm_desc &d = descs[i];
         if (d.M == 0 || d.N == 0) continue;
         int cfg = table[bucket(d.M)][bucket(d.N)];
-        if (cfg < 0) cfg = default_cfg(d.M, d.N);
-        if (cfg != CFG_64x64) p->wide = true;
+        if (cfg < 0 || (cfg_fast(cfg) && !desc_fast(d))) cfg = default_cfg(d);
+        const int L = cfg_fast(cfg) ? 0 : 1;
+        if (cfg != CFG_64x64 && cfg != CFG_F64) p->wide[L] = true;
         const int64_t tm = ceil_div(d.M, cfg_bm[cfg]), tn = ceil_div(d.N, cfg_bn[cfg]);
         const double c = (double)cfg_bm[cfg] * cfg_bn[cfg] * (double)(ceil_div(d.K, BK) + 2);
         for (int64_t a = 0; a < tm; ++a)
             for (int64_t b = 0; b < tn; ++b) {
-                tiles.push_back(TileItem{(int32_t)i, (int32_t)a, (int32_t)b, cfg});
-                cost.push_back(c);
+                tiles[L].push_back(TileItem{(int32_t)i, (int32_t)a, (int32_t)b, cfg});
+                cost[L].push_back(c);
             }
         const size_t ws = gemm_ws_bytes(variant, d.M, d.N, d.K);
         if (ws > p->ws_bytes) p->ws_bytes = ws;
     }
-    std::vector<size_t> order(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<TileItem> sorted(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    // LPT order within each list; the fast list first in device memory
+    std::vector<TileItem> sorted;
+    for (int L = 0; L < 2; ++L) {
+        std::vector<size_t> order(tiles[L].size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return cost[L][a] > cost[L][b]; });
+        for (size_t i = 0; i < order.size(); ++i) sorted.push_back(tiles[L][order[i]]);
+        p->n_list[L] = (int64_t)order.size();
+    }
     p->ntiles = (int64_t)sorted.size();
 
     int rc = BFX_OK;
@@ -255,22 +306,28 @@ extern "C" int bfx_gemm_batched_plan_create(int variant, int64_t count, const bf
         return fail(e, "hipMemcpy(plan tiles)");
 
     switch (variant) {
-        case 1: p->kernel = pick_kernel<1>(p->wide); p->lds = lds_for<1>(p->wide); break;
-        case 3: p->kernel = pick_kernel<3>(p->wide); p->lds = lds_for<3>(p->wide); break;
-        case 6: p->kernel = pick_kernel<6>(p->wide); p->lds = lds_for<6>(p->wide); break;
-        default: p->kernel = pick_kernel<9>(p->wide); p->lds = lds_for<9>(p->wide); break;
+        case 1: pick<1>(p); break;
+        case 3: pick<3>(p); break;
+        case 6: pick<6>(p); break;
+        default: pick<9>(p); break;
     }
-    if ((e = hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds)) !=
-        hipSuccess)
-        return fail(e, "hipFuncSetAttribute(persistent)");
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return fail(e, "hipGetDevice");
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return fail(e, "hipDeviceGetAttribute");
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p->kernel, 256, p->lds)) != hipSuccess)
-        return fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-    if (per_cu < 1) per_cu = 1;
-    p->grid = cus * per_cu;
+    for (int L = 0; L < 2; ++L) {
+        if (p->n_list[L] == 0) continue;
+        const int threads = L == 0 ? 512 : 256;
+        if ((e = hipFuncSetAttribute(p->kern[L], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)p->lds[L])) != hipSuccess)
+            return fail(e, "hipFuncSetAttribute(persistent)");
+        int per_cu = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p->kern[L], threads, p->lds[L])) !=
+            hipSuccess)
+            return fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        if (per_cu < 1) per_cu = 1;
+        p->grid[L] = cus * per_cu;
+    }
     if ((e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) != hipSuccess)
         return fail(e, "hipStreamCreate(plan)");
     *out = p;
@@ -285,8 +342,15 @@ extern "C" int bfx_plan_launch(bfx_plan *p, void *stream) {
     if (!p->exec) {
         BFX_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
         hipLaunchKernelGGL(plan_zero_counter, dim3(1), dim3(64), 0, p->cap, p->d_counter);
-        void *args[] = {&p->d_probs, &p->d_tiles, &p->ntiles, &p->d_counter};
-        hipError_t el = hipLaunchKernel(p->kernel, dim3(p->grid), dim3(256), args, p->lds, p->cap);
+        hipError_t el = hipGetLastError();
+        for (int L = 0; L < 2 && el == hipSuccess; ++L) {
+            if (p->n_list[L] == 0) continue;
+            TileItem *list = p->d_tiles + (L == 0 ? 0 : p->n_list[0]);
+            uint32_t *cnt = p->d_counter + L;
+            void *args[] = {&p->d_probs, &list, &p->n_list[L], &cnt};
+            el = hipLaunchKernel(p->kern[L], dim3(p->grid[L]), dim3(L == 0 ? 512 : 256), args,
+                                 p->lds[L], p->cap);
+        }
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(p->cap, &g);
         if (el != hipSuccess) {

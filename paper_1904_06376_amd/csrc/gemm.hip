@@ -31,12 +31,13 @@ gemm_split_kernel(GemmParams p) {
     gemm_tile<V, BM, BN, WM, WN>(p, m0, n0, kb, ke, split, smem);
 }
 
-// Aligned tiles (see gemm_tile_fast), 512 threads: 4 MFMA + 4 helper waves.
+// Wave-specialised tiles (see gemm_tile_fast), 512 threads: 4 MFMA + 4
+// helper waves.
 template <int V, int BM, int BN>
 __global__ void __launch_bounds__(512, 1)
 gemm_fast_kernel(GemmParams p) {
     extern __shared__ __align__(16) uint16_t smem[];
-    const int64_t tiles_m = p.M / BM, tiles_n = p.N / BN;
+    const int64_t tiles_m = ceil_div(p.M, BM), tiles_n = ceil_div(p.N, BN);
     const int64_t tiles = tiles_m * tiles_n;
     const int64_t total = tiles * p.splits;
     const int64_t id = xcd_remap(blockIdx.x, total);
@@ -54,35 +55,60 @@ gemm_fast_kernel(GemmParams p) {
     gemm_tile_fast<V, BM, BN>(p, m0, n0, kb, ke, split, smem);
 }
 
-// Fixed-order reduction of split-K partials, then the epilogue.  Each
-// workgroup owns 64 consecutive outputs; its 4 waves sum interleaved slices of
-// the splits (wave w takes splits w, w+4, ...) in increasing order, and the
-// four slice sums are added in a fixed order: deterministic for a given
-// split count.
+// Fixed-order reduction of split-K partials, then the epilogue.  Two passes
+// so that a long reduction over few outputs still spreads over many
+// workgroups:
+//   pass 1 (only when splits > SPLIT_GROUP): group g sums splits
+//           g*SPLIT_GROUP .. in increasing order, hi and lo apart;
+//   pass 2: the group sums (or the splits themselves) are added in increasing
+//           order, X = hi + lo (the largest bin last), then the epilogue.
+// The order depends only on the split count: deterministic.
+constexpr int SPLIT_GROUP = 16;
+
 __global__ void __launch_bounds__(256)
-splitk_reduce_kernel(const float *__restrict__ partial, int splits, int64_t M,
-                     int64_t N, float alpha, float beta, float *C, int64_t ldc) {
-    __shared__ float sh[4][64], sl[4][64];
-    const int64_t MN = M * N;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-    float h = 0.0f, l = 0.0f;
-    if (e < MN)
-        for (int s = w; s < splits; s += 4) {
-            h += partial[(int64_t)(2 * s) * MN + e];
-            l += partial[(int64_t)(2 * s + 1) * MN + e];
-        }
-    sh[w][lane] = h;
-    sl[w][lane] = l;
-    __syncthreads();
-    if (w == 0 && e < MN) {
-        const float H = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
-        const float L = (sl[0][lane] + sl[1][lane]) + (sl[2][lane] + sl[3][lane]);
-        const float X = H + L;
-        const int64_t row = e / N, col = e % N;
-        float *c = C + row * ldc + col;
-        *c = (beta == 0.0f) ? alpha * X : fmaf(alpha, X, beta * *c);
+splitk_group_kernel(const float *__restrict__ partial, int splits, int64_t MN,
+                    float *__restrict__ group) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int g = blockIdx.y;
+    if (e >= MN) return;
+    const int s0 = g * SPLIT_GROUP;
+    const int s1 = (s0 + SPLIT_GROUP < splits) ? s0 + SPLIT_GROUP : splits;
+    float hv[SPLIT_GROUP], lv[SPLIT_GROUP];
+#pragma unroll
+    for (int q = 0; q < SPLIT_GROUP; ++q) {
+        const bool in = s0 + q < s1;
+        hv[q] = in ? partial[(int64_t)(2 * (s0 + q)) * MN + e] : 0.0f;
+        lv[q] = in ? partial[(int64_t)(2 * (s0 + q) + 1) * MN + e] : 0.0f;
     }
+    float h = 0.0f, l = 0.0f;
+#pragma unroll
+    for (int q = 0; q < SPLIT_GROUP; ++q) {
+        if (s0 + q < s1) { h += hv[q]; l += lv[q]; }
+    }
+    group[(int64_t)(2 * g) * MN + e] = h;
+    group[(int64_t)(2 * g + 1) * MN + e] = l;
+}
+
+__global__ void __launch_bounds__(256)
+splitk_final_kernel(const float *__restrict__ src, int count, int64_t M, int64_t N,
+                    float alpha, float beta, float *C, int64_t ldc) {
+    const int64_t MN = M * N;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= MN) return;
+    float h = 0.0f, l = 0.0f;
+#pragma unroll 8
+    for (int s = 0; s < count; ++s) {
+        h += src[(int64_t)(2 * s) * MN + e];
+        l += src[(int64_t)(2 * s + 1) * MN + e];
+    }
+    const float X = h + l;
+    const int64_t row = e / N, col = e % N;
+    float *c = C + row * ldc + col;
+    *c = (beta == 0.0f) ? alpha * X : fmaf(alpha, X, beta * *c);
+}
+
+static int split_groups(int splits) {
+    return splits > SPLIT_GROUP ? (int)ceil_div(splits, SPLIT_GROUP) : 0;
 }
 
 // --------------------------------------------------------------------------
@@ -134,7 +160,7 @@ size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K) {
     tile_for(M, N, BM, BN);
     const int s = choose_splits(M, N, K, BM, BN);
     if (s <= 1) return 0;
-    return (size_t)s * 2 * (size_t)M * (size_t)N * sizeof(float);
+    return (size_t)(s + split_groups(s)) * 2 * (size_t)M * (size_t)N * sizeof(float);
 }
 
 template <int V, int BM, int BN>
@@ -146,19 +172,20 @@ static int launch_fast(const GemmParams &p, hipStream_t s) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    const int64_t blocks = (p.M / BM) * (p.N / BN) * p.splits;
+    const int64_t blocks = ceil_div(p.M, BM) * ceil_div(p.N, BN) * p.splits;
     hipLaunchKernelGGL((gemm_fast_kernel<V, BM, BN>), dim3((unsigned)blocks), dim3(512), lds, s, p);
     BFX_LAUNCH_CHECK("gemm_fast_kernel launch");
     return BFX_OK;
 }
 
-// The aligned fast path applies when every tile is full, every K range is a
-// whole number of 32-steps and rows are 16-byte aligned.
-// Buffer offsets are 32-bit: 128 rows of A and one split's K rows of B must
-// each span less than 2^31 bytes.
+// The wave-specialised path applies when A's rows are 16-byte aligned, K is a
+// multiple of 4 (whole 16-byte vectors along k) and each split's K range is a
+// multiple of 32.  Buffer offsets are 32-bit: BM rows of A and one split's K
+// rows of B must each span less than 2^31 bytes.
 static bool fast_ok(const GemmParams &p, int BM, int BN) {
-    return p.M % BM == 0 && p.N % BN == 0 && p.K % BK == 0 && p.K > 0 &&
-           p.k_per_split % BK == 0 && p.vecA && p.vecB && ((uintptr_t)p.C % 4 == 0) &&
+    (void)BN;
+    return p.K % 4 == 0 && p.K > 0 && p.k_per_split % BK == 0 && p.vecA &&
+           ((uintptr_t)p.B % 4 == 0) && ((uintptr_t)p.C % 4 == 0) &&
            BM * p.lda * 4 < (int64_t(1) << 31) &&
            p.k_per_split * p.ldb * 4 < (int64_t(1) << 31);
 }
@@ -190,7 +217,8 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
     p.partial = (float *)ws;
     p.vecA = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
     p.vecB = ((uintptr_t)B % 16 == 0) && (ldb % 4 == 0);
-    if (p.splits > 1 && (size_t)p.splits * 2 * M * N * sizeof(float) > ws_bytes)
+    const int groups = split_groups(p.splits);
+    if (p.splits > 1 && (size_t)(p.splits + groups) * 2 * M * N * sizeof(float) > ws_bytes)
         return -14;
     int rc;
     switch (variant) {
@@ -201,10 +229,20 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
         default: return -1;
     }
     if (rc != BFX_OK || p.splits <= 1) return rc;
-    const int64_t blocks = ceil_div(M * N, 64);
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       p.partial, p.splits, M, N, alpha, beta, C, ldc);
-    BFX_LAUNCH_CHECK("splitk_reduce_kernel launch");
+    const int64_t blocks = ceil_div(M * N, 256);
+    const float *src = p.partial;
+    int count = p.splits;
+    if (groups > 0) {
+        float *grp = p.partial + (size_t)p.splits * 2 * M * N;
+        hipLaunchKernelGGL(splitk_group_kernel, dim3((unsigned)blocks, (unsigned)groups), dim3(256),
+                           0, stream, p.partial, p.splits, M * N, grp);
+        BFX_LAUNCH_CHECK("splitk_group_kernel launch");
+        src = grp;
+        count = groups;
+    }
+    hipLaunchKernelGGL(splitk_final_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       src, count, M, N, alpha, beta, C, ldc);
+    BFX_LAUNCH_CHECK("splitk_final_kernel launch");
     return BFX_OK;
 }
 

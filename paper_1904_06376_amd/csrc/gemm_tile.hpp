@@ -253,13 +253,15 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int64_t m0, int64
 
 
 // ---------------------------------------------------------------------------
-// Aligned fast path: BM x BN tile (128 x 128 or 64 x 64), 4 waves (2 x 2),
-// K a multiple of 32, rows 16-byte aligned, no bounds checks.  Differences
-// from gemm_tile:
+// Fast path: BM x BN tile (128 x 128 or 64 x 64), 4 MFMA + 4 helper waves.
+// Requirements: A rows 16-byte aligned (A 16-byte aligned, lda % 4 == 0),
+// K % 4 == 0 and the K range of a split a multiple of 32.  M, N and K need
+// not fill the tile: partial tiles are handled by clamped loads whose values
+// are replaced by zeros and by a masked epilogue.  Differences from gemm_tile:
 //   * loads: one thread per A row / B column and BM*32/256 consecutive k
 //     values (16-byte loads of A, coalesced 4-byte loads of B) through buffer
-//     resources with SGPR offsets, so every LDS store is a conflict-free
-//     16-byte store of 8 BF16 (rows are 80 bytes apart);
+//     resources, so every LDS store is a conflict-free 16-byte store of 8 BF16
+//     (rows are 80 bytes apart);
 //   * global loads are issued two K-steps ahead (two register stages);
 //   * the split is branch-free (hardware RNE); the rare values for which it is
 //     not exact (Inf/NaN, or a first term that rounds to Inf) are detected from
@@ -306,7 +308,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     constexpr int KPT = BM * BK / 256;                  // k values per helper thread
     static_assert(BM == BN && KPT % 8 == 0, "square tiles with >= 8 k values per helper thread");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int KT = (int)((ke - kb) / BK);
+    const int KT = (int)ceil_div(ke - kb, (int64_t)BK);
 
     if (wave < 4) {
         // ------------------------------ MFMA waves ------------------------------
@@ -368,6 +370,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                 for (int e = 0; e < 4; ++e) {
                     const int64_t row = m0 + wm * (BM / 2) + i * 16 + kg * 4 + e;
                     const int64_t col = n0 + wn * (BN / 2) + j * 16 + r16;
+                    if (row >= p.M || col >= p.N) continue;
                     if (p.splits > 1) {
                         float *dst = p.partial + (split * 2) * p.M * p.N + row * p.N + col;
                         dst[0] = hi[i][j][e];
@@ -385,29 +388,64 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     const int h = tid - 256;
     const int arow = h % BM, aq = h / BM;   // A row, k group
     const int bcol = h % BN, bq = h / BN;   // B column, k group
-    // Buffer resources over this tile's A rows and B columns: loads take one
-    // VGPR offset per thread and SGPR offsets per step (no 64-bit addresses).
+    // Extent of this tile inside the matrices.  `full` (uniform) selects the
+    // unmasked code; otherwise every load is clamped to an element inside the
+    // tile's range and its value replaced by zero before the split.
+    const int rows = (int)((p.M - m0 < BM) ? p.M - m0 : BM);
+    const int cols = (int)((p.N - n0 < BN) ? p.N - n0 : BN);
+    const int klen = (int)(ke - kb);
+    const bool full = rows == BM && cols == BN && klen % BK == 0;
+    const bool a_ok = arow < rows, b_ok = bcol < cols;
+    // Buffer resources over exactly the elements of this tile's A rows and B
+    // columns (the range check is a second guard; no load leaves the range).
     const int lda = (int)p.lda, ldb = (int)p.ldb;
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(p.A + m0 * p.lda + kb), (short)0, BM * lda * 4, 0x00020000);
+        (void *)(p.A + m0 * p.lda + kb), (short)0, ((rows - 1) * lda + klen) * 4, 0x00020000);
     const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(p.B + kb * p.ldb + n0), (short)0, (int)(ke - kb) * ldb * 4, 0x00020000);
-    const int voA = (arow * lda + aq * KPT) * 4;
-    const int voB = (bq * KPT * ldb + bcol) * 4;
+        (void *)(p.B + kb * p.ldb + n0), (short)0, ((klen - 1) * ldb + cols) * 4, 0x00020000);
+    const int voA = ((a_ok ? arow : 0) * lda + aq * KPT) * 4;
+    const int voB = (bq * KPT * ldb + (b_ok ? bcol : 0)) * 4;
 
     float ra[2][KPT], rb[2][KPT];
     auto issue = [&](int st, int step) {
-        const int soA = step * BK * 4;
+        if (full) {
+            const int soA = step * BK * 4;
 #pragma unroll
-        for (int q = 0; q < KPT / 4; ++q) {
-            const bfx_f32x4 v = __builtin_bit_cast(
-                bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA + 16 * q, soA, 0));
-            ra[st][4 * q] = v[0]; ra[st][4 * q + 1] = v[1]; ra[st][4 * q + 2] = v[2]; ra[st][4 * q + 3] = v[3];
+            for (int q = 0; q < KPT / 4; ++q) {
+                const bfx_f32x4 v = __builtin_bit_cast(
+                    bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA + 16 * q, soA, 0));
+                ra[st][4 * q] = v[0]; ra[st][4 * q + 1] = v[1]; ra[st][4 * q + 2] = v[2]; ra[st][4 * q + 3] = v[3];
+            }
+            const int soB = step * BK * ldb * 4;
+#pragma unroll
+            for (int j = 0; j < KPT; ++j)
+                rb[st][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, voB, soB + j * ldb * 4, 0));
+        } else {
+            // k beyond the range: read k = 0 of the same row / column instead
+            const int k0 = step * BK + aq * KPT;
+#pragma unroll
+            for (int q = 0; q < KPT / 4; ++q) {
+                const int off = (k0 + 4 * q < klen) ? voA + (step * BK + 4 * q) * 4 : voA - aq * KPT * 4;
+                const bfx_f32x4 v = __builtin_bit_cast(
+                    bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, off, 0, 0));
+                ra[st][4 * q] = v[0]; ra[st][4 * q + 1] = v[1]; ra[st][4 * q + 2] = v[2]; ra[st][4 * q + 3] = v[3];
+            }
+            const int kB = step * BK + bq * KPT;
+#pragma unroll
+            for (int j = 0; j < KPT; ++j) {
+                const int off = (kB + j < klen) ? voB + (step * BK + j) * ldb * 4 : voB - bq * KPT * ldb * 4;
+                rb[st][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, off, 0, 0));
+            }
         }
-        const int soB = step * BK * ldb * 4;
+    };
+    // Zeros for the values outside the tile (partial tiles only).
+    auto mask = [&](int st, int step) {
+        const int k0 = step * BK + aq * KPT, kB = step * BK + bq * KPT;
 #pragma unroll
-        for (int j = 0; j < KPT; ++j)
-            rb[st][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, voB, soB + j * ldb * 4, 0));
+        for (int q = 0; q < KPT; ++q) {
+            if (!a_ok || k0 + q >= klen) ra[st][q] = 0.0f;
+            if (!b_ok || kB + q >= klen) rb[st][q] = 0.0f;
+        }
     };
     auto put = [&](uint16_t *base, int row, int kg0, const uint32_t pl8[][KPT / 2]) {
 #pragma unroll
@@ -419,7 +457,8 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                     make_uint4(pl8[pl][4 * c], pl8[pl][4 * c + 1], pl8[pl][4 * c + 2], pl8[pl][4 * c + 3]);
         }
     };
-    auto stage = [&](int st, int buf) {
+    auto stage = [&](int st, int buf, int step) {
+        if (!full) mask(st, step);
         uint16_t *base = smem + buf * P * PLANE;
         uint32_t flag = 0, pa[3][KPT / 2], pb[3][KPT / 2];
         split_run_fast<P, KPT>(ra[st], pa, flag);
@@ -436,13 +475,14 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         for (int e = 0; e < 2 * KPT; ++e) {
             const bool isA = e < KPT;
             const int q = isA ? e : e - KPT;
-            const uint32_t bits = isA
-                ? __builtin_amdgcn_raw_buffer_load_b32(rA, voA + 4 * q, step * BK * 4, 0)
-                : __builtin_amdgcn_raw_buffer_load_b32(rB, voB, (step * BK + q) * ldb * 4, 0);
+            const int k = (isA ? aq : bq) * KPT + q;
+            const bool in = (isA ? a_ok : b_ok) && step * BK + k < klen;
+            const uint32_t bits = !in ? 0u
+                : isA ? __builtin_amdgcn_raw_buffer_load_b32(rA, voA + 4 * q, step * BK * 4, 0)
+                      : __builtin_amdgcn_raw_buffer_load_b32(rB, voB, (step * BK + q) * ldb * 4, 0);
             uint32_t hh[3];
             split3_exact(__builtin_bit_cast(float, bits), hh[0], hh[1], hh[2]);
             const int row = isA ? arow : BM + bcol;
-            const int k = (isA ? aq : bq) * KPT + q;
 #pragma unroll
             for (int pl = 0; pl < P; ++pl) base[pl * PLANE + row * LDK + k] = (uint16_t)hh[pl];
         }
@@ -453,7 +493,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     {                                                                      \
         __syncthreads();                                                   \
         if ((t) + 1 < KT) {                                                \
-            const uint32_t flag = stage(SP, ((t) + 1) & 1);                \
+            const uint32_t flag = stage(SP, ((t) + 1) & 1, (t) + 1);       \
             issue(SP, ((t) + 3 < KT) ? (t) + 3 : KT - 1);                  \
             if (flag_bad(flag)) fixup((t) + 1, ((t) + 1) & 1);             \
         }                                                                  \
@@ -461,7 +501,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     if (KT > 0) {
         issue(0, 0);
         issue(1, KT > 1 ? 1 : KT - 1);
-        const uint32_t flag = stage(0, 0);
+        const uint32_t flag = stage(0, 0, 0);
         issue(0, KT > 2 ? 2 : KT - 1);
         if (flag_bad(flag)) fixup(0, 0);
         int s = 0;

@@ -4,12 +4,15 @@
 //   1. panel_kernel  - FP32 factorisation of the (n-j) x jb panel.  The panel
 //      rows are spread over G co-resident workgroups, 256 rows each, held in
 //      LDS for the whole panel.  Per column: each workgroup finds its local
-//      arg-max (wave shuffles + LDS), publishes the candidate row, one grid
-//      barrier, then every workgroup picks the same pivot (largest magnitude,
-//      lowest row on ties, as ISAMAX), swaps, divides and applies the rank-1
-//      update to its own rows.  One grid barrier per column.
+//      arg-max (wave shuffles + LDS) and publishes the candidate row and a
+//      64-bit header {column tag, |candidate|}; every workgroup then polls the
+//      G headers of that column, picks the same pivot (largest magnitude,
+//      lowest row on ties, as ISAMAX: workgroups own increasing row ranges),
+//      reads the winning row, swaps, divides and applies the rank-1 update to
+//      its own rows.  The header exchange is the only grid-wide
+//      synchronisation: one round of polling per column, no barrier counter.
 //   2. laswp_kernel  - the panel's row interchanges applied to the columns
-//      left and right of the panel.
+//      left and right of the panel (rows staged in LDS, swaps replayed there).
 //   3. trsm_kernel   - U12 = L11^{-1} A12 (unit lower, FP32 FMA chains in
 //      index order, one thread per column, L11 in LDS).
 //   4. A22 -= L21 x U12 with the split-BF16 GEMM (alpha = -1, beta = 1).
@@ -26,11 +29,10 @@ constexpr int MAX_G = 256;   // co-resident workgroups the panel may use
 constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
 
 struct LuWs {
-    float *slot_val;    // [2][MAX_G]
-    int32_t *slot_idx;  // [2][MAX_G]
-    float *slot_row;    // [2][MAX_G][PNB]
-    float *diag_row;    // [2][PNB]
-    uint32_t *counter;  // grid barrier arrivals
+    uint64_t *hdr;      // [2][MAX_G] {tag << 32 | bits(|candidate|)}
+    int32_t *slot_idx;  // [2][MAX_G] candidate row (panel-relative)
+    float *slot_row;    // [2][MAX_G][PNB] candidate row values
+    float *diag_row;    // [2][PNB] row c before the interchange
 };
 
 size_t lu_ws_layout(LuWs *w, void *base) {
@@ -40,18 +42,16 @@ size_t lu_ws_layout(LuWs *w, void *base) {
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const size_t o_val = take(sizeof(float) * 2 * MAX_G);
+    const size_t o_hdr = take(sizeof(uint64_t) * 2 * MAX_G);
     const size_t o_idx = take(sizeof(int32_t) * 2 * MAX_G);
     const size_t o_row = take(sizeof(float) * 2 * MAX_G * PNB);
     const size_t o_diag = take(sizeof(float) * 2 * PNB);
-    const size_t o_cnt = take(sizeof(uint32_t) * 4);
     if (w && base) {
         char *b = (char *)base;
-        w->slot_val = (float *)(b + o_val);
+        w->hdr = (uint64_t *)(b + o_hdr);
         w->slot_idx = (int32_t *)(b + o_idx);
         w->slot_row = (float *)(b + o_row);
         w->diag_row = (float *)(b + o_diag);
-        w->counter = (uint32_t *)(b + o_cnt);
     }
     return off;
 }
@@ -70,35 +70,13 @@ __device__ __forceinline__ void better(float &v, int &i, float v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
 
-// Grid-wide barrier over the G workgroups of the panel: arrivals counted on a
-// monotonic counter; every wait is bounded.  On expiry info is set to -1 and
-// from then on no barrier of this launch waits, so every wave still exits
-// promptly (the factorisation is then reported invalid through info).
-__device__ void grid_barrier(uint32_t *counter, uint32_t target, int32_t *info) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) break;
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    __syncthreads();
-    __threadfence();
-}
-
 __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
     extern __shared__ float P[];  // [PROWS][w + 1]
     __shared__ float U[PNB], D[PNB];
     __shared__ float red_v[PROWS / 64];
     __shared__ int red_i[PROWS / 64];
-    __shared__ int s_piv;
+    __shared__ int s_piv, s_win;
+    __shared__ float s_val;
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int w = a.w, ld = w + 1;
@@ -115,6 +93,7 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
 
     for (int c = 0; c < w; ++c) {
         const int par = c & 1;
+        const uint32_t tag = (uint32_t)(a.j + c + 1);   // never 0 (headers start zeroed)
         // ---- local arg-max of |P[., c]| over rows >= c
         float v = (own && pr >= c) ? fabsf(P[t * ld + c]) : -1.0f;
         int idx = own ? (int)pr : INT_MAX;
@@ -130,42 +109,74 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
             float bv = red_v[0];
             int bi = red_i[0];
             for (int k = 1; k < PROWS / 64; ++k) better(bv, bi, red_v[k], red_i[k]);
-            a.ws.slot_val[par * MAX_G + g] = bv;
-            a.ws.slot_idx[par * MAX_G + g] = (bv >= 0.0f) ? bi : INT_MAX;
+            s_val = bv;
             s_piv = (bv >= 0.0f) ? bi : -1;
         }
         __syncthreads();
+        // ---- publish the candidate row (and row c, by its owner), then the header
         if (s_piv >= 0 && t < w)
             a.ws.slot_row[(par * MAX_G + g) * PNB + t] = P[(s_piv - row0) * ld + t];
+        if (t == 0) a.ws.slot_idx[par * MAX_G + g] = s_piv;
         if (c >= row0 && c < row0 + PROWS && t < w)
             a.ws.diag_row[par * PNB + t] = P[(c - row0) * ld + t];
-        grid_barrier(a.ws.counter, (uint32_t)(c + 1) * (uint32_t)a.G, a.info);
-
-        // ---- global pivot: every workgroup reduces the same candidates
-        if (wave == 0) {
-            float bv = -1.0f;
-            int bi = INT_MAX, bg = 0;
-            for (int k = lane; k < a.G; k += 64) {
-                const float v2 = a.ws.slot_val[par * MAX_G + k];
-                const int i2 = a.ws.slot_idx[par * MAX_G + k];
-                if (v2 > bv || (v2 == bv && i2 < bi)) { bv = v2; bi = i2; bg = k; }
+        __threadfence();
+        __syncthreads();
+        if (t == 0) {
+            const uint64_t h = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(s_val);
+            __hip_atomic_store(&a.ws.hdr[par * MAX_G + g], h, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // ---- every wave polls 64 of the G headers (bounded wait), then the
+        // largest candidate wins, the lowest workgroup on ties
+        {
+            const int k = wave * 64 + lane;
+            float bv = -2.0f;
+            int bg = INT_MAX;
+            if (k < a.G) {
+                uint64_t h = 0;
+                unsigned spins = 0;
+                for (;;) {
+                    h = __hip_atomic_load(&a.ws.hdr[par * MAX_G + k], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(h >> 32) == tag) break;
+                    if (__hip_atomic_load(a.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) break;
+                    if (++spins > SPIN_LIMIT) {
+                        __hip_atomic_store(a.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                bv = __uint_as_float((uint32_t)h);
+                bg = k;
             }
             for (int off = 32; off > 0; off >>= 1) {
                 const float v2 = __shfl_xor(bv, off);
-                const int i2 = __shfl_xor(bi, off);
                 const int g2 = __shfl_xor(bg, off);
-                if (v2 > bv || (v2 == bv && i2 < bi)) { bv = v2; bi = i2; bg = g2; }
+                better(bv, bg, v2, g2);
             }
-            if (lane == 0) { s_piv = bi; red_i[0] = bg; }
+            if (lane == 0) { red_v[wave] = bv; red_i[wave] = bg; }
         }
         __syncthreads();
-        const int p = s_piv;
-        const int pg = red_i[0];
+        __threadfence();
+        if (t == 0) {
+            float bv = red_v[0];
+            int bg = red_i[0];
+            for (int k = 1; k < PROWS / 64; ++k) better(bv, bg, red_v[k], red_i[k]);
+            // a wait that expired leaves bg possibly without a published row:
+            // fall back to this workgroup's own slot (the result is invalid
+            // anyway and reported through info = -1)
+            s_win = (bg < a.G) ? bg : g;
+        }
+        __syncthreads();
+        const int pg = s_win;
         if (t < w) {
             U[t] = a.ws.slot_row[(par * MAX_G + pg) * PNB + t];
             D[t] = a.ws.diag_row[par * PNB + t];
         }
+        if (t == 0) s_piv = a.ws.slot_idx[par * MAX_G + pg];
         __syncthreads();
+        // a valid pivot row is >= c; anything else only follows an expired wait
+        const int p = (s_piv >= c && s_piv < a.m) ? s_piv : c;
         const float piv = U[c];
         if (g == 0 && t == 0) {
             a.ipiv[a.j + c] = (int32_t)(a.j + p);
@@ -194,24 +205,57 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(64) zero_u32(uint32_t *p, int n) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+__global__ void __launch_bounds__(256) zero_u64(uint64_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += 256) p[i] = 0ull;
 }
 
-// Row interchanges of rows j..j+w-1 (ipiv) on every column outside the panel.
-__global__ void __launch_bounds__(256)
+// Row interchanges of rows j..j+w-1 (ipiv, applied in order) on every column
+// outside the panel.  Each 64-thread workgroup owns 64 columns (one per
+// lane): it stages the block rows and every row below the block that an
+// interchange names in LDS, replays the interchanges there in order (each
+// lane touches only its own column) and writes the rows back.  Block rows
+// keep LDS slots 0..w-1; a row below the block takes slot w + i for the first
+// interchange i that names it.
+constexpr int SWP_COLS = 64;
+constexpr size_t SWP_LDS = (size_t)2 * PNB * SWP_COLS * sizeof(float);
+__global__ void __launch_bounds__(SWP_COLS)
 laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *ipiv) {
-    int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    extern __shared__ float T[];  // [2 * PNB][SWP_COLS]
+    __shared__ int sp[PNB], slot[PNB];
+    const int l = threadIdx.x;
+    for (int i = l; i < w; i += SWP_COLS) {
+        const int64_t q = ipiv[j + i] - j;  // >= i for a valid factorisation
+        sp[i] = (q >= i && q < n - j) ? (int)q : i;
+    }
+    __syncthreads();
+    for (int i = l; i < w; i += SWP_COLS) {
+        const int q = sp[i];
+        int sl = q;
+        if (q >= w) {
+            int i0 = 0;
+            while (sp[i0] != q) ++i0;  // ends at i0 = i at the latest
+            sl = w + i0;
+        }
+        slot[i] = sl;
+    }
+    __syncthreads();
+    int64_t col = (int64_t)blockIdx.x * SWP_COLS + l;
     if (col >= j) col += w;
     if (col >= n) return;
+    for (int i = 0; i < w; ++i) T[i * SWP_COLS + l] = A[(j + i) * lda + col];
+    for (int i = 0; i < w; ++i)
+        if (slot[i] == w + i) T[(w + i) * SWP_COLS + l] = A[(j + sp[i]) * lda + col];
     for (int i = 0; i < w; ++i) {
-        const int64_t r = j + i, p = ipiv[r];
-        if (p != r) {
-            const float x = A[r * lda + col];
-            A[r * lda + col] = A[p * lda + col];
-            A[p * lda + col] = x;
+        const int q = slot[i];
+        if (q != i) {
+            const float x = T[i * SWP_COLS + l];
+            T[i * SWP_COLS + l] = T[q * SWP_COLS + l];
+            T[q * SWP_COLS + l] = x;
         }
     }
+    for (int i = 0; i < w; ++i) A[(j + i) * lda + col] = T[i * SWP_COLS + l];
+    for (int i = 0; i < w; ++i)
+        if (slot[i] == w + i) A[(j + sp[i]) * lda + col] = T[(w + i) * SWP_COLS + l];
 }
 
 // U12 = L11^{-1} A12.  Each 128-thread workgroup copies 128 columns of A12
@@ -260,25 +304,27 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         BFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (PNB * PNB + PNB * (TRSM_COLS + 1)) * (int)sizeof(float)));
+        BFX_HIP(hipFuncSetAttribute((const void *)laswp_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)SWP_LDS));
         attr = true;
     }
     BFX_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, s, w.hdr, 2 * MAX_G);
+    BFX_LAUNCH_CHECK("zero_u64");
     for (int64_t j = 0; j < n; j += PNB) {
         const int jb = (int)((n - j < PNB) ? n - j : PNB);
         PanelArgs pa;
         pa.A = A; pa.lda = lda; pa.n = n; pa.j = j; pa.m = n - j; pa.w = jb;
         pa.G = (int)ceil_div(n - j, PROWS);
         pa.ipiv = ipiv; pa.info = info; pa.ws = w;
-        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, w.counter, 4);
-        BFX_LAUNCH_CHECK("zero_u32");
         void *args[] = {&pa};
         const size_t lds = (size_t)PROWS * (jb + 1) * sizeof(float);
         BFX_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(pa.G), dim3(PROWS),
                                            args, (unsigned)lds, s));
         const int64_t others = n - jb;
         if (others > 0) {
-            hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, 256)), dim3(256), 0, s,
-                               A, lda, n, j, jb, ipiv);
+            hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_COLS),
+                               SWP_LDS, s, A, lda, n, j, jb, ipiv);
             BFX_LAUNCH_CHECK("laswp_kernel");
         }
         const int64_t rest = n - j - jb;

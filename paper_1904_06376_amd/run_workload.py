@@ -1,0 +1,80 @@
+"""Run one library workload a few times (for profilers such as rocprofv3).
+
+    python paper_1904_06376_amd/run_workload.py gemm   --n 8192 --variant 6 --reps 5
+    python paper_1904_06376_amd/run_workload.py splitk --variant 6 --reps 10
+    python paper_1904_06376_amd/run_workload.py lu     --n 16384 --kappa 1e4
+    python paper_1904_06376_amd/run_workload.py batched-gemm --count 4096 --reps 3
+    python paper_1904_06376_amd/run_workload.py batched-solve --count 512 --reps 2
+
+Inputs are the seeded synthetic workloads of the benchmark; nothing is timed
+here except a one-line summary printed at the end.
+"""
+import argparse
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", choices=["gemm", "splitk", "lu", "batched-gemm", "batched-solve"])
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--variant", type=int, default=6)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--kappa", type=float, default=1e4)
+    ap.add_argument("--count", type=int, default=4096)
+    a = ap.parse_args()
+
+    import torch
+    import paper_1904_06376_amd as bfx
+    import workloads
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    if a.workload == "gemm":
+        A = torch.from_numpy(workloads.normal((a.n, a.n), 100)).to(dev)
+        B = torch.from_numpy(workloads.normal((a.n, a.n), 101)).to(dev)
+        C = torch.empty_like(A)
+        for _ in range(a.reps):
+            bfx.gemm(a.variant, A, B, C)
+    elif a.workload == "splitk":
+        K = 1 << 20
+        X = torch.from_numpy(workloads.uniform((64, K), 201)).to(dev)
+        Y = torch.from_numpy(workloads.uniform((K, 64), 202)).to(dev)
+        Z = torch.empty((64, 64), dtype=torch.float32, device=dev)
+        for _ in range(a.reps):
+            bfx.gemm(a.variant, X, Y, Z)
+    elif a.workload == "lu":
+        A, b = workloads.conditioned_system_torch(a.n, a.kappa, 7, dev)
+        for _ in range(a.reps):
+            LU = A.clone()
+            _, ipiv, info = bfx.lu_factor(LU, a.variant)
+            x, res = bfx.ir_solve(A, LU, ipiv, b)
+    elif a.workload == "batched-gemm":
+        shapes, probs = workloads.batched_problems(a.count, 0)
+        tens = [(torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev),
+                 torch.empty((x.shape[0], y.shape[1]), dtype=torch.float32, device=dev), 1.0, 0.0)
+                for (x, y) in probs]
+        plan = bfx.BatchedGemmPlan(a.variant, tens)
+        for _ in range(a.reps):
+            plan.launch()
+        plan.close()
+    else:
+        systems, sizes = workloads.batch_systems_torch(a.count, a.kappa, 11, dev)
+        probs = [(A, b, torch.empty(b.shape[0], dtype=torch.float64, device=dev))
+                 for (A, b) in systems]
+        plan = bfx.BatchedSolvePlan(a.variant, probs)
+        for _ in range(a.reps):
+            plan.launch()
+        plan.results()
+        plan.close()
+    torch.cuda.synchronize()
+    print(f"{a.workload}: done in {time.perf_counter() - t0:.2f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -24,7 +24,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-TILES = {0: "64x64", 1: "128x128", 2: "128x64", 3: "64x128"}
+# 0-3: general engine (256 threads); 4-5: wave-specialised engine (512 threads)
+TILES = {0: "64x64", 1: "128x128", 2: "128x64", 3: "64x128", 4: "ws64x64", 5: "ws128x128"}
 EDGES = [(32, 64), (80, 128), (144, 256), (272, 512)]
 
 

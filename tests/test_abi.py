@@ -39,7 +39,7 @@ def test_argument_errors_before_device_use():
     assert lib.bfx_gemm(6, 4, 4, 4, 1.0, v, 3, v, 4, 0.0, v, 4, None, 0, None) == -7
     assert lib.bfx_gemm(6, 4, 4, 4, 1.0, v, 4, v, 4, 0.0, v, 2, None, 0, None) == -12
     assert lib.bfx_gemm(6, 0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, None, 0, None) == 0
-    assert lib.bfx_sgemm_fp32(4, 4, -2, 1.0, v, 4, v, 4, 0.0, v, 4, None) == -3
+    assert lib.bfx_sgemm_fp32(4, 4, -2, 1.0, v, 4, v, 4, 0.0, v, 4, None, 0, None) == -3
     assert lib.bfx_split_f32(v, -1, 3, v, v, v, None) == -2
     assert lib.bfx_split_f32(v, 8, 4, v, v, v, None) == -3
     assert lib.bfx_split_f32(v, 8, 3, v, v, None, None) == -6

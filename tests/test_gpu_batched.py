@@ -73,10 +73,12 @@ def test_batched_matches_per_problem_and_replays(bfx):
 
 
 def test_batched_beta_and_ragged(bfx, orc):
-    """beta = 1 accumulation, shapes not multiples of 16, empty problems."""
+    """beta = 1 accumulation, shapes not multiples of 16, empty problems; the
+    plan mixes both engines (K % 4 == 0 goes to the wave-specialised one)."""
     g = np.random.default_rng(9)
     probs = []
-    for (M, N, K) in [(33, 47, 19), (1, 1, 1), (130, 70, 257), (0, 5, 5), (64, 64, 0), (200, 300, 31)]:
+    for (M, N, K) in [(33, 47, 19), (1, 1, 1), (130, 70, 257), (0, 5, 5), (64, 64, 0), (200, 300, 31),
+                      (33, 47, 20), (130, 70, 256), (200, 300, 36), (1, 1, 4), (300, 270, 516)]:
         probs.append((workloads.normal((M, K), M + N), workloads.normal((K, N), K + 3)))
     tens = []
     C0s = []
@@ -95,11 +97,13 @@ def test_batched_beta_and_ragged(bfx, orc):
 
 
 def test_batched_tune_table(bfx, tmp_path):
-    """A tuning table forcing each tile shape gives the same results (within the
-    bound; summation order per tile shape is identical inside a K-step)."""
+    """A tuning table forcing each tile shape: the four general-engine shapes
+    give identical results (same summation order inside a K-step), so do the
+    two wave-specialised shapes; across engines the product order differs and
+    the results agree within twice the bound."""
     shapes, probs = _problems(12, 21, 32, 300)
     outs = []
-    for tile in range(4):
+    for tile in range(6):
         table = {"arch": "gfx950", "variant": 6,
                  "entries": [{"m": m, "n": n, "tile": tile} for m in (64, 128, 256, 512)
                              for n in (64, 128, 256, 512)]}
@@ -110,9 +114,15 @@ def test_batched_tune_table(bfx, tmp_path):
         plan.launch()
         outs.append([host(t[2]).copy() for t in tens])
         plan.close()
-    for k in range(1, 4):
+    for k in (1, 2, 3):
         for a, b in zip(outs[0], outs[k]):
             np.testing.assert_array_equal(a, b)
+    for a, b in zip(outs[4], outs[5]):
+        np.testing.assert_array_equal(a, b)
+    for (A, B), a, b in zip(probs, outs[0], outs[4]):
+        bnd = gemm_bound(6, A.shape[1]) * absref(A, B)
+        assert np.all(np.abs(b - ref64(A, B)) <= bnd)
+        assert np.all(np.abs(a - b) <= 2 * bnd)
 
 
 def test_batched_4096_workload_sampled(bfx, orc):

@@ -13,8 +13,11 @@ from tests.gpu_util import absref, dev, gemm_bound, host, ref64
 
 pytestmark = pytest.mark.gpu
 
+# K % 4 == 0 with 16-byte aligned rows takes the wave-specialised engine
+# (partial tiles masked); the other shapes the general engine.
 SHAPES = [(256, 256, 256), (200, 130, 77), (129, 257, 33), (17, 300, 5), (1, 1, 1),
-          (64, 64, 1000), (300, 40, 600), (3, 5, 4096), (130, 130, 128)]
+          (64, 64, 1000), (300, 40, 600), (3, 5, 4096), (130, 130, 128),
+          (200, 130, 96), (129, 257, 36), (1, 1, 4), (65, 63, 44), (127, 129, 1028)]
 
 
 def _check_bound(variant, A, B, C, Corc=None, alpha=1.0):
@@ -153,6 +156,27 @@ def test_gemm_fast_vs_general_engine(bfx, orc, variant):
     assert np.all(np.abs(Cf - Cg) <= 2 * bnd)
 
 
+@pytest.mark.parametrize("variant", [3, 6, 9])
+def test_gemm_partial_tiles_fast_vs_general(bfx, orc, variant):
+    """Partial tiles through the wave-specialised engine (masked loads and
+    epilogue) and through the general engine: both within the bound."""
+    A = workloads.normal((200, 132), 18)
+    B = workloads.normal((132, 70), 19)
+    Cf = host(bfx.gemm(variant, dev(A), dev(B)))
+    tA = dev(np.pad(A, ((0, 0), (0, 1))))[:, :132]
+    Cg = host(bfx.gemm(variant, tA, dev(B)))
+    bnd = gemm_bound(variant, 132) * absref(A, B)
+    z = ref64(A, B)
+    assert np.all(np.abs(Cf - z) <= bnd) and np.all(np.abs(Cg - z) <= bnd)
+    assert np.all(np.abs(Cf - Cg) <= 2 * bnd)
+    # the masked region of C is untouched: write into a larger buffer
+    big = torch.full((210, 80), 7.0, dtype=torch.float32, device="cuda")
+    bfx.gemm(variant, dev(A), dev(B), big[:200, :70])
+    hb = host(big)
+    assert np.all(hb[200:] == 7.0) and np.all(hb[:, 70:] == 7.0)
+    np.testing.assert_array_equal(hb[:200, :70], Cf)
+
+
 def test_gemm_K0(bfx):
     A = np.zeros((5, 0), np.float32)
     B = np.zeros((0, 7), np.float32)
@@ -161,8 +185,9 @@ def test_gemm_K0(bfx):
 
 
 @pytest.mark.parametrize("shape", [(256, 256, 256), (200, 130, 77), (1, 1, 1), (129, 257, 33),
-                                   (64, 64, 1000)])
+                                   (64, 64, 500)])
 def test_sgemm_bitwise_equals_oracle(bfx, orc, shape):
+    """Without split-K every output is the oracle's FMA chain: bit-identical."""
     M, N, K = shape
     A = workloads.normal((M, K), 40 + M)
     B = workloads.normal((K, N), 41 + N)
@@ -170,6 +195,17 @@ def test_sgemm_bitwise_equals_oracle(bfx, orc, shape):
     C0 = workloads.normal((M, N), 42)
     np.testing.assert_array_equal(host(bfx.sgemm_fp32(dev(A), dev(B), dev(C0), 0.5, -2.0)),
                                   orc.sgemm(A, B, C0, 0.5, -2.0))
+
+
+def test_sgemm_splitk_long_k(bfx, orc):
+    """Few tiles and a long K: the comparator splits K (fixed-order sum of the
+    chains of each range); within the FP32 bound of the exact product."""
+    A = workloads.uniform((64, 1 << 16), 50)
+    B = workloads.uniform((1 << 16, 64), 51)
+    assert bfx.lib.bfx_sgemm_ws_size(64, 64, 1 << 16) > 0
+    C = host(bfx.sgemm_fp32(dev(A), dev(B)))
+    K = A.shape[1]
+    assert np.all(np.abs(C - ref64(A, B)) <= K * 2.0 ** -24 * absref(A, B))
 
 
 # ---- full-size workloads: sampled entries checked against the oracle ----------
