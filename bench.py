@@ -323,8 +323,10 @@ def main():
 
 
 def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
+    """One n x n system per kappa: LU (bf16x6 trailing updates) + LU-IR, and
+    for kappa >= 1e8 also GMRES-IR (bounded budget at 1e12, status reported)."""
     res = {}
-    for kappa in (1e4,):
+    for kappa in (1e1, 1e4, 1e8, 1e12):
         t0 = time.perf_counter()
         A, b = workloads.conditioned_system_torch(n, kappa, 7, dev)
         log(f"[bench] generated n={n} kappa={kappa:g} system in {time.perf_counter() - t0:.1f}s")
@@ -338,44 +340,64 @@ def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
         x, r = bfx.ir_solve(A, LU, ipiv, b)
         torch.cuda.synchronize()
         t_ir = time.perf_counter() - t0
-        res[f"n{n}_kappa{kappa:g}"] = {"lu_ms": round(t_lu * 1e3, 2), "ir_ms": round(t_ir * 1e3, 2),
-                                       "solves_per_s": round(1.0 / (t_lu + t_ir), 3),
-                                       "lu_tflops_fp32eq": round(2 / 3 * n ** 3 / t_lu / 1e12, 2),
-                                       "iters": r["iters"], "status": r["status"],
-                                       "eta": r["eta"], "info": int(info.item())}
+        row = {"lu_ms": round(t_lu * 1e3, 2), "lu_tflops_fp32eq": round(2 / 3 * n ** 3 / t_lu / 1e12, 2),
+               "info": int(info.item()),
+               "lu_ir": {"ms": round(t_ir * 1e3, 2), "iters": r["iters"], "status": r["status"],
+                         "eta": r["eta"], "solves_per_s": round(1.0 / (t_lu + t_ir), 3)}}
+        if kappa >= 1e8:
+            budget = dict(max_iter=3, restart=60) if kappa >= 1e12 else dict(max_iter=10, restart=50)
+            t0 = time.perf_counter()
+            xg, g = bfx.gmres_ir_solve(A, LU, ipiv, b, **budget)
+            torch.cuda.synchronize()
+            t_g = time.perf_counter() - t0
+            row["gmres_ir"] = {"ms": round(t_g * 1e3, 2), "iters": g["iters"], "inner": g["inner"],
+                               "status": g["status"], "eta": g["eta"], "budget": budget,
+                               "solves_per_s": round(1.0 / (t_lu + t_g), 3)}
+            del xg
+        res[f"n{n}_kappa{kappa:g}"] = row
+        log(f"[bench] n={n} kappa={kappa:g}: {row}")
         del A, b, LU, x
+        torch.cuda.empty_cache()
     return res
 
 
-def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512, kappa=1e4):
-    t0 = time.perf_counter()
-    systems, sizes = workloads.batch_systems_torch(count, kappa, 11, dev)
-    log(f"[bench] generated {count} systems (n in [64,1024]) in {time.perf_counter() - t0:.1f}s")
-    probs = [(A, b, torch.empty(b.shape[0], dtype=torch.float64, device=dev)) for (A, b) in systems]
-    plan = bfx.BatchedSolvePlan(6, probs)
-    plan.launch()
-    res = plan.results()
-    ms, _ = time_launches(torch, plan.launch, 3, stream)
-    conv = sum(1 for r in res if r["status"] == 0)
-    out = {"ms": round(ms, 3), "solves_per_s": round(count / (ms * 1e-3), 1),
-           "converged": conv, "count": count, "kappa": kappa,
-           "max_eta": max(r["eta"] for r in res),
-           "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
-           "lu_flop_fp32eq": float(sum(2.0 / 3.0 * int(n) ** 3 for n in sizes))}
-    plan.close()
-    sub = probs[:64]
-    plan2 = bfx.BatchedSolvePlan(6, sub)
-    plan2.launch_per_problem()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan2.launch_per_problem()
-    torch.cuda.synchronize()
-    per = (time.perf_counter() - t0) / len(sub)
-    plan2.close()
-    out["per_problem_ms_each"] = round(per * 1e3, 3)
-    out["per_problem_extrapolated_ms"] = round(per * 1e3 * count, 1)
-    out["speedup_vs_per_problem"] = round(per * 1e3 * count / ms, 1)
-    del probs, systems
+def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512):
+    """512 systems, n uniform in [64, 1024], one persistent launch of LU + IR
+    per kappa; one launch per problem timed on a 64-system subset at 1e4."""
+    out = {}
+    for kappa in (1e1, 1e4, 1e8, 1e12):
+        t0 = time.perf_counter()
+        systems, sizes = workloads.batch_systems_torch(count, kappa, 11, dev)
+        log(f"[bench] generated {count} systems (n in [64,1024], kappa {kappa:g}) in "
+            f"{time.perf_counter() - t0:.1f}s")
+        probs = [(A, b, torch.empty(b.shape[0], dtype=torch.float64, device=dev)) for (A, b) in systems]
+        plan = bfx.BatchedSolvePlan(6, probs)
+        plan.launch()
+        res = plan.results()
+        ms, _ = time_launches(torch, plan.launch, 3, stream)
+        conv = sum(1 for r in res if r["status"] == 0)
+        row = {"ms": round(ms, 3), "solves_per_s": round(count / (ms * 1e-3), 1),
+               "converged": conv, "count": count,
+               "max_eta": max(r["eta"] for r in res),
+               "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+               "lu_flop_fp32eq": float(sum(2.0 / 3.0 * int(n) ** 3 for n in sizes))}
+        plan.close()
+        if kappa == 1e4:
+            sub = probs[:64]
+            plan2 = bfx.BatchedSolvePlan(6, sub)
+            plan2.launch_per_problem()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan2.launch_per_problem()
+            torch.cuda.synchronize()
+            per = (time.perf_counter() - t0) / len(sub)
+            plan2.close()
+            row["per_problem_ms_each"] = round(per * 1e3, 3)
+            row["per_problem_extrapolated_ms"] = round(per * 1e3 * count, 1)
+            row["speedup_vs_per_problem"] = round(per * 1e3 * count / ms, 1)
+        out[f"kappa{kappa:g}"] = row
+        log(f"[bench] batched solves kappa={kappa:g}: {row}")
+        del probs, systems
     return out
 
 

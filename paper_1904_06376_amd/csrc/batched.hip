@@ -57,7 +57,7 @@ __device__ __forceinline__ GemmParams desc_params(const bfx_gemm_desc &d) {
 // Wave-specialised persistent kernel (512 threads).  WIDE = false: only the
 // 64 x 64 tile (half the LDS, two workgroups per CU); true: 64 and 128.
 template <int V, bool WIDE>
-__global__ void __launch_bounds__(512, 1)
+__global__ void __launch_bounds__(512, WIDE ? 1 : 2)
 persistent_fast_kernel(const bfx_gemm_desc *__restrict__ probs,
                        const TileItem *__restrict__ tiles, int64_t ntiles, uint32_t *counter) {
     extern __shared__ __align__(16) uint16_t smem[];
@@ -71,7 +71,7 @@ persistent_fast_kernel(const bfx_gemm_desc *__restrict__ probs,
         const TileItem t = tiles[idx];
         const bfx_gemm_desc d = probs[t.prob];
         const GemmParams p = desc_params(d);
-        if (WIDE && t.cfg == CFG_F128)
+        if (WIDE && V != 9 && t.cfg == CFG_F128)
             gemm_tile_fast<V, 128, 128>(p, (int64_t)t.tm * 128, (int64_t)t.tn * 128, 0, d.K, 0, smem);
         else
             gemm_tile_fast<V, 64, 64>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
@@ -185,8 +185,8 @@ bool parse_table(const char *path, int variant, int table[4][4]) {
 // Whether the wave-specialised engine can take the problem (as fast_ok of
 // the one-problem path, with the whole K in one range).
 bool desc_fast(const bfx_gemm_desc &d) {
-    return d.K > 0 && d.K % 4 == 0 && ((uintptr_t)d.A % 16 == 0) && d.lda % 4 == 0 &&
-           ((uintptr_t)d.B % 4 == 0) && ((uintptr_t)d.C % 4 == 0) &&
+    return d.K > 0 && d.K % 4 == 0 && d.N % 4 == 0 && ((uintptr_t)d.A % 16 == 0) && d.lda % 4 == 0 &&
+           ((uintptr_t)d.B % 16 == 0) && d.ldb % 4 == 0 && ((uintptr_t)d.C % 4 == 0) &&
            128 * d.lda * 4 < (int64_t(1) << 31) && d.K * d.ldb * 4 < (int64_t(1) << 31);
 }
 
@@ -202,7 +202,7 @@ template <int V>
 void pick(bfx_plan *p) {
     p->kern[0] = p->wide[0] ? (const void *)persistent_fast_kernel<V, true>
                             : (const void *)persistent_fast_kernel<V, false>;
-    p->lds[0] = p->wide[0] ? tile_lds_bytes<V, 128, 128>() : tile_lds_bytes<V, 64, 64>();
+    p->lds[0] = p->wide[0] ? fast_lds_bytes<V, 128, 128>() : fast_lds_bytes<V, 64, 64>();
     p->kern[1] = p->wide[1] ? (const void *)persistent_gemm_kernel<V, true>
                             : (const void *)persistent_gemm_kernel<V, false>;
     p->lds[1] = p->wide[1] ? tile_lds_bytes<V, 128, 128>() : tile_lds_bytes<V, 64, 64>();
@@ -260,6 +260,9 @@ extern "C" int bfx_gemm_batched_plan_create(int variant, int64_t count, const bf
         if (d.M == 0 || d.N == 0) continue;
         int cfg = table[bucket(d.M)][bucket(d.N)];
         if (cfg < 0 || (cfg_fast(cfg) && !desc_fast(d))) cfg = default_cfg(d);
+        // x9 with both wave-specialised widths in one kernel exceeds the
+        // register file; its batches use the 64-wide tile only
+        if (variant == 9 && cfg == CFG_F128) cfg = CFG_F64;
         const int L = cfg_fast(cfg) ? 0 : 1;
         if (cfg != CFG_64x64 && cfg != CFG_F64) p->wide[L] = true;
         const int64_t tm = ceil_div(d.M, cfg_bm[cfg]), tn = ceil_div(d.N, cfg_bn[cfg]);

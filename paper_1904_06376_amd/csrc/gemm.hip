@@ -34,7 +34,7 @@ gemm_split_kernel(GemmParams p) {
 // Wave-specialised tiles (see gemm_tile_fast), 512 threads: 4 MFMA + 4
 // helper waves.
 template <int V, int BM, int BN>
-__global__ void __launch_bounds__(512, 1)
+__global__ void __launch_bounds__(512, BM == 64 ? 2 : 1)
 gemm_fast_kernel(GemmParams p) {
     extern __shared__ __align__(16) uint16_t smem[];
     const int64_t tiles_m = ceil_div(p.M, BM), tiles_n = ceil_div(p.N, BN);
@@ -165,7 +165,7 @@ size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K) {
 
 template <int V, int BM, int BN>
 static int launch_fast(const GemmParams &p, hipStream_t s) {
-    const size_t lds = tile_lds_bytes<V, BM, BN>();
+    const size_t lds = fast_lds_bytes<V, BM, BN>();
     static bool attr_set = false;
     if (!attr_set) {
         BFX_HIP(hipFuncSetAttribute((const void *)gemm_fast_kernel<V, BM, BN>,
@@ -178,14 +178,14 @@ static int launch_fast(const GemmParams &p, hipStream_t s) {
     return BFX_OK;
 }
 
-// The wave-specialised path applies when A's rows are 16-byte aligned, K is a
-// multiple of 4 (whole 16-byte vectors along k) and each split's K range is a
-// multiple of 32.  Buffer offsets are 32-bit: BM rows of A and one split's K
+// The wave-specialised path applies when A's and B's rows are 16-byte
+// aligned, K and N are multiples of 4 (whole 16-byte vectors along k and n)
+// and each split's K range is a multiple of 32.  Buffer offsets are 32-bit: BM rows of A and one split's K
 // rows of B must each span less than 2^31 bytes.
 static bool fast_ok(const GemmParams &p, int BM, int BN) {
     (void)BN;
-    return p.K % 4 == 0 && p.K > 0 && p.k_per_split % BK == 0 && p.vecA &&
-           ((uintptr_t)p.B % 4 == 0) && ((uintptr_t)p.C % 4 == 0) &&
+    return p.K % 4 == 0 && p.K > 0 && p.N % 4 == 0 && p.k_per_split % BK == 0 && p.vecA &&
+           p.vecB && ((uintptr_t)p.C % 4 == 0) &&
            BM * p.lda * 4 < (int64_t(1) << 31) &&
            p.k_per_split * p.ldb * 4 < (int64_t(1) << 31);
 }

@@ -16,6 +16,8 @@
 // split-K, the hi and lo partial sums.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace bfx {
@@ -71,6 +73,77 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
 template <int V, int BM, int BN>
 constexpr size_t tile_lds_bytes() {
     return 2ull * Prods<V>::P * (BM + BN) * LDK * sizeof(uint16_t);
+}
+
+// The wave-specialised tile additionally keeps, per helper thread, room for
+// its 2*KPT FP32 values (rare exact re-split path; stride padded by one).
+template <int V, int BM, int BN>
+constexpr size_t fast_lds_bytes() {
+    return tile_lds_bytes<V, BM, BN>() + 256ull * (2 * (BM * 32 / 256) + 1) * sizeof(float);
+}
+
+// Epilogue of one MFMA wave's TM x TN block of 16 x 16 tiles.  Output layout
+// of v_mfma_f32_16x16x32_bf16: lane holds column lane%16, rows 4*(lane/16) +
+// 0..3 of each 16 x 16 tile.  X = hi + lo (the largest bin added last), then
+// C = alpha X (beta == 0: C not read) or fma(alpha, X, beta C), or, for
+// split-K, the hi and lo partial sums.  With beta != 0 the C values of a
+// 16-row band are all loaded before the band's first store, so those loads
+// are in flight together instead of each waiting for the previous store.
+template <int TM, int TN>
+__device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32x4 (&hi)[TM][TN],
+                                              const bfx_f32x4 (&lo)[TM][TN], int64_t row0,
+                                              int64_t col0, int kg, int r16, int64_t split) {
+    auto row_of = [&](int i, int e) { return row0 + i * 16 + kg * 4 + e; };
+    auto col_of = [&](int j) { return col0 + j * 16 + r16; };
+    if (p.splits > 1) {
+        const int64_t MN = p.M * p.N;
+        float *base = p.partial + (split * 2) * MN;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t row = row_of(i, e), col = col_of(j);
+                    if (row >= p.M || col >= p.N) continue;
+                    base[row * p.N + col] = hi[i][j][e];
+                    base[MN + row * p.N + col] = lo[i][j][e];
+                }
+        return;
+    }
+    if (p.beta == 0.0f) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t row = row_of(i, e), col = col_of(j);
+                    if (row >= p.M || col >= p.N) continue;
+                    p.C[row * p.ldc + col] = p.alpha * (hi[i][j][e] + lo[i][j][e]);
+                }
+        return;
+    }
+    // one 16-row band at a time: its TN*4 loads in flight together
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        float cv[TN][4];
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row_of(i, e), col = col_of(j);
+                cv[j][e] = (row < p.M && col < p.N) ? p.C[row * p.ldc + col] : 0.0f;
+            }
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row_of(i, e), col = col_of(j);
+                if (row >= p.M || col >= p.N) continue;
+                p.C[row * p.ldc + col] = fmaf(p.alpha, hi[i][j][e] + lo[i][j][e], p.beta * cv[j][e]);
+            }
+    }
 }
 
 // Computes one BM x BN output tile at (m0, n0) over K range [kb, ke).
@@ -228,46 +301,27 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int64_t m0, int64
         }
     }
 
-    // Output layout of v_mfma_f32_16x16x32_bf16: lane holds column lane%16,
-    // rows 4*(lane/16) + 0..3 of the 16x16 tile.
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t row = m0 + wm * TM * 16 + i * 16 + kg * 4 + e;
-                const int64_t col = n0 + wn * TN * 16 + j * 16 + r16;
-                if (row >= p.M || col >= p.N) continue;
-                if (p.splits > 1) {
-                    float *dst = p.partial + (split * 2) * p.M * p.N + row * p.N + col;
-                    dst[0] = hi[i][j][e];
-                    dst[p.M * p.N] = lo[i][j][e];
-                } else {
-                    const float X = hi[i][j][e] + lo[i][j][e];
-                    float *c = p.C + row * p.ldc + col;
-                    *c = (p.beta == 0.0f) ? p.alpha * X : fmaf(p.alpha, X, p.beta * *c);
-                }
-            }
+    tile_epilogue<TM, TN>(p, hi, lo, m0 + wm * TM * 16, n0 + wn * TN * 16, kg, r16, split);
 }
 
 
 // ---------------------------------------------------------------------------
 // Fast path: BM x BN tile (128 x 128 or 64 x 64), 4 MFMA + 4 helper waves.
-// Requirements: A rows 16-byte aligned (A 16-byte aligned, lda % 4 == 0),
-// K % 4 == 0 and the K range of a split a multiple of 32.  M, N and K need
+// Requirements: A and B rows 16-byte aligned (pointers 16-byte aligned, lda
+// and ldb multiples of 4), K % 4 == 0, N % 4 == 0 and the K range of a split
+// a multiple of 32.  M, N and K need
 // not fill the tile: partial tiles are handled by clamped loads whose values
 // are replaced by zeros and by a masked epilogue.  Differences from gemm_tile:
 //   * loads: one thread per A row / B column and BM*32/256 consecutive k
 //     values (16-byte loads of A, coalesced 4-byte loads of B) through buffer
 //     resources, so every LDS store is a conflict-free 16-byte store of 8 BF16
 //     (rows are 80 bytes apart);
-//   * global loads are issued two K-steps ahead (two register stages);
+//   * global loads are issued three (128-wide tiles) or two (64-wide) K-steps
+//     ahead, one register stage per step in flight;
 //   * the split is branch-free (hardware RNE); the rare values for which it is
 //     not exact (Inf/NaN, or a first term that rounds to Inf) are detected from
-//     the first plane and re-split exactly afterwards, outside the MFMA block,
-//     from a second read of global memory, so loads, split and MFMA of one
-//     K-step form a single basic block.
+//     the first plane and the thread's values re-split exactly before its
+//     register stage is reloaded.
 // ---------------------------------------------------------------------------
 
 // Packed BF16 pairs of KPT consecutive values -> P planes x KPT/2 dwords.
@@ -291,13 +345,21 @@ __device__ __forceinline__ bool flag_bad(uint32_t flag) {
     return (flag & 0xffffu) >= 0x7f80u || (flag >> 16) >= 0x7f80u;
 }
 
+// LDS row of B column n (0 <= n < BN) in the wave-specialised tile: inside
+// every aligned group of 16 columns the low two bits are XORed with the group
+// index, so that (a) the 16 columns an MFMA fragment read covers stay in 16
+// distinct rows (conflict-free 16-byte reads, rows 80 bytes apart) and (b)
+// the helpers' stores of column 4c + j (fixed j, c = 0..15) spread over 16
+// row residues as well.
+__device__ __forceinline__ int bcol_row(int n) { return (n & ~3) | ((n & 3) ^ ((n >> 4) & 3)); }
+
 // Wave-specialised aligned tile: 512 threads.  Waves 0-3 (one per SIMD) only
 // read BF16 fragments from LDS, run the MFMAs and write the epilogue; waves
-// 4-7 (one per SIMD) only load FP32 tiles (two K-steps ahead), split them and
+// 4-7 (one per SIMD) only load FP32 tiles (2-3 K-steps ahead), split them and
 // store the planes.  Every SIMD thus runs one wave of each kind and overlaps
 // the split's VALU work with the other wave's matrix work.  Both kinds pass
 // the same barrier once per K-step; the LDS planes are double-buffered.
-template <int V, int BM, int BN>
+template <int V, int BM, int BN, int NST_ = 0>
 __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, int64_t n0,
                                                int64_t kb, int64_t ke, int64_t split,
                                                uint16_t *smem) {
@@ -306,6 +368,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     constexpr int PLANE = (BM + BN) * LDK;
     constexpr int TM = BM / 32, TN = BN / 32;          // 16x16 tiles per MFMA wave (2 x 2 waves)
     constexpr int KPT = BM * BK / 256;                  // k values per helper thread
+    constexpr int NST = NST_ ? NST_ : (BM == 128 ? 3 : 2);  // helper register stages
     static_assert(BM == BN && KPT % 8 == 0, "square tiles with >= 8 k values per helper thread");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int KT = (int)ceil_div(ke - kb, (int64_t)BK);
@@ -322,6 +385,9 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                 lo[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
             }
         const int r16 = lane & 15, kg = lane >> 4;
+        int boff[TN];   // B fragment offsets (elements) inside a plane
+#pragma unroll
+        for (int j = 0; j < TN; ++j) boff[j] = (BM + bcol_row(wn * (BN / 2) + j * 16 + r16)) * LDK + kg * 8;
         for (int s = 0; s < KT; ++s) {
             __syncthreads();  // buffer s&1 holds step s
             const uint16_t *base = smem + (s & 1) * P * PLANE;
@@ -339,8 +405,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                 bfx_bf16x8 bf[TN];
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(
-                        base + jp * PLANE + (BM + wn * (BN / 2) + j * 16 + r16) * LDK + kg * 8);
+                    bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(base + jp * PLANE + boff[j]);
 #pragma unroll
                 for (int q = 0; q < PR::n; ++q) {
                     if (PR::bj[q] != jp) continue;
@@ -362,32 +427,26 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
             }
         }
         __syncthreads();  // matches the helpers' final barrier
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int64_t row = m0 + wm * (BM / 2) + i * 16 + kg * 4 + e;
-                    const int64_t col = n0 + wn * (BN / 2) + j * 16 + r16;
-                    if (row >= p.M || col >= p.N) continue;
-                    if (p.splits > 1) {
-                        float *dst = p.partial + (split * 2) * p.M * p.N + row * p.N + col;
-                        dst[0] = hi[i][j][e];
-                        dst[p.M * p.N] = lo[i][j][e];
-                    } else {
-                        const float X = hi[i][j][e] + lo[i][j][e];
-                        float *c = p.C + row * p.ldc + col;
-                        *c = (p.beta == 0.0f) ? p.alpha * X : fmaf(p.alpha, X, p.beta * *c);
-                    }
-                }
+        tile_epilogue<TM, TN>(p, hi, lo, m0 + wm * (BM / 2), n0 + wn * (BN / 2), kg, r16, split);
         return;
     }
 
     // ------------------------------ helper waves ------------------------------
+    // A: eight lanes cover one row's 32 k (128 bytes) with 16-byte loads, so a
+    //    wave's load touches 8 whole rows (8 cache lines); each thread holds
+    //    4 consecutive k of AR = BM/32 rows (ar0, ar0+32, ...).
+    // B: 16-byte loads of 4 columns; a half-wave covers 64 columns of two k
+    //    rows (BN = 128) or all 64 columns of one k row (BN = 64), so a
+    //    wave's load touches whole 256-byte row segments; each thread holds
+    //    4 columns x RB = BN/32 consecutive k, stored per column (rows
+    //    permuted by bcol_row) as RB BF16 per plane.
+    constexpr int AR = BM / 32;
+    constexpr int RB = BN / 32;
     const int h = tid - 256;
-    const int arow = h % BM, aq = h / BM;   // A row, k group
-    const int bcol = h % BN, bq = h / BN;   // B column, k group
+    const int ar0 = h / 8, ac = h % 8;      // A: first row, 4-k chunk
+    const int hl = h & 63, hw = h >> 6;     // helper lane, helper wave
+    const int bc = (BN == 128) ? (hl & 15) + 16 * (hl >> 5) : (hl & 15);      // column group
+    const int bkq = (BN == 128) ? 2 * hw + ((hl >> 4) & 1) : 4 * hw + (hl >> 4);  // k rows RB*bkq ..
     // Extent of this tile inside the matrices.  `full` (uniform) selects the
     // unmasked code; otherwise every load is clamped to an element inside the
     // tile's range and its value replaced by zero before the split.
@@ -395,7 +454,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     const int cols = (int)((p.N - n0 < BN) ? p.N - n0 : BN);
     const int klen = (int)(ke - kb);
     const bool full = rows == BM && cols == BN && klen % BK == 0;
-    const bool a_ok = arow < rows, b_ok = bcol < cols;
+    const bool b_ok = 4 * bc < cols;        // N % 4 == 0: a vector is valid or not as a whole
     // Buffer resources over exactly the elements of this tile's A rows and B
     // columns (the range check is a second guard; no load leaves the range).
     const int lda = (int)p.lda, ldb = (int)p.ldb;
@@ -403,115 +462,168 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         (void *)(p.A + m0 * p.lda + kb), (short)0, ((rows - 1) * lda + klen) * 4, 0x00020000);
     const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(p.B + kb * p.ldb + n0), (short)0, ((klen - 1) * ldb + cols) * 4, 0x00020000);
-    const int voA = ((a_ok ? arow : 0) * lda + aq * KPT) * 4;
-    const int voB = (bq * KPT * ldb + (b_ok ? bcol : 0)) * 4;
+    int voA[AR];                            // byte offset of (row, k = 0) of each A row
+#pragma unroll
+    for (int i = 0; i < AR; ++i) voA[i] = ((ar0 + 32 * i < rows) ? (ar0 + 32 * i) * lda : 0) * 4;
+    const int voB = (RB * bkq * ldb + (b_ok ? 4 * bc : 0)) * 4;
 
-    float ra[2][KPT], rb[2][KPT];
-    auto issue = [&](int st, int step) {
-        if (full) {
-            const int soA = step * BK * 4;
+    // One instantiation per case, so that each K loop is a single code path
+    // and the compiler's wait counts on the register stages stay exact.
+    auto helpers = [&](auto fullc) {
+        constexpr bool FULL = decltype(fullc)::value;
+        float ra[NST][KPT], rb[NST][KPT];   // ra[.][4i + j]: row ar0+32i, k = 4ac + j
+        auto issue = [&](int st, int step) {
+            if constexpr (FULL) {
+                // per-lane part (row, k chunk) in the VGPR offset, the step in
+                // the uniform SGPR offset
+                const int soA = step * BK * 4;
 #pragma unroll
-            for (int q = 0; q < KPT / 4; ++q) {
-                const bfx_f32x4 v = __builtin_bit_cast(
-                    bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA + 16 * q, soA, 0));
-                ra[st][4 * q] = v[0]; ra[st][4 * q + 1] = v[1]; ra[st][4 * q + 2] = v[2]; ra[st][4 * q + 3] = v[3];
+                for (int i = 0; i < AR; ++i) {
+                    const bfx_f32x4 v = __builtin_bit_cast(
+                        bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[i] + ac * 16, soA, 0));
+                    ra[st][4 * i] = v[0]; ra[st][4 * i + 1] = v[1]; ra[st][4 * i + 2] = v[2]; ra[st][4 * i + 3] = v[3];
+                }
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {
+                    const bfx_f32x4 v = __builtin_bit_cast(
+                        bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rB, voB, (step * BK + i) * ldb * 4, 0));
+                    rb[st][4 * i] = v[0]; rb[st][4 * i + 1] = v[1]; rb[st][4 * i + 2] = v[2]; rb[st][4 * i + 3] = v[3];
+                }
+            } else {
+                // k beyond the range: read k = 0 of the same row / column instead
+                const int kA = step * BK + ac * 4;
+                const int dA = (kA < klen) ? kA * 4 : 0;
+#pragma unroll
+                for (int i = 0; i < AR; ++i) {
+                    const bfx_f32x4 v = __builtin_bit_cast(
+                        bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[i] + dA, 0, 0));
+                    ra[st][4 * i] = v[0]; ra[st][4 * i + 1] = v[1]; ra[st][4 * i + 2] = v[2]; ra[st][4 * i + 3] = v[3];
+                }
+                const int kB = step * BK + RB * bkq;
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {
+                    const int off = (kB + i < klen) ? voB + (step * BK + i) * ldb * 4 : voB - RB * bkq * ldb * 4;
+                    const bfx_f32x4 v = __builtin_bit_cast(
+                        bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rB, off, 0, 0));
+                    rb[st][4 * i] = v[0]; rb[st][4 * i + 1] = v[1]; rb[st][4 * i + 2] = v[2]; rb[st][4 * i + 3] = v[3];
+                }
             }
-            const int soB = step * BK * ldb * 4;
+        };
+        // Zeros for the values outside the tile (partial tiles only).
+        auto mask = [&](int st, int step) {
+            const bool kA_ok = step * BK + ac * 4 < klen;
+            const int kB = step * BK + RB * bkq;
 #pragma unroll
-            for (int j = 0; j < KPT; ++j)
-                rb[st][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, voB, soB + j * ldb * 4, 0));
-        } else {
-            // k beyond the range: read k = 0 of the same row / column instead
-            const int k0 = step * BK + aq * KPT;
+            for (int i = 0; i < AR; ++i) {
+                const bool ok = kA_ok && ar0 + 32 * i < rows;
 #pragma unroll
-            for (int q = 0; q < KPT / 4; ++q) {
-                const int off = (k0 + 4 * q < klen) ? voA + (step * BK + 4 * q) * 4 : voA - aq * KPT * 4;
-                const bfx_f32x4 v = __builtin_bit_cast(
-                    bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rA, off, 0, 0));
-                ra[st][4 * q] = v[0]; ra[st][4 * q + 1] = v[1]; ra[st][4 * q + 2] = v[2]; ra[st][4 * q + 3] = v[3];
+                for (int j = 0; j < 4; ++j)
+                    if (!ok) ra[st][4 * i + j] = 0.0f;
             }
-            const int kB = step * BK + bq * KPT;
 #pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                const int off = (kB + j < klen) ? voB + (step * BK + j) * ldb * 4 : voB - bq * KPT * ldb * 4;
-                rb[st][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, off, 0, 0));
+            for (int i = 0; i < RB; ++i) {
+                const bool ok = b_ok && kB + i < klen;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (!ok) rb[st][4 * i + j] = 0.0f;
             }
-        }
-    };
-    // Zeros for the values outside the tile (partial tiles only).
-    auto mask = [&](int st, int step) {
-        const int k0 = step * BK + aq * KPT, kB = step * BK + bq * KPT;
+        };
+        auto stage = [&](int st, int buf, int step) {
+            if constexpr (!FULL) mask(st, step);
+            uint16_t *base = smem + buf * P * PLANE;
+            uint32_t flag = 0, pa[3][KPT / 2], pb[3][KPT / 2];
+            float bt[KPT];   // B values column by column: bt[RB * j + i] = k row i, column j
 #pragma unroll
-        for (int q = 0; q < KPT; ++q) {
-            if (!a_ok || k0 + q >= klen) ra[st][q] = 0.0f;
-            if (!b_ok || kB + q >= klen) rb[st][q] = 0.0f;
-        }
-    };
-    auto put = [&](uint16_t *base, int row, int kg0, const uint32_t pl8[][KPT / 2]) {
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int pl = 0; pl < P; ++pl) {
-            uint16_t *d = base + pl * PLANE + row * LDK + kg0 * KPT;
+                for (int i = 0; i < RB; ++i) bt[RB * j + i] = rb[st][4 * i + j];
+            split_run_fast<P, KPT>(ra[st], pa, flag);
+            split_run_fast<P, KPT>(bt, pb, flag);
 #pragma unroll
-            for (int c = 0; c < KPT / 8; ++c)
-                *reinterpret_cast<uint4 *>(d + 8 * c) =
-                    make_uint4(pl8[pl][4 * c], pl8[pl][4 * c + 1], pl8[pl][4 * c + 2], pl8[pl][4 * c + 3]);
-        }
-    };
-    auto stage = [&](int st, int buf, int step) {
-        if (!full) mask(st, step);
-        uint16_t *base = smem + buf * P * PLANE;
-        uint32_t flag = 0, pa[3][KPT / 2], pb[3][KPT / 2];
-        split_run_fast<P, KPT>(ra[st], pa, flag);
-        split_run_fast<P, KPT>(rb[st], pb, flag);
-        put(base, arow, aq, pa);
-        put(base, BM + bcol, bq, pb);
-        return flag;
-    };
-    // Rare path: re-read this thread's values of K-step `step` (still in L2)
-    // and split them exactly, one BF16 store at a time.
-    auto fixup = [&](int step, int buf) {
-        uint16_t *base = smem + buf * P * PLANE;
+            for (int pl = 0; pl < P; ++pl) {
+                // A: 4 BF16 (8 bytes) per row
+#pragma unroll
+                for (int i = 0; i < AR; ++i)
+                    *reinterpret_cast<uint2 *>(base + pl * PLANE + (ar0 + 32 * i) * LDK + ac * 4) =
+                        make_uint2(pa[pl][2 * i], pa[pl][2 * i + 1]);
+                // B: RB BF16 of each of the 4 columns
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint16_t *d = base + pl * PLANE + (BM + bcol_row(4 * bc + j)) * LDK + RB * bkq;
+                    if constexpr (RB == 4)
+                        *reinterpret_cast<uint2 *>(d) = make_uint2(pb[pl][2 * j], pb[pl][2 * j + 1]);
+                    else
+                        *reinterpret_cast<uint32_t *>(d) = pb[pl][j];
+                }
+            }
+            return flag;
+        };
+        // Rare path: split this thread's values exactly, one BF16 store at a time.
+        // The values still sit in the register stage (masked); they go through a
+        // per-thread LDS area so that the loop below indexes memory, not
+        // registers.  It runs before the stage is reloaded and issues no global
+        // load, so the prefetch accounting of the common path is unaffected.
+        float *raw = reinterpret_cast<float *>(smem + 2 * P * PLANE) + h * (2 * KPT + 1);
+        auto fixup = [&](int st, int buf) {
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                raw[q] = ra[st][q];
+                raw[KPT + q] = rb[st][q];
+            }
+            uint16_t *base = smem + buf * P * PLANE;
 #pragma unroll 1
-        for (int e = 0; e < 2 * KPT; ++e) {
-            const bool isA = e < KPT;
-            const int q = isA ? e : e - KPT;
-            const int k = (isA ? aq : bq) * KPT + q;
-            const bool in = (isA ? a_ok : b_ok) && step * BK + k < klen;
-            const uint32_t bits = !in ? 0u
-                : isA ? __builtin_amdgcn_raw_buffer_load_b32(rA, voA + 4 * q, step * BK * 4, 0)
-                      : __builtin_amdgcn_raw_buffer_load_b32(rB, voB, (step * BK + q) * ldb * 4, 0);
-            uint32_t hh[3];
-            split3_exact(__builtin_bit_cast(float, bits), hh[0], hh[1], hh[2]);
-            const int row = isA ? arow : BM + bcol;
+            for (int e = 0; e < 2 * KPT; ++e) {
+                const bool isA = e < KPT;
+                const int q = e - KPT;   // B: q = 4 i + j, k row RB*bkq + i, column 4 bc + j
+                const int row = isA ? ar0 + 32 * (e / 4) : BM + bcol_row(4 * bc + (q & 3));
+                const int k = isA ? ac * 4 + (e % 4) : RB * bkq + (q >> 2);
+                uint32_t hh[3];
+                split3_exact(raw[e], hh[0], hh[1], hh[2]);
 #pragma unroll
-            for (int pl = 0; pl < P; ++pl) base[pl * PLANE + row * LDK + k] = (uint16_t)hh[pl];
+                for (int pl = 0; pl < P; ++pl) base[pl * PLANE + row * LDK + k] = (uint16_t)hh[pl];
+            }
+        };
+        // Barrier t starts MFMA step t (buffer t&1).  Between barriers t and
+        // t+1 the helpers split step t+1 into buffer (t+1)&1 and reload the
+        // register stage they just emptied with step t+1+NST: step s lives in
+        // stage s % NST, loaded NST K-steps before it is split (NST = 3 for
+        // 128-wide tiles, 2 for 64-wide ones, whose register budget allows two
+        // workgroups per CU).  The steady-state loop has no conditional
+        // loads, so every stage is consumed exactly NST-1 full stages behind
+        // the newest loads.
+        if (KT > 0) {
+            const int last = KT - 1;
+            auto lim = [&](int s) { return s < last ? s : last; };
+            auto step_of = [&](int st, int s) {
+                const uint32_t f = stage(st, s & 1, s);
+                if (flag_bad(f)) fixup(st, s & 1);
+            };
+#pragma unroll
+            for (int st = 0; st < NST; ++st) issue(st, lim(st));
+            step_of(0, 0);
+            issue(0, lim(NST));
+            int t = 0;
+            for (; t + NST < KT; t += NST) {
+#pragma unroll
+                for (int u = 1; u <= NST; ++u) {
+                    __syncthreads();
+                    step_of(u % NST, t + u);
+                    issue(u % NST, lim(t + u + NST));
+                }
+            }
+            // t % NST == 0 and t + NST >= KT: steps t+1 .. KT-1 remain
+#pragma unroll
+            for (int u = 1; u < NST; ++u) {
+                if (t + u < KT) {
+                    __syncthreads();
+                    step_of(u, t + u);
+                }
+            }
+            __syncthreads();    // barrier KT-1
         }
     };
-    // Step t+1 is split into buffer (t+1)&1 while the MFMA waves work on step
-    // t; its registers then receive the loads of step t+3.
-#define BFX_HELPER_STEP(t, SP)                                             \
-    {                                                                      \
-        __syncthreads();                                                   \
-        if ((t) + 1 < KT) {                                                \
-            const uint32_t flag = stage(SP, ((t) + 1) & 1, (t) + 1);       \
-            issue(SP, ((t) + 3 < KT) ? (t) + 3 : KT - 1);                  \
-            if (flag_bad(flag)) fixup((t) + 1, ((t) + 1) & 1);             \
-        }                                                                  \
-    }
-    if (KT > 0) {
-        issue(0, 0);
-        issue(1, KT > 1 ? 1 : KT - 1);
-        const uint32_t flag = stage(0, 0, 0);
-        issue(0, KT > 2 ? 2 : KT - 1);
-        if (flag_bad(flag)) fixup(0, 0);
-        int s = 0;
-        for (; s + 1 < KT; s += 2) {
-            BFX_HELPER_STEP(s, 1);
-            BFX_HELPER_STEP(s + 1, 0);
-        }
-        if (s < KT) BFX_HELPER_STEP(s, 1);
-    }
-#undef BFX_HELPER_STEP
+    if (full) helpers(std::true_type{});
+    else helpers(std::false_type{});
     __syncthreads();
 }
 

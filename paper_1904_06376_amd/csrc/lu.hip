@@ -66,20 +66,26 @@ struct PanelArgs {
 };
 }  // namespace
 
+// LDS row stride of the panel: a multiple of 4 floats (16-byte row updates)
+// with an odd number of 16-byte chunks, so that the 16 lanes of a 16-byte
+// access phase hit distinct banks.
+__host__ __device__ constexpr int panel_ld(int w) { return 4 * (((w + 3) / 4) | 1); }
+
 __device__ __forceinline__ void better(float &v, int &i, float v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
 
 __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
-    extern __shared__ float P[];  // [PROWS][w + 1]
-    __shared__ float U[PNB], D[PNB];
+    extern __shared__ __align__(16) float P[];  // [PROWS][panel_ld(w)]
+    __shared__ __align__(16) float U[PNB];
+    __shared__ __align__(16) float D[PNB];
     __shared__ float red_v[PROWS / 64];
     __shared__ int red_i[PROWS / 64];
     __shared__ int s_piv, s_win;
     __shared__ float s_val;
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int w = a.w, ld = w + 1;
+    const int w = a.w, ld = panel_ld(w);
     const int64_t row0 = (int64_t)g * PROWS;      // first panel row of this workgroup
     const int64_t pr = row0 + t;                   // panel row owned by this thread
     const bool own = pr < a.m;
@@ -113,18 +119,21 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
             s_piv = (bv >= 0.0f) ? bi : -1;
         }
         __syncthreads();
-        // ---- publish the candidate row (and row c, by its owner), then the header
-        if (s_piv >= 0 && t < w)
-            a.ws.slot_row[(par * MAX_G + g) * PNB + t] = P[(s_piv - row0) * ld + t];
-        if (t == 0) a.ws.slot_idx[par * MAX_G + g] = s_piv;
-        if (c >= row0 && c < row0 + PROWS && t < w)
-            a.ws.diag_row[par * PNB + t] = P[(c - row0) * ld + t];
-        __threadfence();
-        __syncthreads();
-        if (t == 0) {
-            const uint64_t h = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(s_val);
-            __hip_atomic_store(&a.ws.hdr[par * MAX_G + g], h, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        // ---- wave 0 publishes the candidate row (and row c, by its owner),
+        // then the header with release order (covering the wave's own stores)
+        if (wave == 0) {
+            const bool has_c = c >= row0 && c < row0 + PROWS;
+            for (int q = lane; q < w; q += 64) {
+                if (s_piv >= 0) a.ws.slot_row[(par * MAX_G + g) * PNB + q] = P[(s_piv - row0) * ld + q];
+                if (has_c) a.ws.diag_row[par * PNB + q] = P[(c - row0) * ld + q];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                a.ws.slot_idx[par * MAX_G + g] = s_piv;
+                const uint64_t h = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(s_val);
+                __hip_atomic_store(&a.ws.hdr[par * MAX_G + g], h, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         // ---- every wave polls 64 of the G headers (bounded wait), then the
         // largest candidate wins, the lowest workgroup on ties
@@ -138,7 +147,12 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
                 for (;;) {
                     h = __hip_atomic_load(&a.ws.hdr[par * MAX_G + k], __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-                    if ((uint32_t)(h >> 32) == tag) break;
+                    if ((uint32_t)(h >> 32) == tag) {
+                        // acquire: the candidate rows published before it are visible
+                        (void)__hip_atomic_load(&a.ws.hdr[par * MAX_G + k], __ATOMIC_ACQUIRE,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
                     if (__hip_atomic_load(a.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) break;
                     if (++spins > SPIN_LIMIT) {
                         __hip_atomic_store(a.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -157,7 +171,6 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
             if (lane == 0) { red_v[wave] = bv; red_i[wave] = bg; }
         }
         __syncthreads();
-        __threadfence();
         if (t == 0) {
             float bv = red_v[0];
             int bg = red_i[0];
@@ -185,15 +198,37 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
         // ---- swap rows c and p, divide, rank-1 update of the own row
         if (own) {
             float *row = P + t * ld;
-            if (pr == p && p != c)
-                for (int q = 0; q < w; ++q) row[q] = D[q];
-            if (pr == c)
-                for (int q = 0; q < w; ++q) row[q] = U[q];
+            float4 *r4 = reinterpret_cast<float4 *>(row);
+            const int w4 = (w + 3) >> 2;   // 16-byte groups (padding columns are never stored)
+            if (pr == p && p != c) {
+                const float4 *d4 = reinterpret_cast<const float4 *>(D);
+#pragma unroll 8
+                for (int g4 = 0; g4 < w4; ++g4) r4[g4] = d4[g4];
+            }
+            if (pr == c) {
+                const float4 *u4 = reinterpret_cast<const float4 *>(U);
+#pragma unroll 8
+                for (int g4 = 0; g4 < w4; ++g4) r4[g4] = u4[g4];
+            }
             if (pr > c) {
                 float l = row[c];
                 if (piv != 0.0f) l = l / piv;
                 row[c] = l;
-                for (int q = c + 1; q < w; ++q) row[q] = fmaf(-l, U[q], row[q]);
+                // columns c+1 .. w-1 in 16-byte groups from the group holding
+                // c+1 (columns <= c of that group are kept; the padding
+                // columns up to the next multiple of 4 are never stored)
+                const float4 *u4 = reinterpret_cast<const float4 *>(U);
+#pragma unroll 4
+                for (int g4 = (c + 1) >> 2; g4 < w4; ++g4) {
+                    const float4 u = u4[g4];
+                    float4 r = r4[g4];
+                    const int q = 4 * g4;
+                    r.x = (q > c) ? fmaf(-l, u.x, r.x) : r.x;
+                    r.y = (q + 1 > c) ? fmaf(-l, u.y, r.y) : r.y;
+                    r.z = (q + 2 > c) ? fmaf(-l, u.z, r.z) : r.z;
+                    r.w = (q + 3 > c) ? fmaf(-l, u.w, r.w) : r.w;
+                    r4[g4] = r;
+                }
             }
         }
         __syncthreads();
@@ -300,7 +335,7 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
     if (!attr) {
         BFX_HIP(hipFuncSetAttribute((const void *)panel_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    PROWS * (PNB + 1) * (int)sizeof(float)));
+                                    PROWS * panel_ld(PNB) * (int)sizeof(float)));
         BFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (PNB * PNB + PNB * (TRSM_COLS + 1)) * (int)sizeof(float)));
@@ -318,7 +353,7 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         pa.G = (int)ceil_div(n - j, PROWS);
         pa.ipiv = ipiv; pa.info = info; pa.ws = w;
         void *args[] = {&pa};
-        const size_t lds = (size_t)PROWS * (jb + 1) * sizeof(float);
+        const size_t lds = (size_t)PROWS * panel_ld(jb) * sizeof(float);
         BFX_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(pa.G), dim3(PROWS),
                                            args, (unsigned)lds, s));
         const int64_t others = n - jb;

@@ -5,6 +5,7 @@
     python paper_1904_06376_amd/run_workload.py lu     --n 16384 --kappa 1e4
     python paper_1904_06376_amd/run_workload.py batched-gemm --count 4096 --reps 3
     python paper_1904_06376_amd/run_workload.py batched-solve --count 512 --reps 2
+    python paper_1904_06376_amd/run_workload.py lu-update --n 16384 --reps 5
 
 Inputs are the seeded synthetic workloads of the benchmark; nothing is timed
 here except a one-line summary printed at the end.
@@ -21,7 +22,8 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["gemm", "splitk", "lu", "batched-gemm", "batched-solve"])
+    ap.add_argument("workload", choices=["gemm", "splitk", "lu", "batched-gemm", "batched-solve",
+                                            "lu-update"])
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--variant", type=int, default=6)
     ap.add_argument("--reps", type=int, default=3)
@@ -54,6 +56,22 @@ def main():
             LU = A.clone()
             _, ipiv, info = bfx.lu_factor(LU, a.variant)
             x, res = bfx.ir_solve(A, LU, ipiv, b)
+    elif a.workload == "lu-update":
+        # the first trailing update of an n x n LU: A22 -= L21 x U12, K = 128,
+        # all three operands strided views of one n x n matrix
+        M = torch.from_numpy(workloads.normal((a.n, a.n), 102)).to(dev)
+        L21, U12, A22 = M[128:, :128], M[:128, 128:], M[128:, 128:]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * a.reps)]
+        for r in range(a.reps):
+            ev[2 * r].record()
+            bfx.gemm(a.variant, L21, U12, A22, alpha=-1.0, beta=1.0)
+            ev[2 * r + 1].record()
+        torch.cuda.synchronize()
+        ms = [ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(a.reps)]
+        m = a.n - 128
+        print(f"lu-update {m}x{m}x128: " + " ".join(f"{x:.3f}" for x in ms) + " ms; "
+              f"{a.variant * 2.0 * m * m * 128 / (min(ms) * 1e-3) / 1e12:.0f} TFLOP/s BF16, "
+              f"{8.0 * m * m / (min(ms) * 1e-3) / 1e9:.0f} GB/s of C", flush=True)
     elif a.workload == "batched-gemm":
         shapes, probs = workloads.batched_problems(a.count, 0)
         tens = [(torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev),

@@ -13,11 +13,13 @@ from tests.gpu_util import absref, dev, gemm_bound, host, ref64
 
 pytestmark = pytest.mark.gpu
 
-# K % 4 == 0 with 16-byte aligned rows takes the wave-specialised engine
-# (partial tiles masked); the other shapes the general engine.
+# K % 4 == 0 and N % 4 == 0 with 16-byte aligned rows take the
+# wave-specialised engine (partial tiles masked); the other shapes the general
+# engine.
 SHAPES = [(256, 256, 256), (200, 130, 77), (129, 257, 33), (17, 300, 5), (1, 1, 1),
-          (64, 64, 1000), (300, 40, 600), (3, 5, 4096), (130, 130, 128),
-          (200, 130, 96), (129, 257, 36), (1, 1, 4), (65, 63, 44), (127, 129, 1028)]
+          (64, 64, 1000), (300, 40, 600), (3, 5, 4096), (130, 132, 128),
+          (200, 132, 96), (129, 256, 36), (1, 4, 4), (65, 64, 44), (127, 128, 1028),
+          (200, 130, 96), (65, 63, 44)]
 
 
 def _check_bound(variant, A, B, C, Corc=None, alpha=1.0):
@@ -119,16 +121,19 @@ def test_gemm_nonfinite_pattern(bfx, orc):
 
 
 @pytest.mark.parametrize("variant", [1, 3, 6, 9])
-def test_gemm_fast_path_nonfinite_and_saturating(bfx, orc, variant):
-    """128-aligned shapes take the branch-free fast path; values whose first
-    BF16 term would be Inf/NaN are re-split exactly out of band."""
-    A = workloads.uniform((256, 128), 14)
-    B = workloads.uniform((128, 256), 15)
+@pytest.mark.parametrize("shape", [(256, 128, 256), (200, 132, 72)])
+def test_gemm_fast_path_nonfinite_and_saturating(bfx, orc, variant, shape):
+    """Shapes the wave-specialised engine takes (full and partial tiles):
+    values whose first BF16 term would be Inf/NaN are re-split exactly out
+    of band."""
+    M, K, N = shape
+    A = workloads.uniform((M, K), 14)
+    B = workloads.uniform((K, N), 15)
     A[5, 3] = np.inf
-    A[200, 100] = -np.inf
-    B[64, 77] = np.nan
+    A[M - 56, K - 28] = -np.inf
+    B[64, N - 3] = np.nan
     A[130, 31] = 3.3e38      # rounds past the largest BF16: saturating split
-    B[127, 255] = -3.39e38
+    B[K - 1, N - 1] = -3.39e38
     C = host(bfx.gemm(variant, dev(A), dev(B)))
     Co = orc.gemm(variant, A, B)
     np.testing.assert_array_equal(np.isfinite(C), np.isfinite(Co))
@@ -137,7 +142,7 @@ def test_gemm_fast_path_nonfinite_and_saturating(bfx, orc, variant):
     A2 = np.where(np.isfinite(A), A, 0).astype(np.float32)
     B2 = np.where(np.isfinite(B), B, 0).astype(np.float32)
     zh = absref(A2, B2)
-    bnd = gemm_bound(variant, 128) * zh + 1e-30
+    bnd = gemm_bound(variant, K) * zh + 1e-30
     assert np.all(np.abs(C[fin] - Co[fin]) <= 2 * bnd[fin])
 
 
@@ -161,7 +166,7 @@ def test_gemm_partial_tiles_fast_vs_general(bfx, orc, variant):
     """Partial tiles through the wave-specialised engine (masked loads and
     epilogue) and through the general engine: both within the bound."""
     A = workloads.normal((200, 132), 18)
-    B = workloads.normal((132, 70), 19)
+    B = workloads.normal((132, 72), 19)
     Cf = host(bfx.gemm(variant, dev(A), dev(B)))
     tA = dev(np.pad(A, ((0, 0), (0, 1))))[:, :132]
     Cg = host(bfx.gemm(variant, tA, dev(B)))
@@ -171,10 +176,10 @@ def test_gemm_partial_tiles_fast_vs_general(bfx, orc, variant):
     assert np.all(np.abs(Cf - Cg) <= 2 * bnd)
     # the masked region of C is untouched: write into a larger buffer
     big = torch.full((210, 80), 7.0, dtype=torch.float32, device="cuda")
-    bfx.gemm(variant, dev(A), dev(B), big[:200, :70])
+    bfx.gemm(variant, dev(A), dev(B), big[:200, :72])
     hb = host(big)
-    assert np.all(hb[200:] == 7.0) and np.all(hb[:, 70:] == 7.0)
-    np.testing.assert_array_equal(hb[:200, :70], Cf)
+    assert np.all(hb[200:] == 7.0) and np.all(hb[:, 72:] == 7.0)
+    np.testing.assert_array_equal(hb[:200, :72], Cf)
 
 
 def test_gemm_K0(bfx):
