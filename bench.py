@@ -82,7 +82,7 @@ def time_launches(torch, fn, reps, stream):
     return float(np.mean(ts)), float(np.median(ts))
 
 
-def sampled_errors(orc, A, B, C, variant, nsample=256, seed=0):
+def sampled_errors(A, B, C, variant, nsample=256, seed=0):
     g = np.random.default_rng(seed)
     r = g.integers(0, A.shape[0], nsample)
     c = g.integers(0, B.shape[1], nsample)
@@ -166,12 +166,43 @@ def main():
                 "traffic": measured_traffic(), "kernel": "gemm_fast_kernel<6,128,128>",
                 "algorithmic_flop_per_launch": bf16_flop, "avg_launch_ms": round(avg_ms, 4)}
 
-    import oracle as orc
     C6 = tC.cpu().numpy()
-    errors = {"x6": sampled_errors(orc, A, B, C6, 6)}
+    errors = {"x6": sampled_errors(A, B, C6, 6)}
 
     extras = {}
     if not args.skip_extras:
+        # 256^3, U[-1,1]: split of all 131072 inputs against the oracle, and the
+        # mean relative Frobenius error over 100 seeds per variant (Fig. 2 style)
+        small = {}
+        Ssplit = np.concatenate([workloads.uniform((256, 256), 0).ravel(),
+                                 workloads.uniform((256, 256), 1).ravel()])
+        planes = [x.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+                  for x in bfx.split(torch.from_numpy(Ssplit).to(dev), 3)]
+        total = sum(pl.view(np.float32).astype(np.float64) for pl in planes)
+        small["split_131072_sum_exact"] = bool(np.array_equal(total, Ssplit.astype(np.float64)))
+        rel = {k: [] for k in ("x3", "x6", "x9", "fp32_vector")}
+        tS1 = torch.empty((256, 256), dtype=torch.float32, device=dev)
+        for seed in range(100):
+            A1 = workloads.uniform((256, 256), 2 * seed)
+            B1 = workloads.uniform((256, 256), 2 * seed + 1)
+            z = A1.astype(np.float64) @ B1.astype(np.float64)
+            tA1, tB1 = torch.from_numpy(A1).to(dev), torch.from_numpy(B1).to(dev)
+            for v in (3, 6, 9, 0):
+                if v:
+                    bfx.gemm(v, tA1, tB1, tS1)
+                else:
+                    bfx.sgemm_fp32(tA1, tB1, tS1)
+                c1 = tS1.cpu().numpy().astype(np.float64)
+                rel["fp32_vector" if v == 0 else f"x{v}"].append(np.linalg.norm(c1 - z) / np.linalg.norm(z))
+        small["mean_rel_frobenius_100_seeds"] = {k: float(np.mean(vv)) for k, vv in rel.items()}
+        us = {}
+        for v in (3, 6, 9):
+            ms, _ = time_launches(torch, lambda: bfx.gemm(v, tA1, tB1, tS1), 20, stream)
+            us[f"x{v}"] = round(ms * 1e3, 1)
+        small["launch_us"] = us
+        extras["gemm_256"] = small
+        log(f"[bench] 256^3 {small}")
+
         variants = {}
         for v in (3, 9):
             for _ in range(2):
@@ -179,18 +210,18 @@ def main():
             ms, _ = time_launches(torch, lambda: step(v), 5, stream)
             variants[f"x{v}"] = {"ms": round(ms, 3), "tflops_fp32eq": round(flop / ms / 1e9, 2),
                                  "tflops_bf16": round(v * flop / ms / 1e9, 2)}
-            errors[f"x{v}"] = sampled_errors(orc, A, B, tC.cpu().numpy(), v)
+            errors[f"x{v}"] = sampled_errors(A, B, tC.cpu().numpy(), v)
         variants["x6"] = {"ms": round(avg_ms, 3), "tflops_fp32eq": round(flop / avg_ms / 1e9, 2),
                           "tflops_bf16": round(achieved, 2)}
         # FP32 comparators
         tS = torch.empty_like(tC)
         bfx.sgemm_fp32(tA, tB, tS)
         ms_s, _ = time_launches(torch, lambda: bfx.sgemm_fp32(tA, tB, tS), 3, stream)
-        errors["fp32_vector"] = sampled_errors(orc, A, B, tS.cpu().numpy(), 0)
+        errors["fp32_vector"] = sampled_errors(A, B, tS.cpu().numpy(), 0)
         torch.backends.cuda.matmul.allow_tf32 = False
         torch.matmul(tA, tB, out=tS)
         ms_t, _ = time_launches(torch, lambda: torch.matmul(tA, tB, out=tS), 5, stream)
-        errors["torch_fp32"] = sampled_errors(orc, A, B, tS.cpu().numpy(), 0)
+        errors["torch_fp32"] = sampled_errors(A, B, tS.cpu().numpy(), 0)
         extras["variants"] = variants
         extras["fp32_vector_gemm"] = {"ms": round(ms_s, 3), "tflops": round(flop / ms_s / 1e9, 2)}
         extras["torch_fp32_matmul"] = {"ms": round(ms_t, 3), "tflops": round(flop / ms_t / 1e9, 2)}
@@ -207,9 +238,9 @@ def main():
         wide_err = {}
         for v in (3, 6, 9):
             bfx.gemm(v, tW1, tW2, tC)
-            wide_err[f"x{v}"] = sampled_errors(orc, W1, W2, tC.cpu().numpy(), v)
+            wide_err[f"x{v}"] = sampled_errors(W1, W2, tC.cpu().numpy(), v)
         torch.matmul(tW1, tW2, out=tC)
-        wide_err["torch_fp32"] = sampled_errors(orc, W1, W2, tC.cpu().numpy(), 0)
+        wide_err["torch_fp32"] = sampled_errors(W1, W2, tC.cpu().numpy(), 0)
         extras["errors_wide"] = wide_err
         del tW1, tW2, W1, W2
 
@@ -293,6 +324,7 @@ def main():
         log(f"[bench] batched solves {extras['batched_solves_512']}")
 
     # ---------------- CPU baseline: the oracle on a row sample ----------------
+    import oracle as orc
     cores = orc.num_threads()
     rows = 2
     t0 = time.perf_counter()
@@ -345,7 +377,7 @@ def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
                "lu_ir": {"ms": round(t_ir * 1e3, 2), "iters": r["iters"], "status": r["status"],
                          "eta": r["eta"], "solves_per_s": round(1.0 / (t_lu + t_ir), 3)}}
         if kappa >= 1e8:
-            budget = dict(max_iter=3, restart=60) if kappa >= 1e12 else dict(max_iter=10, restart=50)
+            budget = dict(max_iter=2, restart=120) if kappa >= 1e12 else dict(max_iter=4, restart=120)
             t0 = time.perf_counter()
             xg, g = bfx.gmres_ir_solve(A, LU, ipiv, b, **budget)
             torch.cuda.synchronize()

@@ -7,6 +7,10 @@ import fails with an error that says so.
 import ctypes
 import os
 
+# torch first: its HIP runtime is then the one libbfx.so binds to, so that
+# device memory allocated by torch and by the library share one runtime.
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbfx.so")
 

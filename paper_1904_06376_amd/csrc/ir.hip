@@ -220,12 +220,28 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
     // L, descending for U).  A block only completes after every block before
     // it in that order, so one acquire of a flag covers all earlier blocks and
     // thread 0 waits only when the next block is not yet known complete.
+    // The factor values of the next dependency are loaded before waiting for
+    // it (they do not depend on the solve), so only the solution values are
+    // fetched after a completion flag is seen.
     const int rr = t >> 2, sub = t & 3;
     T acc = 0;
     const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
+    const float *lrow = LU + (r0 + (rr < rows ? rr : 0)) * ld;
+    auto col0 = [&](int64_t d) { return (lower ? d : nblk - 1 - d) * TB + sub * 16; };
+    float lc[16], ln[16];
+    if (nb_dep > 0) {
+        const int64_t c1 = col0(0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lc[k] = (c1 + k < n) ? lrow[c1 + k] : 0.0f;
+    }
     int64_t known = 0;  // dependencies known complete
     for (int64_t d = 0; d < nb_dep; ++d) {
         const int64_t jb = lower ? d : nblk - 1 - d;
+        if (d + 1 < nb_dep) {
+            const int64_t c1 = col0(d + 1);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) ln[k] = (c1 + k < n) ? lrow[c1 + k] : 0.0f;
+        }
         if (d >= known) {
             if (t == 0) {
                 unsigned spins = 0;
@@ -251,11 +267,12 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
         }
         const int64_t c0 = jb * TB + sub * 16;
         if (rr < rows) {
-            const float *lrow = LU + (r0 + rr) * ld;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (c0 + k < n) acc = fma((T)lrow[c0 + k], y[c0 + k], acc);
+                if (c0 + k < n) acc = fma((T)lc[k], y[c0 + k], acc);
         }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lc[k] = ln[k];
     }
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);

@@ -277,7 +277,9 @@ laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *
     int64_t col = (int64_t)blockIdx.x * SWP_COLS + l;
     if (col >= j) col += w;
     if (col >= n) return;
+#pragma unroll 8
     for (int i = 0; i < w; ++i) T[i * SWP_COLS + l] = A[(j + i) * lda + col];
+#pragma unroll 8
     for (int i = 0; i < w; ++i)
         if (slot[i] == w + i) T[(w + i) * SWP_COLS + l] = A[(j + sp[i]) * lda + col];
     for (int i = 0; i < w; ++i) {
@@ -288,6 +290,7 @@ laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *
             T[q * SWP_COLS + l] = x;
         }
     }
+#pragma unroll 8
     for (int i = 0; i < w; ++i) A[(j + i) * lda + col] = T[i * SWP_COLS + l];
     for (int i = 0; i < w; ++i)
         if (slot[i] == w + i) A[(j + sp[i]) * lda + col] = T[(w + i) * SWP_COLS + l];
@@ -318,6 +321,8 @@ trsm_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w) {
         for (int i = 1; i < w; ++i) {
             float s = X[i * XLD + t];
             const float *li = L + i * PNB;
+            // one FMA chain in increasing p; the LDS reads run ahead of it
+#pragma unroll 8
             for (int p = 0; p < i; ++p) s = fmaf(-li[p], X[p * XLD + t], s);
             X[i * XLD + t] = s;
         }
