@@ -14,7 +14,7 @@
 //   2. laswp_kernel  - the panel's row interchanges applied to the columns
 //      left and right of the panel (rows staged in LDS, swaps replayed there).
 //   3. trsm_kernel   - U12 = L11^{-1} A12 (unit lower, FP32 FMA chains in
-//      index order, one thread per column, L11 in LDS).
+//      index order; column-oriented steps over register-resident rows).
 //   4. A22 -= L21 x U12 with the split-BF16 GEMM (alpha = -1, beta = 1).
 #include <climits>
 
@@ -24,7 +24,7 @@ namespace bfx {
 
 namespace {
 constexpr int PNB = 128;     // panel width
-constexpr int PROWS = 256;   // panel rows per workgroup (= threads)
+constexpr int PROWS = 512;   // panel rows per workgroup (= threads, one row each in registers)
 constexpr int MAX_G = 256;   // co-resident workgroups the panel may use
 constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
 
@@ -75,33 +75,38 @@ __device__ __forceinline__ void better(float &v, int &i, float v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
 }
 
-__global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
-    extern __shared__ __align__(16) float P[];  // [PROWS][panel_ld(w)]
-    __shared__ __align__(16) float U[PNB];
-    __shared__ __align__(16) float D[PNB];
+// Each thread holds one panel row in registers, r[0..PNB-1], in a layout
+// that keeps the current column in r[0]: after k eliminations (k = the
+// column index for rows still below the diagonal) r[0 .. w-k-1] hold columns
+// k .. w-1, r[PNB-k .. PNB-1] hold the multipliers l_0 .. l_{k-1}, and the
+// registers between are padding.  An elimination shifts the row left by one
+// (r[i] = r[i+1] - l U[i+1] on the live part, a plain shift elsewhere) and
+// puts the new multiplier in r[PNB-1]; all register indices are static.  Rows
+// that reach the diagonal freeze.  Two rows that swap at column c were both
+// shifted c times, so their register images are exchanged as they are.
+__global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
+    __shared__ __align__(16) float U[PNB], D[PNB], rowbuf[PNB], diagbuf[PNB];
     __shared__ float red_v[PROWS / 64];
     __shared__ int red_i[PROWS / 64];
     __shared__ int s_piv, s_win;
     __shared__ float s_val;
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int w = a.w, ld = panel_ld(w);
+    const int w = a.w;
     const int64_t row0 = (int64_t)g * PROWS;      // first panel row of this workgroup
     const int64_t pr = row0 + t;                   // panel row owned by this thread
     const bool own = pr < a.m;
     float *Ag = a.A + a.j * a.lda + a.j;           // panel origin
-
-    for (int e = t; e < PROWS * w; e += PROWS) {
-        const int r = e / w, q = e % w;
-        P[r * ld + q] = (row0 + r < a.m) ? Ag[(row0 + r) * a.lda + q] : 0.0f;
-    }
-    __syncthreads();
+    float r[PNB];
+#pragma unroll
+    for (int k = 0; k < PNB; ++k) r[k] = (own && k < w) ? Ag[pr * a.lda + k] : 0.0f;
 
     for (int c = 0; c < w; ++c) {
         const int par = c & 1;
         const uint32_t tag = (uint32_t)(a.j + c + 1);   // never 0 (headers start zeroed)
-        // ---- local arg-max of |P[., c]| over rows >= c
-        float v = (own && pr >= c) ? fabsf(P[t * ld + c]) : -1.0f;
+        const bool active = own && pr >= c;             // rows at or below the diagonal
+        // ---- local arg-max of |column c| over rows >= c
+        float v = active ? fabsf(r[0]) : -1.0f;
         int idx = own ? (int)pr : INT_MAX;
         if (!(v == v)) v = INFINITY;  // NaN pivots win (and poison the result)
         for (int off = 32; off > 0; off >>= 1) {
@@ -119,13 +124,23 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
             s_piv = (bv >= 0.0f) ? bi : -1;
         }
         __syncthreads();
-        // ---- wave 0 publishes the candidate row (and row c, by its owner),
-        // then the header with release order (covering the wave's own stores)
+        // ---- the candidate row and row c (register images) to LDS
+        if (own && pr == s_piv) {
+#pragma unroll
+            for (int k = 0; k < PNB; ++k) rowbuf[k] = r[k];
+        }
+        if (own && pr == c) {
+#pragma unroll
+            for (int k = 0; k < PNB; ++k) diagbuf[k] = r[k];
+        }
+        __syncthreads();
+        // ---- wave 0 publishes them, then the header with release order
+        // (covering the wave's own stores)
         if (wave == 0) {
             const bool has_c = c >= row0 && c < row0 + PROWS;
-            for (int q = lane; q < w; q += 64) {
-                if (s_piv >= 0) a.ws.slot_row[(par * MAX_G + g) * PNB + q] = P[(s_piv - row0) * ld + q];
-                if (has_c) a.ws.diag_row[par * PNB + q] = P[(c - row0) * ld + q];
+            for (int q = lane; q < PNB; q += 64) {
+                if (s_piv >= 0) a.ws.slot_row[(par * MAX_G + g) * PNB + q] = rowbuf[q];
+                if (has_c) a.ws.diag_row[par * PNB + q] = diagbuf[q];
             }
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) {
@@ -182,7 +197,7 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
         }
         __syncthreads();
         const int pg = s_win;
-        if (t < w) {
+        if (t < PNB) {
             U[t] = a.ws.slot_row[(par * MAX_G + pg) * PNB + t];
             D[t] = a.ws.diag_row[par * PNB + t];
         }
@@ -190,53 +205,63 @@ __global__ void __launch_bounds__(PROWS) panel_kernel(PanelArgs a) {
         __syncthreads();
         // a valid pivot row is >= c; anything else only follows an expired wait
         const int p = (s_piv >= c && s_piv < a.m) ? s_piv : c;
-        const float piv = U[c];
+        const float piv = U[0];
         if (g == 0 && t == 0) {
             a.ipiv[a.j + c] = (int32_t)(a.j + p);
             if (piv == 0.0f && *a.info == 0) *a.info = (int32_t)(a.j + c + 1);  // -1 (expired wait) is kept
         }
-        // ---- swap rows c and p, divide, rank-1 update of the own row
-        if (own) {
-            float *row = P + t * ld;
-            float4 *r4 = reinterpret_cast<float4 *>(row);
-            const int w4 = (w + 3) >> 2;   // 16-byte groups (padding columns are never stored)
+        // ---- swap rows c and p, divide, shift-update the rows below
+        if (active) {
             if (pr == p && p != c) {
-                const float4 *d4 = reinterpret_cast<const float4 *>(D);
-#pragma unroll 8
-                for (int g4 = 0; g4 < w4; ++g4) r4[g4] = d4[g4];
+#pragma unroll
+                for (int k = 0; k < PNB; ++k) r[k] = D[k];
             }
             if (pr == c) {
-                const float4 *u4 = reinterpret_cast<const float4 *>(U);
-#pragma unroll 8
-                for (int g4 = 0; g4 < w4; ++g4) r4[g4] = u4[g4];
-            }
-            if (pr > c) {
-                float l = row[c];
+#pragma unroll
+                for (int k = 0; k < PNB; ++k) r[k] = U[k];
+            } else {
+                float l = r[0];
                 if (piv != 0.0f) l = l / piv;
-                row[c] = l;
-                // columns c+1 .. w-1 in 16-byte groups from the group holding
-                // c+1 (columns <= c of that group are kept; the padding
-                // columns up to the next multiple of 4 are never stored)
-                const float4 *u4 = reinterpret_cast<const float4 *>(U);
-#pragma unroll 4
-                for (int g4 = (c + 1) >> 2; g4 < w4; ++g4) {
-                    const float4 u = u4[g4];
-                    float4 r = r4[g4];
-                    const int q = 4 * g4;
-                    r.x = (q > c) ? fmaf(-l, u.x, r.x) : r.x;
-                    r.y = (q + 1 > c) ? fmaf(-l, u.y, r.y) : r.y;
-                    r.z = (q + 2 > c) ? fmaf(-l, u.z, r.z) : r.z;
-                    r.w = (q + 3 > c) ? fmaf(-l, u.w, r.w) : r.w;
-                    r4[g4] = r;
+                const int live = w - c;   // r[0 .. live-1] are columns c .. w-1
+                // blocks of 8 registers: all updated, all shifted, or mixed
+#pragma unroll
+                for (int b = 0; b < PNB / 8; ++b) {
+                    if (8 * b + 8 <= live - 1) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int k = 8 * b + i;
+                            if (k < PNB - 1) r[k] = fmaf(-l, U[k + 1], r[k + 1]);
+                        }
+                    } else if (8 * b >= live - 1) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int k = 8 * b + i;
+                            if (k < PNB - 1) r[k] = r[k + 1];
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int k = 8 * b + i;
+                            if (k < PNB - 1) r[k] = (k < live - 1) ? fmaf(-l, U[k + 1], r[k + 1]) : r[k + 1];
+                        }
+                    }
                 }
+                r[PNB - 1] = l;
             }
         }
-        __syncthreads();
     }
 
-    for (int e = t; e < PROWS * w; e += PROWS) {
-        const int r = e / w, q = e % w;
-        if (row0 + r < a.m) Ag[(row0 + r) * a.lda + q] = P[r * ld + q];
+    // ---- write back: register k of a row shifted s times holds column s + k
+    // (k < w - s) or multiplier k - (PNB - s) (k >= PNB - s)
+    if (own) {
+        const int sh = (pr < w) ? (int)pr : w;
+#pragma unroll
+        for (int k = 0; k < PNB; ++k) {
+            int col = -1;
+            if (k < w - sh) col = sh + k;
+            else if (k >= PNB - sh) col = k - (PNB - sh);
+            if (col >= 0) Ag[pr * a.lda + col] = r[k];
+        }
     }
 }
 
@@ -296,40 +321,58 @@ laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *
         if (slot[i] == w + i) A[(j + sp[i]) * lda + col] = T[(w + i) * SWP_COLS + l];
 }
 
-// U12 = L11^{-1} A12.  Each 128-thread workgroup copies 128 columns of A12
-// and L11 into LDS; each thread then solves its own column by forward
-// substitution in row order, s = a_r - sum_{p<r} L_rp x_p as one FMA chain in
-// increasing p (the unblocked algorithm's order), and the block is copied back.
-constexpr int TRSM_COLS = 128;
-__global__ void __launch_bounds__(TRSM_COLS)
+// U12 = L11^{-1} A12 (unit lower L11, jb x jb).  Column-oriented forward
+// substitution: at step p the now final row p of X is broadcast and every row
+// i > p is updated, x_i = fma(-L_ip, x_p, x_i) -- for each element the same
+// FMA chain, in increasing p, as the row-oriented algorithm.  A 256-thread
+// workgroup owns 64 columns; wave h keeps rows 32h .. 32h+31 of its column in
+// registers, L11 is staged transposed in LDS (rows padded to 132 floats).
+// Steps are unrolled in blocks of 32 so that register indices are static.
+constexpr int TRSM_COLS = 64;
+constexpr int TRSM_LD = PNB + 4;
+constexpr size_t TRSM_LDS = (size_t)PNB * TRSM_LD * sizeof(float);
+__global__ void __launch_bounds__(256, 2)
 trsm_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w) {
-    extern __shared__ float sm[];
-    float *L = sm;                    // [PNB][PNB]
-    float *X = sm + PNB * PNB;        // [PNB][TRSM_COLS + 1]
-    constexpr int XLD = TRSM_COLS + 1;
-    const int t = threadIdx.x;
-    const int64_t c0 = j + w + (int64_t)blockIdx.x * TRSM_COLS;
-    const int ncols = (int)((n - c0 < TRSM_COLS) ? n - c0 : TRSM_COLS);
-    for (int e = t; e < PNB * PNB; e += TRSM_COLS) {
+    extern __shared__ __align__(16) float Lt[];   // Lt[p * TRSM_LD + i] = L11[i][p]
+    __shared__ float xb[TRSM_COLS];
+    const int t = threadIdx.x, c = t & 63, h = t >> 6;
+    const int64_t col = j + w + (int64_t)blockIdx.x * TRSM_COLS + c;
+    const bool ok = col < n;
+    for (int e = t; e < PNB * PNB; e += 256) {
         const int i = e / PNB, p = e % PNB;
-        L[e] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
+        Lt[p * TRSM_LD + i] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
     }
-    for (int i = 0; i < w; ++i)
-        if (t < ncols) X[i * XLD + t] = A[(j + i) * lda + c0 + t];
+    float x[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const int i = 32 * h + k;
+        x[k] = (ok && i < w) ? A[(j + i) * lda + col] : 0.0f;
+    }
     __syncthreads();
-    if (t < ncols) {
-        for (int i = 1; i < w; ++i) {
-            float s = X[i * XLD + t];
-            const float *li = L + i * PNB;
-            // one FMA chain in increasing p; the LDS reads run ahead of it
-#pragma unroll 8
-            for (int p = 0; p < i; ++p) s = fmaf(-li[p], X[p * XLD + t], s);
-            X[i * XLD + t] = s;
+    for (int hp = 0; hp < 4; ++hp) {
+        if (32 * hp >= w - 1) break;   // uniform
+#pragma unroll
+        for (int kp = 0; kp < 32; ++kp) {
+            const int p = 32 * hp + kp;
+            if (h == hp) xb[c] = x[kp];
+            __syncthreads();
+            const float xp = xb[c];
+            const float *lp = Lt + p * TRSM_LD + 32 * h;   // L11[32h + k][p]
+            if (h > hp) {
+#pragma unroll
+                for (int k = 0; k < 32; ++k) x[k] = fmaf(-lp[k], xp, x[k]);
+            } else if (h == hp) {
+#pragma unroll
+                for (int k = kp + 1; k < 32; ++k) x[k] = fmaf(-lp[k], xp, x[k]);
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
-    for (int i = 1; i < w; ++i)
-        if (t < ncols) A[(j + i) * lda + c0 + t] = X[i * XLD + t];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const int i = 32 * h + k;
+        if (ok && i >= 1 && i < w) A[(j + i) * lda + col] = x[k];
+    }
 }
 
 static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv,
@@ -338,12 +381,8 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
     lu_ws_layout(&w, ws);
     static bool attr = false;
     if (!attr) {
-        BFX_HIP(hipFuncSetAttribute((const void *)panel_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    PROWS * panel_ld(PNB) * (int)sizeof(float)));
         BFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (PNB * PNB + PNB * (TRSM_COLS + 1)) * (int)sizeof(float)));
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)TRSM_LDS));
         BFX_HIP(hipFuncSetAttribute((const void *)laswp_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)SWP_LDS));
         attr = true;
@@ -358,9 +397,8 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         pa.G = (int)ceil_div(n - j, PROWS);
         pa.ipiv = ipiv; pa.info = info; pa.ws = w;
         void *args[] = {&pa};
-        const size_t lds = (size_t)PROWS * panel_ld(jb) * sizeof(float);
         BFX_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(pa.G), dim3(PROWS),
-                                           args, (unsigned)lds, s));
+                                           args, 0, s));
         const int64_t others = n - jb;
         if (others > 0) {
             hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_COLS),
@@ -369,8 +407,8 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         }
         const int64_t rest = n - j - jb;
         if (rest <= 0) continue;
-        hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(rest, TRSM_COLS)), dim3(TRSM_COLS),
-                           (PNB * PNB + PNB * (TRSM_COLS + 1)) * sizeof(float), s, A, lda, n, j, jb);
+        hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(rest, TRSM_COLS)), dim3(256), TRSM_LDS, s,
+                           A, lda, n, j, jb);
         BFX_LAUNCH_CHECK("trsm_kernel");
         float *A21 = A + (j + jb) * lda + j;
         float *A12 = A + j * lda + (j + jb);

@@ -54,8 +54,15 @@ def main():
         A, b = workloads.conditioned_system_torch(a.n, a.kappa, 7, dev)
         for _ in range(a.reps):
             LU = A.clone()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
             _, ipiv, info = bfx.lu_factor(LU, a.variant)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
             x, res = bfx.ir_solve(A, LU, ipiv, b)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            print(f"lu {1e3 * (t2 - t1):.1f} ms, ir {1e3 * (t3 - t2):.1f} ms, {res}", flush=True)
     elif a.workload == "lu-update":
         # the first trailing update of an n x n LU: A22 -= L21 x U12, K = 128,
         # all three operands strided views of one n x n matrix
