@@ -75,11 +75,30 @@ constexpr size_t tile_lds_bytes() {
     return 2ull * Prods<V>::P * (BM + BN) * LDK * sizeof(uint16_t);
 }
 
+// LDS row length (BF16) of the wave-specialised tile: 128-wide tiles use
+// unpadded 64-byte rows with the permuted layout of swz_off, 64-wide tiles
+// the padded 80-byte rows of the general tile.
+template <int BM>
+constexpr int fast_ldk() { return BM == 128 ? BK : LDK; }
+
 // The wave-specialised tile additionally keeps, per helper thread, room for
 // its 2*KPT FP32 values (rare exact re-split path; stride padded by one).
 template <int V, int BM, int BN>
 constexpr size_t fast_lds_bytes() {
-    return tile_lds_bytes<V, BM, BN>() + 256ull * (2 * (BM * 32 / 256) + 1) * sizeof(float);
+    return 2ull * Prods<V>::P * (BM + BN) * fast_ldk<BM>() * sizeof(uint16_t) +
+           256ull * (2 * (BM * 32 / 256) + 1) * sizeof(float);
+}
+
+// Element offset of (row n, k) in a plane of the 128-wide wave-specialised
+// tile (rows of 32 BF16 = 64 bytes; n counts A rows, then B columns).  Row n
+// sits in physical row n ^ ((n >> 2) & 1) and its 16-byte chunk k/8 at
+// position (k/8) ^ ((n >> 1) & 3).  On gfx950 (64 banks of 4 bytes) this keeps
+// three access patterns free of bank conflicts: the MFMA fragment reads
+// (16-byte reads of rows n0 + lane%16, chunk lane/16), the helpers' 8-byte
+// stores of A (two consecutive rows per 16 lanes) and their 8-byte stores of
+// B (columns 4 apart, whose physical rows then alternate in parity).
+__device__ __forceinline__ int swz_off(int n, int k) {
+    return ((n ^ ((n >> 2) & 1)) << 5) + ((((k >> 3) ^ (n >> 1)) & 3) << 3) + (k & 7);
 }
 
 // Epilogue of one MFMA wave's TM x TN block of 16 x 16 tiles.  Output layout
@@ -312,10 +331,12 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int64_t m0, int64
 // a multiple of 32.  M, N and K need
 // not fill the tile: partial tiles are handled by clamped loads whose values
 // are replaced by zeros and by a masked epilogue.  Differences from gemm_tile:
-//   * loads: one thread per A row / B column and BM*32/256 consecutive k
-//     values (16-byte loads of A, coalesced 4-byte loads of B) through buffer
-//     resources, so every LDS store is a conflict-free 16-byte store of 8 BF16
-//     (rows are 80 bytes apart);
+//   * loads: 16-byte buffer loads of A row segments and B row segments
+//     (4 columns); every helper thread holds 4 consecutive k of BM/32 A rows
+//     and 4 columns x BN/32 consecutive k of B, so every LDS store is an
+//     8-byte store of 4 BF16 of one row (A) or one column (B); the 128-wide
+//     tile uses the bank-conflict-free layout of swz_off, the 64-wide tile
+//     padded 80-byte rows;
 //   * global loads are issued three (128-wide tiles) or two (64-wide) K-steps
 //     ahead, one register stage per step in flight;
 //   * the split is branch-free (hardware RNE); the rare values for which it is
@@ -365,7 +386,9 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                                                uint16_t *smem) {
     using PR = Prods<V>;
     constexpr int P = PR::P;
-    constexpr int PLANE = (BM + BN) * LDK;
+    constexpr bool SWZ = BM == 128;                     // swz_off layout (else padded rows)
+    constexpr int FLDK = fast_ldk<BM>();
+    constexpr int PLANE = (BM + BN) * FLDK;
     constexpr int TM = BM / 32, TN = BN / 32;          // 16x16 tiles per MFMA wave (2 x 2 waves)
     constexpr int KPT = BM * BK / 256;                  // k values per helper thread
     constexpr int NST = NST_ ? NST_ : (BM == 128 ? 3 : 2);  // helper register stages
@@ -387,7 +410,14 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         const int r16 = lane & 15, kg = lane >> 4;
         int boff[TN];   // B fragment offsets (elements) inside a plane
 #pragma unroll
-        for (int j = 0; j < TN; ++j) boff[j] = (BM + bcol_row(wn * (BN / 2) + j * 16 + r16)) * LDK + kg * 8;
+        for (int j = 0; j < TN; ++j)
+            boff[j] = SWZ ? swz_off(BM + wn * (BN / 2) + j * 16 + r16, kg * 8)
+                          : (BM + bcol_row(wn * (BN / 2) + j * 16 + r16)) * FLDK + kg * 8;
+        int aoff[TM];   // A fragment offsets
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            aoff[i] = SWZ ? swz_off(wm * (BM / 2) + i * 16 + r16, kg * 8)
+                          : (wm * (BM / 2) + i * 16 + r16) * FLDK + kg * 8;
         for (int s = 0; s < KT; ++s) {
             __syncthreads();  // buffer s&1 holds step s
             const uint16_t *base = smem + (s & 1) * P * PLANE;
@@ -396,8 +426,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
             for (int pl = 0; pl < P; ++pl)
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(
-                        base + pl * PLANE + (wm * (BM / 2) + i * 16 + r16) * LDK + kg * 8);
+                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
             // B fragments one plane at a time (plane 2, 1, 0): within each B
             // plane the lo products are issued smallest bin first.
 #pragma unroll
@@ -435,18 +464,18 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     // A: eight lanes cover one row's 32 k (128 bytes) with 16-byte loads, so a
     //    wave's load touches 8 whole rows (8 cache lines); each thread holds
     //    4 consecutive k of AR = BM/32 rows (ar0, ar0+32, ...).
-    // B: 16-byte loads of 4 columns; a half-wave covers 64 columns of two k
-    //    rows (BN = 128) or all 64 columns of one k row (BN = 64), so a
-    //    wave's load touches whole 256-byte row segments; each thread holds
-    //    4 columns x RB = BN/32 consecutive k, stored per column (rows
-    //    permuted by bcol_row) as RB BF16 per plane.
+    // B: 16-byte loads of 4 columns; each thread holds 4 columns x RB =
+    //    BN/32 consecutive k, stored per column as RB BF16 per plane.  For
+    //    BN = 128 eight lanes cover 4 k rows of the same 4 columns and a
+    //    wave's load touches 8 k rows x 128 bytes; for BN = 64 a half-wave
+    //    covers all 64 columns of one k row (rows permuted by bcol_row).
     constexpr int AR = BM / 32;
     constexpr int RB = BN / 32;
     const int h = tid - 256;
     const int ar0 = h / 8, ac = h % 8;      // A: first row, 4-k chunk
     const int hl = h & 63, hw = h >> 6;     // helper lane, helper wave
-    const int bc = (BN == 128) ? (hl & 15) + 16 * (hl >> 5) : (hl & 15);      // column group
-    const int bkq = (BN == 128) ? 2 * hw + ((hl >> 4) & 1) : 4 * hw + (hl >> 4);  // k rows RB*bkq ..
+    const int bc = SWZ ? h >> 3 : (hl & 15);                 // column group
+    const int bkq = SWZ ? h & 7 : 4 * hw + (hl >> 4);        // k rows RB*bkq ..
     // Extent of this tile inside the matrices.  `full` (uniform) selects the
     // unmasked code; otherwise every load is clamped to an element inside the
     // tile's range and its value replaced by zero before the split.
@@ -544,12 +573,14 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                 // A: 4 BF16 (8 bytes) per row
 #pragma unroll
                 for (int i = 0; i < AR; ++i)
-                    *reinterpret_cast<uint2 *>(base + pl * PLANE + (ar0 + 32 * i) * LDK + ac * 4) =
+                    *reinterpret_cast<uint2 *>(base + pl * PLANE +
+                                               (SWZ ? swz_off(ar0 + 32 * i, ac * 4) : (ar0 + 32 * i) * FLDK + ac * 4)) =
                         make_uint2(pa[pl][2 * i], pa[pl][2 * i + 1]);
                 // B: RB BF16 of each of the 4 columns
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    uint16_t *d = base + pl * PLANE + (BM + bcol_row(4 * bc + j)) * LDK + RB * bkq;
+                    uint16_t *d = base + pl * PLANE +
+                                  (SWZ ? swz_off(BM + 4 * bc + j, RB * bkq) : (BM + bcol_row(4 * bc + j)) * FLDK + RB * bkq);
                     if constexpr (RB == 4)
                         *reinterpret_cast<uint2 *>(d) = make_uint2(pb[pl][2 * j], pb[pl][2 * j + 1]);
                     else
@@ -575,12 +606,13 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
             for (int e = 0; e < 2 * KPT; ++e) {
                 const bool isA = e < KPT;
                 const int q = e - KPT;   // B: q = 4 i + j, k row RB*bkq + i, column 4 bc + j
-                const int row = isA ? ar0 + 32 * (e / 4) : BM + bcol_row(4 * bc + (q & 3));
+                const int row = isA ? ar0 + 32 * (e / 4) : BM + (SWZ ? 4 * bc + (q & 3) : bcol_row(4 * bc + (q & 3)));
                 const int k = isA ? ac * 4 + (e % 4) : RB * bkq + (q >> 2);
+                const int off = SWZ ? swz_off(row, k) : row * FLDK + k;
                 uint32_t hh[3];
                 split3_exact(raw[e], hh[0], hh[1], hh[2]);
 #pragma unroll
-                for (int pl = 0; pl < P; ++pl) base[pl * PLANE + row * LDK + k] = (uint16_t)hh[pl];
+                for (int pl = 0; pl < P; ++pl) base[pl * PLANE + off] = (uint16_t)hh[pl];
             }
         };
         // Barrier t starts MFMA step t (buffer t&1).  Between barriers t and
