@@ -326,11 +326,19 @@ def main():
     # ---------------- CPU baseline: the oracle on a row sample ----------------
     import oracle as orc
     cores = orc.num_threads()
-    rows = 2
-    t0 = time.perf_counter()
-    orc.gemm(6, A[:rows], B)
-    dt = time.perf_counter() - t0
-    rows2 = int(min(256, max(rows, rows * args.cpu_seconds / max(dt, 1e-3))))
+    # Each oracle call has a fixed part (splitting all of B) and a part
+    # proportional to the rows of C: after a warm-up call, calibrate on 8 and
+    # 40 rows and size the sample so that the timed call takes about
+    # --cpu-seconds.
+    def timed(r):
+        t = time.perf_counter()
+        orc.gemm(6, A[:r], B)
+        return time.perf_counter() - t
+    timed(2)
+    ta, tb = timed(8), timed(40)
+    per_row = max((tb - ta) / 32.0, 1e-3)
+    fixed = max(ta - 8 * per_row, 0.0)
+    rows2 = int(min(2048, max(8, (args.cpu_seconds - fixed) / per_row)))
     t0 = time.perf_counter()
     orc.gemm(6, A[:rows2], B)
     dt2 = time.perf_counter() - t0
