@@ -11,7 +11,7 @@
 //   trsv_kernel      blocked triangular solve without a global barrier: each
 //                    workgroup takes the next block row from a ticket counter,
 //                    waits (bounded) on the completion flags of the blocks it
-//                    depends on, adds their contribution, solves its 64 x 64
+//                    depends on, adds their contribution, solves its 128 x 128
 //                    diagonal block in one wave and publishes its flag;
 //   perm_kernel      the row permutation of ipiv, composed once per solve.
 // The host reads |r|_inf and |x|_inf once per step to apply the stopping rule.
@@ -25,7 +25,8 @@
 namespace bfx {
 
 namespace {
-constexpr int TB = 64;
+constexpr int TB = 128;
+constexpr size_t TRSV_LDS = sizeof(float) * TB * (TB + 1);
 constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
 
 enum { S_NORMA = 0, S_NORMB = 1, S_RN = 2, S_XN = 3, S_NSCAL = 8 };
@@ -191,19 +192,38 @@ vec_absmax_kernel(const double *v, int64_t n, unsigned long long *dst) {
     if ((threadIdx.x & 63) == 0) atomic_max_abs(dst, m);
 }
 
+// Value of v in lane l (l uniform), through v_readlane.
+__device__ __forceinline__ float bcast_lane(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Blocked triangular solve with the FP32 LU factors, in place on y; T is the
 // arithmetic and vector type (float for LU-IR, double for the GMRES
 // preconditioner).  lower = 1: unit lower L (forward); lower = 0: upper U
-// (backward, divides).
+// (backward, divides).  One workgroup per block row of TB = 128 rows, taken in
+// dependency order from a ticket counter.  Off-diagonal part: wave w owns rows
+// 16w .. 16w+15 of the block row; for every dependency block its 64 lanes
+// read 2 consecutive columns each (one coalesced 512-byte load per row) and
+// accumulate per row in column order, the 16 row sums being reduced across
+// the wave at the end.  The factor values of the next dependency are loaded
+// before waiting for it.  Diagonal block: one wave, lane l holding rows l and
+// l + 64, substitution in column order with the diagonal block in LDS.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32_t *ticket,
             int32_t *err, int lower) {
+    extern __shared__ float Ld[];   // [TB][TB + 1] diagonal block
     __shared__ int s_blk;
     __shared__ int64_t s_known;
-    __shared__ T Ld[TB][TB + 1];
     __shared__ T rhs[TB];
-    const int t = threadIdx.x, lane = t & 63;
+    constexpr int LDD = TB + 1;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t nblk = ceil_div(n, TB);
     if (t == 0) s_blk = (int)atomicAdd(ticket, 1u);
     __syncthreads();
@@ -211,93 +231,148 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
     const int64_t r0 = blk * TB;
     const int rows = (int)((n - r0 < TB) ? n - r0 : TB);
     // diagonal block to LDS (independent of other blocks)
-    for (int e = t; e < TB * TB; e += 256) {
+    for (int e = t; e < TB * TB; e += 512) {
         const int i = e / TB, c = e % TB;
-        Ld[i][c] = (i < rows && c < rows) ? (T)LU[(r0 + i) * ld + r0 + c] : (T)0;
+        Ld[i * LDD + c] = (i < rows && c < rows) ? LU[(r0 + i) * ld + r0 + c] : 0.0f;
     }
-    // Off-diagonal contributions: thread (rr = t/4, sub = t%4) covers 16
-    // columns.  Dependencies are visited in completion order (ascending for
-    // L, descending for U).  A block only completes after every block before
-    // it in that order, so one acquire of a flag covers all earlier blocks and
-    // thread 0 waits only when the next block is not yet known complete.
-    // The factor values of the next dependency are loaded before waiting for
-    // it (they do not depend on the solve), so only the solution values are
-    // fetched after a completion flag is seen.
-    const int rr = t >> 2, sub = t & 3;
-    T acc = 0;
     const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
-    const float *lrow = LU + (r0 + (rr < rows ? rr : 0)) * ld;
-    auto col0 = [&](int64_t d) { return (lower ? d : nblk - 1 - d) * TB + sub * 16; };
-    float lc[16], ln[16];
-    if (nb_dep > 0) {
-        const int64_t c1 = col0(0);
+    // rows 16 wave .. 16 wave + 15 of this block row (clamped: rows past the
+    // end of the matrix re-read the last row and are never stored)
+    const float *lrow[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lc[k] = (c1 + k < n) ? lrow[c1 + k] : 0.0f;
+    for (int q = 0; q < 16; ++q) {
+        const int rr = 16 * wave + q;
+        lrow[q] = LU + (r0 + (rr < rows ? rr : rows - 1)) * ld;
     }
+    auto col0 = [&](int64_t d) { return (lower ? d : nblk - 1 - d) * TB + 2 * lane; };
+    float lc[16][2], ln[16][2];
+    auto load = [&](float (&dst)[16][2], int64_t c) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            dst[q][0] = (c < n) ? lrow[q][c] : 0.0f;
+            dst[q][1] = (c + 1 < n) ? lrow[q][c + 1] : 0.0f;
+        }
+    };
+    T acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0;
+    if (nb_dep > 0) load(lc, col0(0));
     int64_t known = 0;  // dependencies known complete
     for (int64_t d = 0; d < nb_dep; ++d) {
         const int64_t jb = lower ? d : nblk - 1 - d;
-        if (d + 1 < nb_dep) {
-            const int64_t c1 = col0(d + 1);
-#pragma unroll
-            for (int k = 0; k < 16; ++k) ln[k] = (c1 + k < n) ? lrow[c1 + k] : 0.0f;
-        }
+        if (d + 1 < nb_dep) load(ln, col0(d + 1));
         if (d >= known) {
+            // A block completes only after every block before it in this
+            // order, so one acquire of the furthest flag known set covers all
+            // earlier blocks; polls are relaxed.
             if (t == 0) {
                 unsigned spins = 0;
-                while (__hip_atomic_load(flags + jb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                while (__hip_atomic_load(flags + jb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
                     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
                     if (++spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                // extend over dependencies that are already complete: scan with
-                // relaxed loads, then one acquire on the furthest one found
                 int64_t e = d + 1;
                 while (e < nb_dep &&
                        __hip_atomic_load(flags + (lower ? e : nblk - 1 - e), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT) != 0)
                     ++e;
-                if (e > d + 1)
-                    (void)__hip_atomic_load(flags + (lower ? e - 1 : nblk - e), __ATOMIC_ACQUIRE,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+                (void)__hip_atomic_load(flags + (lower ? e - 1 : nblk - e), __ATOMIC_ACQUIRE,
+                                        __HIP_MEMORY_SCOPE_AGENT);
                 s_known = e;
             }
             __syncthreads();
             known = s_known;
         }
-        const int64_t c0 = jb * TB + sub * 16;
-        if (rr < rows) {
+        const int64_t c = jb * TB + 2 * lane;
+        const T y0 = (c < n) ? y[c] : (T)0, y1 = (c + 1 < n) ? y[c + 1] : (T)0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (c0 + k < n) acc = fma((T)lc[k], y[c0 + k], acc);
+        for (int q = 0; q < 16; ++q) {
+            acc[q] = fma((T)lc[q][0], y0, acc[q]);
+            acc[q] = fma((T)lc[q][1], y1, acc[q]);
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lc[k] = ln[k];
+        for (int q = 0; q < 16; ++q) { lc[q][0] = ln[q][0]; lc[q][1] = ln[q][1]; }
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    if (sub == 0 && rr < rows) rhs[rr] = y[r0 + rr] - acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    if (lane < 16) {
+        // lane q publishes row 16 wave + q (static register index via a select chain)
+        T v = acc[0];
+#pragma unroll
+        for (int q = 1; q < 16; ++q) if (lane == q) v = acc[q];
+        const int rr = 16 * wave + lane;
+        if (rr < rows) rhs[rr] = y[r0 + rr] - v;
+    }
     __syncthreads();
     if (t < 64) {
-        T v = (lane < rows) ? rhs[lane] : (T)0;
+        // Column c's solution value is read with v_readlane (c is uniform),
+        // so it is a wave-uniform operand; every lane computes the FMA and a
+        // select keeps it only for the rows it applies to (no exec-mask
+        // changes; rows it does not apply to keep their value even when the
+        // product is not finite).  The LDS operands of 8 columns
+        // are loaded one chunk ahead.  Backward solve on the rows scaled by
+        // the reciprocals of their diagonal entries (products rounded once,
+        // formed off the dependency chain).
+        T v0 = (lane < rows) ? rhs[lane] : (T)0;
+        T v1 = (lane + 64 < rows) ? rhs[lane + 64] : (T)0;
+        const float *l0 = Ld + lane * LDD, *l1 = Ld + (lane + 64) * LDD;
+        float a0[8], a1[8], b0[8], b1[8];
+        const int nch = (rows + 7) / 8;
         if (lower) {
-            for (int c = 0; c < rows; ++c) {
-                const T yc = __shfl(v, c);
-                if (lane > c) v = fma(-Ld[lane][c], yc, v);
+            // unit diagonal; columns >= rows of the block hold zeros
+#pragma unroll
+            for (int k = 0; k < 8; ++k) { a0[k] = l0[k]; a1[k] = l1[k]; }
+            for (int ch = 0; ch < nch; ++ch) {
+                const int cn = 8 * (ch + 1 < nch ? ch + 1 : ch);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) { b0[k] = l0[cn + k]; b1[k] = l1[cn + k]; }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int c = 8 * ch + k;
+                    const T yc = bcast_lane(c < 64 ? v0 : v1, c & 63);
+                    const T u0 = fma(-(T)a0[k], yc, v0), u1 = fma(-(T)a1[k], yc, v1);
+                    v0 = (lane > c) ? u0 : v0;
+                    v1 = (lane + 64 > c) ? u1 : v1;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) { a0[k] = b0[k]; a1[k] = b1[k]; }
             }
         } else {
-            for (int c = rows - 1; c >= 0; --c) {
-                if (lane == c) v = v / Ld[c][c];
-                const T yc = __shfl(v, c);
-                if (lane < c) v = fma(-Ld[lane][c], yc, v);
+            // Rows scaled by the reciprocal of their diagonal entry (each lane
+            // holds those of its two rows): U' = D^-1 U has a unit diagonal
+            // and the chain per column is one broadcast and one FMA.
+            const T rd0 = (lane < rows) ? (T)1 / (T)l0[lane] : (T)0;
+            const T rd1 = (lane + 64 < rows) ? (T)1 / (T)l1[lane + 64] : (T)0;
+            v0 *= rd0;
+            v1 *= rd1;
+            const int top = 8 * (nch - 1);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) { a0[k] = l0[top + k]; a1[k] = l1[top + k]; }
+            for (int ch = nch - 1; ch >= 0; --ch) {
+                const int cn = 8 * (ch > 0 ? ch - 1 : 0);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) { b0[k] = l0[cn + k]; b1[k] = l1[cn + k]; }
+#pragma unroll
+                for (int k = 7; k >= 0; --k) {
+                    const int c = 8 * ch + k;
+                    if (c < rows) {
+                        const T yc = bcast_lane(c < 64 ? v0 : v1, c & 63);
+                        const T u0 = fma(-((T)a0[k] * rd0), yc, v0), u1 = fma(-((T)a1[k] * rd1), yc, v1);
+                        v0 = (lane < c) ? u0 : v0;
+                        v1 = (lane + 64 < c) ? u1 : v1;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) { a0[k] = b0[k]; a1[k] = b1[k]; }
             }
         }
-        if (lane < rows) y[r0 + lane] = v;
-    }
-    __syncthreads();
-    if (t == 0) {
-        __threadfence();
-        __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane < rows) y[r0 + lane] = v0;
+        if (lane + 64 < rows) y[r0 + 64 + lane] = v1;
+        __builtin_amdgcn_wave_barrier();
+        // the release covers wave 0's stores of y
+        if (t == 0) __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -375,10 +450,16 @@ template <typename T>
 static int lu_solve_vec(int64_t n, const float *LU, int64_t ldlu, T *y, const IrWs &w,
                         hipStream_t s) {
     const int64_t nb = ceil_div(n, TB);
+    static bool attr = false;
+    if (!attr) {
+        BFX_HIP(hipFuncSetAttribute((const void *)trsv_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)TRSV_LDS));
+        attr = true;
+    }
     for (int lower = 1; lower >= 0; --lower) {
         hipLaunchKernelGGL(zero_i32, dim3(grid_for(nb)), dim3(256), 0, s, w.flags, nb);
         hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.ticket, 4);
-        hipLaunchKernelGGL(trsv_kernel<T>, dim3((unsigned)nb), dim3(256), 0, s, LU, ldlu, n, y,
+        hipLaunchKernelGGL(trsv_kernel<T>, dim3((unsigned)nb), dim3(512), TRSV_LDS, s, LU, ldlu, n, y,
                            w.flags, w.ticket, w.err, lower);
         BFX_LAUNCH_CHECK("trsv_kernel");
     }
