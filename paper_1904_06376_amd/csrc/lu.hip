@@ -12,7 +12,8 @@
 //      its own rows.  The header exchange is the only grid-wide
 //      synchronisation: one round of polling per column, no barrier counter.
 //   2. laswp_kernel  - the panel's row interchanges applied to the columns
-//      left and right of the panel (rows staged in LDS, swaps replayed there).
+//      left and right of the panel (composed into one row permutation, each
+//      affected row moved once).
 //   3. trsm_kernel   - U12 = L11^{-1} A12 (unit lower, FP32 FMA chains in
 //      index order; column-oriented steps over register-resident rows).
 //   4. A22 -= L21 x U12 with the split-BF16 GEMM (alpha = -1, beta = 1).
@@ -269,56 +270,66 @@ __global__ void __launch_bounds__(256) zero_u64(uint64_t *p, int n) {
     for (int i = threadIdx.x; i < n; i += 256) p[i] = 0ull;
 }
 
-// Row interchanges of rows j..j+w-1 (ipiv, applied in order) on every column
-// outside the panel.  Each 64-thread workgroup owns 64 columns (one per
-// lane): it stages the block rows and every row below the block that an
-// interchange names in LDS, replays the interchanges there in order (each
-// lane touches only its own column) and writes the rows back.  Block rows
-// keep LDS slots 0..w-1; a row below the block takes slot w + i for the first
-// interchange i that names it.
-constexpr int SWP_COLS = 64;
-constexpr size_t SWP_LDS = (size_t)2 * PNB * SWP_COLS * sizeof(float);
-__global__ void __launch_bounds__(SWP_COLS)
+// Row interchanges of rows j..j+w-1 (ipiv, applied in order, LAPACK laswp
+// semantics) on every column outside the panel.
+constexpr int SWP_COLS = 64;       // columns per workgroup
+constexpr int SWP_THREADS = 256;   // 4 waves: wave v moves affected rows v, v+4, ...
+constexpr int SWP_MAXR = 2 * PNB;  // affected rows: the panel rows and at most w others
+// The w interchanges compose into one permutation of at most 2w rows: the
+// affected positions are the panel rows 0..w-1 and every pivot row beyond
+// them.  Position p receives the old row sigma(p), sigma = tau_0 o tau_1 o
+// ... o tau_{w-1} (tau_i swaps i and ipiv[i]); each thread evaluates sigma
+// for its positions by applying the transpositions in reverse order.  Then
+// every affected row of the workgroup's 64 columns is loaded (coalesced
+// 256-byte row segments, many loads in flight), all loads complete before
+// the barrier, and the rows are stored at their new positions.
+__global__ void __launch_bounds__(SWP_THREADS)
 laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *ipiv) {
-    extern __shared__ float T[];  // [2 * PNB][SWP_COLS]
-    __shared__ int sp[PNB], slot[PNB];
-    const int l = threadIdx.x;
-    for (int i = l; i < w; i += SWP_COLS) {
+    __shared__ int sp[PNB], dpos[SWP_MAXR], spos[SWP_MAXR];
+    __shared__ int s_nd;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int i = t; i < w; i += SWP_THREADS) {
         const int64_t q = ipiv[j + i] - j;  // >= i for a valid factorisation
         sp[i] = (q >= i && q < n - j) ? (int)q : i;
     }
+    if (t == 0) s_nd = w;
     __syncthreads();
-    for (int i = l; i < w; i += SWP_COLS) {
-        const int q = sp[i];
-        int sl = q;
-        if (q >= w) {
-            int i0 = 0;
-            while (sp[i0] != q) ++i0;  // ends at i0 = i at the latest
-            sl = w + i0;
-        }
-        slot[i] = sl;
+    if (t < w) {
+        dpos[t] = t;
+        const int q = sp[t];
+        bool first = q >= w;
+        for (int k = 0; k < t && first; ++k) first = sp[k] != q;
+        if (first) dpos[atomicAdd(&s_nd, 1)] = q;
     }
     __syncthreads();
-    int64_t col = (int64_t)blockIdx.x * SWP_COLS + l;
+    const int nd = s_nd;
+    for (int e = t; e < nd; e += SWP_THREADS) {
+        int pos = dpos[e];
+        for (int i = w - 1; i >= 0; --i) {
+            const int q = sp[i];
+            pos = (pos == i) ? q : ((pos == q) ? i : pos);
+        }
+        spos[e] = pos;
+    }
+    __syncthreads();
+    int64_t col = (int64_t)blockIdx.x * SWP_COLS + lane;
     if (col >= j) col += w;
-    if (col >= n) return;
-#pragma unroll 8
-    for (int i = 0; i < w; ++i) T[i * SWP_COLS + l] = A[(j + i) * lda + col];
-#pragma unroll 8
-    for (int i = 0; i < w; ++i)
-        if (slot[i] == w + i) T[(w + i) * SWP_COLS + l] = A[(j + sp[i]) * lda + col];
-    for (int i = 0; i < w; ++i) {
-        const int q = slot[i];
-        if (q != i) {
-            const float x = T[i * SWP_COLS + l];
-            T[i * SWP_COLS + l] = T[q * SWP_COLS + l];
-            T[q * SWP_COLS + l] = x;
-        }
+    const bool ok = col < n;
+    constexpr int PER = SWP_MAXR / 4;   // rows per wave
+    float v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = wv + 4 * k;
+        v[k] = (ok && e < nd) ? A[(j + spos[e]) * lda + col] : 0.0f;
     }
-#pragma unroll 8
-    for (int i = 0; i < w; ++i) A[(j + i) * lda + col] = T[i * SWP_COLS + l];
-    for (int i = 0; i < w; ++i)
-        if (slot[i] == w + i) A[(j + sp[i]) * lda + col] = T[(w + i) * SWP_COLS + l];
+    // every load of the workgroup has returned before any row is overwritten
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = wv + 4 * k;
+        if (ok && e < nd) A[(j + dpos[e]) * lda + col] = v[k];
+    }
 }
 
 // U12 = L11^{-1} A12 (unit lower L11, jb x jb).  Column-oriented forward
@@ -383,8 +394,6 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
     if (!attr) {
         BFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)TRSM_LDS));
-        BFX_HIP(hipFuncSetAttribute((const void *)laswp_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)SWP_LDS));
         attr = true;
     }
     BFX_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
@@ -401,8 +410,8 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
                                            args, 0, s));
         const int64_t others = n - jb;
         if (others > 0) {
-            hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_COLS),
-                               SWP_LDS, s, A, lda, n, j, jb, ipiv);
+            hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_THREADS),
+                               0, s, A, lda, n, j, jb, ipiv);
             BFX_LAUNCH_CHECK("laswp_kernel");
         }
         const int64_t rest = n - j - jb;
