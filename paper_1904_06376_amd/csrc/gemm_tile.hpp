@@ -69,6 +69,28 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
     return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// Output tiles that one workgroup of a persistent launch computes back to
+// back: logical indices first, first + stride, ... (count of them) of a
+// problem with tiles_m x tiles_n tiles, each mapped to its output tile as a
+// one-tile-per-workgroup launch maps its workgroup index (XCD-aware remap,
+// then 8 tile rows per group, column-major inside the group).
+struct TileSeq {
+    int first, stride, count, total, tiles_m, tiles_n;
+};
+
+__device__ __forceinline__ void seq_tile(const TileSeq &q, int k, int &tm, int &tn) {
+    const int bid = q.first + k * q.stride;
+    const int qq = q.total / 8, r = q.total % 8;
+    const int xcd = bid % 8, slot = bid / 8;
+    const int id = (xcd < r) ? xcd * (qq + 1) + slot : r * (qq + 1) + (xcd - r) * qq + slot;
+    const int group = id / (8 * q.tiles_n);
+    const int first_m = group * 8;
+    const int gsz = (q.tiles_m - first_m < 8) ? q.tiles_m - first_m : 8;
+    const int in_g = id - group * 8 * q.tiles_n;
+    tm = first_m + in_g % gsz;
+    tn = in_g / gsz;
+}
+
 // LDS bytes one tile call needs.
 template <int V, int BM, int BN>
 constexpr size_t tile_lds_bytes() {
@@ -105,10 +127,10 @@ __device__ __forceinline__ int swz_off(int n, int k) {
 // of v_mfma_f32_16x16x32_bf16: lane holds column lane%16, rows 4*(lane/16) +
 // 0..3 of each 16 x 16 tile.  X = hi + lo (the largest bin added last), then
 // C = alpha X (beta == 0: C not read) or fma(alpha, X, beta C), or, for
-// split-K, the hi and lo partial sums.  With beta != 0 the C values of a
-// 16-row band are all loaded before the band's first store, so those loads
-// are in flight together instead of each waiting for the previous store.
-template <int TM, int TN>
+// split-K, the hi and lo partial sums.  With beta != 0 the C values of CB
+// 16-row bands are all loaded before their first store, so those loads are
+// in flight together instead of each waiting for the previous store.
+template <int TM, int TN, int CB = TM>
 __device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32x4 (&hi)[TM][TN],
                                               const bfx_f32x4 (&lo)[TM][TN], int64_t row0,
                                               int64_t col0, int kg, int r16, int64_t split) {
@@ -143,25 +165,32 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32
                 }
         return;
     }
-    // one 16-row band at a time: its TN*4 loads in flight together
+    // CB 16-row bands at a time: all their C values are loaded before the
+    // first store, so that those loads are in flight together
+    static_assert(TM % CB == 0, "bands per batch must divide the bands");
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        float cv[TN][4];
+    for (int i0 = 0; i0 < TM; i0 += CB) {
+        float cv[CB][TN][4];
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int ii = 0; ii < CB; ++ii)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t row = row_of(i, e), col = col_of(j);
-                cv[j][e] = (row < p.M && col < p.N) ? p.C[row * p.ldc + col] : 0.0f;
-            }
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t row = row_of(i0 + ii, e), col = col_of(j);
+                    cv[ii][j][e] = (row < p.M && col < p.N) ? p.C[row * p.ldc + col] : 0.0f;
+                }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t row = row_of(i, e), col = col_of(j);
-                if (row >= p.M || col >= p.N) continue;
-                p.C[row * p.ldc + col] = fmaf(p.alpha, hi[i][j][e] + lo[i][j][e], p.beta * cv[j][e]);
-            }
+        for (int ii = 0; ii < CB; ++ii)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t row = row_of(i0 + ii, e), col = col_of(j);
+                    if (row >= p.M || col >= p.N) continue;
+                    p.C[row * p.ldc + col] =
+                        fmaf(p.alpha, hi[i0 + ii][j][e] + lo[i0 + ii][j][e], p.beta * cv[ii][j][e]);
+                }
     }
 }
 
@@ -380,10 +409,12 @@ __device__ __forceinline__ int bcol_row(int n) { return (n & ~3) | ((n & 3) ^ ((
 // store the planes.  Every SIMD thus runs one wave of each kind and overlaps
 // the split's VALU work with the other wave's matrix work.  Both kinds pass
 // the same barrier once per K-step; the LDS planes are double-buffered.
-template <int V, int BM, int BN, int NST_ = 0>
+// ECB: 16-row bands whose C values the epilogue loads together (0: all of
+// them; fewer where the caller's loop keeps more registers live).
+template <int V, int BM, int BN, int NST_ = 0, bool PERSIST = false, int ECB = 0>
 __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, int64_t n0,
                                                int64_t kb, int64_t ke, int64_t split,
-                                               uint16_t *smem) {
+                                               uint16_t *smem, const TileSeq *seq = nullptr) {
     using PR = Prods<V>;
     constexpr int P = PR::P;
     constexpr bool SWZ = BM == 128;                     // swz_off layout (else padded rows)
@@ -395,6 +426,9 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     static_assert(BM == BN && KPT % 8 == 0, "square tiles with >= 8 k values per helper thread");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int KT = (int)ceil_div(ke - kb, (int64_t)BK);
+    // K-steps of the whole stream: one tile, or every tile of the sequence
+    // (persistent launch: all tiles full, K a multiple of BK, no split-K)
+    const int S = PERSIST ? seq->count * KT : KT;
 
     if (wave < 4) {
         // ------------------------------ MFMA waves ------------------------------
@@ -418,7 +452,8 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         for (int i = 0; i < TM; ++i)
             aoff[i] = SWZ ? swz_off(wm * (BM / 2) + i * 16 + r16, kg * 8)
                           : (wm * (BM / 2) + i * 16 + r16) * FLDK + kg * 8;
-        for (int s = 0; s < KT; ++s) {
+        int tile_k = 0, step_in_tile = 0;   // persistent: tile and step within it
+        for (int s = 0; s < S; ++s) {
             __syncthreads();  // buffer s&1 holds step s
             const uint16_t *base = smem + (s & 1) * P * PLANE;
             bfx_bf16x8 af[P][TM];
@@ -454,9 +489,29 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                                                                                 hi[i][j], 0, 0, 0);
                 }
             }
+            if constexpr (PERSIST) {
+                if (++step_in_tile == KT) {
+                    // last K-step of this tile: its epilogue, overlapped with the
+                    // helpers' loads and split of the next tile's first steps
+                    int tm, tn;
+                    seq_tile(*seq, tile_k, tm, tn);
+                    tile_epilogue<TM, TN, ECB ? ECB : TM>(p, hi, lo, (int64_t)tm * BM + wm * (BM / 2),
+                                          (int64_t)tn * BN + wn * (BN / 2), kg, r16, 0);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) {
+                            hi[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+                            lo[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+                        }
+                    step_in_tile = 0;
+                    ++tile_k;
+                }
+            }
         }
         __syncthreads();  // matches the helpers' final barrier
-        tile_epilogue<TM, TN>(p, hi, lo, m0 + wm * (BM / 2), n0 + wn * (BN / 2), kg, r16, split);
+        if constexpr (!PERSIST)
+            tile_epilogue<TM, TN, ECB ? ECB : TM>(p, hi, lo, m0 + wm * (BM / 2), n0 + wn * (BN / 2), kg, r16, split);
         return;
     }
 
@@ -487,10 +542,11 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     // Buffer resources over exactly the elements of this tile's A rows and B
     // columns (the range check is a second guard; no load leaves the range).
     const int lda = (int)p.lda, ldb = (int)p.ldb;
-    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+    __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(p.A + m0 * p.lda + kb), (short)0, ((rows - 1) * lda + klen) * 4, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+    __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(p.B + kb * p.ldb + n0), (short)0, ((klen - 1) * ldb + cols) * 4, 0x00020000);
+    int rsrc_tile = -1;   // persistent: tile whose resources rA, rB hold (uniform)
     int voA[AR];                            // byte offset of (row, k = 0) of each A row
 #pragma unroll
     for (int i = 0; i < AR; ++i) voA[i] = ((ar0 + 32 * i < rows) ? (ar0 + 32 * i) * lda : 0) * 4;
@@ -503,6 +559,20 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         float ra[NST][KPT], rb[NST][KPT];   // ra[.][4i + j]: row ar0+32i, k = 4ac + j
         auto issue = [&](int st, int step) {
             if constexpr (FULL) {
+                if constexpr (PERSIST) {
+                    // step of the stream -> tile of the sequence and its K-step
+                    const int tk = step / KT;
+                    step -= tk * KT;
+                    if (tk != rsrc_tile) {
+                        int tm, tn;
+                        seq_tile(*seq, tk, tm, tn);
+                        rA = __builtin_amdgcn_make_buffer_rsrc((void *)(p.A + (int64_t)tm * BM * p.lda), (short)0,
+                                                               ((BM - 1) * lda + klen) * 4, 0x00020000);
+                        rB = __builtin_amdgcn_make_buffer_rsrc((void *)(p.B + (int64_t)tn * BN), (short)0,
+                                                               ((klen - 1) * ldb + BN) * 4, 0x00020000);
+                        rsrc_tile = tk;
+                    }
+                }
                 // per-lane part (row, k chunk) in the VGPR offset, the step in
                 // the uniform SGPR offset
                 const int soA = step * BK * 4;
@@ -623,8 +693,8 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         // workgroups per CU).  The steady-state loop has no conditional
         // loads, so every stage is consumed exactly NST-1 full stages behind
         // the newest loads.
-        if (KT > 0) {
-            const int last = KT - 1;
+        if (S > 0) {
+            const int last = S - 1;
             auto lim = [&](int s) { return s < last ? s : last; };
             auto step_of = [&](int st, int s) {
                 const uint32_t f = stage(st, s & 1, s);
@@ -635,7 +705,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
             step_of(0, 0);
             issue(0, lim(NST));
             int t = 0;
-            for (; t + NST < KT; t += NST) {
+            for (; t + NST < S; t += NST) {
 #pragma unroll
                 for (int u = 1; u <= NST; ++u) {
                     __syncthreads();
@@ -643,18 +713,19 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                     issue(u % NST, lim(t + u + NST));
                 }
             }
-            // t % NST == 0 and t + NST >= KT: steps t+1 .. KT-1 remain
+            // t % NST == 0 and t + NST >= S: steps t+1 .. S-1 remain
 #pragma unroll
             for (int u = 1; u < NST; ++u) {
-                if (t + u < KT) {
+                if (t + u < S) {
                     __syncthreads();
                     step_of(u, t + u);
                 }
             }
-            __syncthreads();    // barrier KT-1
+            __syncthreads();    // barrier S-1
         }
     };
-    if (full) helpers(std::true_type{});
+    if constexpr (PERSIST) helpers(std::true_type{});   // every tile of the stream is full
+    else if (full) helpers(std::true_type{});
     else helpers(std::false_type{});
     __syncthreads();
 }

@@ -264,3 +264,29 @@ def test_gemm_long_k_splitk(bfx, orc, cancel):
     o = orc.gemm_entries(6, A, B, r, c)
     C6 = host(bfx.gemm(6, dev(A), dev(B)))
     assert np.all(np.abs(C6[r, c] - o) <= 2 * gemm_bound(6, K) * zh[r, c])
+
+
+@pytest.mark.parametrize("variant", [3, 6, 9])
+def test_gemm_persistent_equals_one_tile_launch(bfx, variant):
+    """Problems made of full 128 x 128 tiles take the persistent launch; with
+    17 x 17 = 289 tiles some workgroups compute two tiles back to back.  Four
+    more columns make the tiling partial, which takes the one-tile-per-
+    workgroup launch with the same tile origins and per-tile arithmetic: the
+    common columns must be bitwise equal, for beta = 0 and beta != 0, and the
+    persistent result must meet the bound of the exact product."""
+    M, K = 2176, 96
+    A = workloads.normal((M, K), 61)
+    B = workloads.normal((K, M + 4), 62)
+    C0 = workloads.normal((M, M + 4), 63)
+    tA, tB = dev(A), dev(B)
+    for alpha, beta in ((1.0, 0.0), (-1.0, 1.0)):
+        Cp = dev(C0[:, :M])
+        bfx.gemm(variant, tA, tB[:, :M], Cp, alpha=alpha, beta=beta)
+        Cr = dev(C0)
+        bfx.gemm(variant, tA, tB, Cr, alpha=alpha, beta=beta)
+        np.testing.assert_array_equal(host(Cp), host(Cr)[:, :M])
+    rows = np.arange(0, M, 97)
+    Cp = host(bfx.gemm(variant, tA, tB[:, :M]))
+    z = ref64(A[rows], B[:, :M])
+    bnd = gemm_bound(variant, K) * absref(A[rows], B[:, :M])
+    assert np.all(np.abs(Cp[rows] - z) <= bnd)
