@@ -72,9 +72,9 @@ persistent_fast_kernel(const bfx_gemm_desc *__restrict__ probs,
         const bfx_gemm_desc d = probs[t.prob];
         const GemmParams p = desc_params(d);
         if (WIDE && V != 9 && t.cfg == CFG_F128)
-            gemm_tile_fast<V, 128, 128, 0, false, 1>(p, (int64_t)t.tm * 128, (int64_t)t.tn * 128, 0, d.K, 0, smem);
+            gemm_tile_fast<V, 128, 128>(p, (int64_t)t.tm * 128, (int64_t)t.tn * 128, 0, d.K, 0, smem);
         else
-            gemm_tile_fast<V, 64, 64, 0, false, 1>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
+            gemm_tile_fast<V, 64, 64>(p, (int64_t)t.tm * 64, (int64_t)t.tn * 64, 0, d.K, 0, smem);
     }
 }
 

@@ -410,8 +410,9 @@ __device__ __forceinline__ int bcol_row(int n) { return (n & ~3) | ((n & 3) ^ ((
 // the split's VALU work with the other wave's matrix work.  Both kinds pass
 // the same barrier once per K-step; the LDS planes are double-buffered.
 // ECB: 16-row bands whose C values the epilogue loads together (0: all of
-// them; fewer where the caller's loop keeps more registers live).
-template <int V, int BM, int BN, int NST_ = 0, bool PERSIST = false, int ECB = 0>
+// them).  One band by default: more raise the kernel's register count, which
+// cost the 8192^3 x6 launch 3%.
+template <int V, int BM, int BN, int NST_ = 0, bool PERSIST = false, int ECB = 1>
 __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, int64_t n0,
                                                int64_t kb, int64_t ke, int64_t split,
                                                uint16_t *smem, const TileSeq *seq = nullptr) {
