@@ -13,7 +13,8 @@
 //                    waits (bounded) on the completion flags of the blocks it
 //                    depends on, adds their contribution, solves its 128 x 128
 //                    diagonal block in one wave and publishes its flag;
-//   perm_kernel      the row permutation of ipiv, composed once per solve.
+//   perm_kernel      the row permutation of ipiv, composed once per solve
+//                    (every position evaluated in parallel).
 // The host reads |r|_inf and |x|_inf once per step to apply the stopping rule.
 #include <algorithm>
 #include <cmath>
@@ -80,28 +81,29 @@ __global__ void __launch_bounds__(256) zero_i32(int32_t *p, int64_t n) {
         p[i] = 0;
 }
 
-// Compose the interchanges ipiv[0..n) into perm: (P v)[i] = v[perm[i]].
-// Sequential by nature (each interchange may move an earlier one's row); one
-// thread applies them to an LDS copy when it fits.
-__global__ void __launch_bounds__(64) perm_kernel(const int32_t *ipiv, int64_t n, int32_t *perm,
-                                                  int use_lds) {
+// Compose the interchanges ipiv[0..n) into perm: (P v)[i] = v[perm[i]], that
+// is perm[i] = tau_0(tau_1(...tau_{n-1}(i))) with tau_k the swap of k and
+// ipiv[k] (applying the swaps to v in order k = 0, 1, ... gives exactly that).
+// Each thread evaluates the composition for its own position by scanning the
+// interchanges backwards (staged in LDS when they fit), so the positions are
+// computed in parallel instead of replaying the swaps one after another.
+__global__ void __launch_bounds__(256) perm_kernel(const int32_t *ipiv, int64_t n, int32_t *perm,
+                                                   int use_lds) {
     extern __shared__ int32_t sp[];
-    int32_t *v = use_lds ? sp : perm;
-    for (int64_t i = threadIdx.x; i < n; i += 64) v[i] = (int32_t)i;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int64_t i = 0; i < n; ++i) {
-            const int32_t p = ipiv[i];
-            if (p != i) {
-                const int32_t t = v[i];
-                v[i] = v[p];
-                v[p] = t;
-            }
-        }
+    const int32_t *iv = ipiv;
+    if (use_lds) {
+        for (int64_t i = threadIdx.x; i < n; i += 256) sp[i] = ipiv[i];
+        __syncthreads();
+        iv = sp;
     }
-    __syncthreads();
-    if (use_lds)
-        for (int64_t i = threadIdx.x; i < n; i += 64) perm[i] = v[i];
+    const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (pos >= n) return;
+    int32_t p = (int32_t)pos;
+    for (int32_t i = (int32_t)n - 1; i >= 0; --i) {
+        const int32_t q = iv[i];
+        p = (p == i) ? q : ((p == q) ? i : p);
+    }
+    perm[pos] = p;
 }
 
 // w[i] = (float)(src[perm[i]] / div)   (src FP64)
@@ -481,7 +483,8 @@ static int compose_perm(int64_t n, const int32_t *ipiv, const IrWs &w, hipStream
             attr = lds;
         }
     }
-    hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(64), use_lds ? lds : 0, s, ipiv, n, w.perm, use_lds);
+    hipLaunchKernelGGL(perm_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), use_lds ? lds : 0, s, ipiv, n,
+                       w.perm, use_lds);
     BFX_LAUNCH_CHECK("perm_kernel");
     return BFX_OK;
 }

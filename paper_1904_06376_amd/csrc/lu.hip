@@ -2,9 +2,10 @@
 // paper's split-BF16 LU, Sec. I and Sec. IV-A).  For every panel of up to 128
 // columns:
 //   1. panel_kernel  - FP32 factorisation of the (n-j) x jb panel.  The panel
-//      rows are spread over G co-resident workgroups, 256 rows each, held in
-//      LDS for the whole panel.  Per column: each workgroup finds its local
-//      arg-max (wave shuffles + LDS) and publishes the candidate row and a
+//      rows are spread over G co-resident workgroups, 512 rows each, one row
+//      per thread held in registers for the whole panel.  Per column: each
+//      workgroup finds its local arg-max (wave shuffles + LDS) and
+//      publishes the candidate row and a
 //      64-bit header {column tag, |candidate|}; every workgroup then polls the
 //      G headers of that column, picks the same pivot (largest magnitude,
 //      lowest row on ties, as ISAMAX: workgroups own increasing row ranges),
@@ -67,10 +68,6 @@ struct PanelArgs {
 };
 }  // namespace
 
-// LDS row stride of the panel: a multiple of 4 floats (16-byte row updates)
-// with an odd number of 16-byte chunks, so that the 16 lanes of a 16-byte
-// access phase hit distinct banks.
-__host__ __device__ constexpr int panel_ld(int w) { return 4 * (((w + 3) / 4) | 1); }
 
 __device__ __forceinline__ void better(float &v, int &i, float v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
