@@ -267,14 +267,16 @@ def test_gemm_long_k_splitk(bfx, orc, cancel):
 
 
 @pytest.mark.parametrize("variant", [3, 6, 9])
-def test_gemm_persistent_equals_one_tile_launch(bfx, variant):
-    """Problems made of full 128 x 128 tiles take the persistent launch; with
-    17 x 17 = 289 tiles some workgroups compute two tiles back to back.  Four
-    more columns make the tiling partial, which takes the one-tile-per-
-    workgroup launch with the same tile origins and per-tile arithmetic: the
-    common columns must be bitwise equal, for beta = 0 and beta != 0, and the
-    persistent result must meet the bound of the exact product."""
-    M, K = 2176, 96
+@pytest.mark.parametrize("K", [96, 160])
+def test_gemm_persistent_equals_one_tile_launch(bfx, variant, K):
+    """Problems made of full 128 x 128 tiles take the persistent launch (64 x
+    64 tiles for K <= 128, 128 x 128 above); with 2176 x 2176 outputs some
+    workgroups compute several tiles back to back.  Four more columns make
+    the tiling partial, which takes the one-tile-per-workgroup launch: every
+    output element is accumulated in the same order, so the common columns
+    must be bitwise equal, for beta = 0 and beta != 0, and the persistent
+    result must meet the bound of the exact product."""
+    M = 2176
     A = workloads.normal((M, K), 61)
     B = workloads.normal((K, M + 4), 62)
     C0 = workloads.normal((M, M + 4), 63)
