@@ -31,6 +31,22 @@ gemm_split_kernel(GemmParams p) {
     gemm_tile<V, BM, BN, WM, WN>(p, m0, n0, kb, ke, split, smem);
 }
 
+// Output tile of tile index t (after the XCD-aware remap): groups of 4 tile
+// columns, row-major inside the group, so that an XCD's workgroups sweep
+// down the same B panels (measured at 8192^3 x6, average of 6 launches:
+// 5.52-5.55 ms vs 5.60-5.82 grouping 4 tile rows and 5.73-5.81 grouping 8
+// tile rows).
+__device__ __forceinline__ void column_grouped_tile(int64_t t, int64_t tiles_m, int64_t tiles_n,
+                                                    int64_t &tm, int64_t &tn) {
+    constexpr int GROUP = 4;
+    const int64_t group = t / (GROUP * tiles_m);
+    const int64_t first_n = group * GROUP;
+    const int64_t gsz = (tiles_n - first_n < GROUP) ? tiles_n - first_n : GROUP;
+    const int64_t in_g = t % (GROUP * tiles_m);
+    tn = first_n + in_g % gsz;
+    tm = in_g / gsz;
+}
+
 // Wave-specialised tiles (see gemm_tile_fast), 512 threads: 4 MFMA + 4
 // helper waves.
 template <int V, int BM, int BN>
@@ -42,19 +58,73 @@ gemm_fast_kernel(GemmParams p) {
     const int64_t total = tiles * p.splits;
     const int64_t id = xcd_remap(blockIdx.x, total);
     const int64_t split = id / tiles;
-    const int64_t t = id % tiles;
-    // grouped order, 4 tile rows per group (measured at 8192^3 x6: 5.54-5.58
-    // ms best vs 5.64-5.78 with 8 rows, 5.67-5.69 with 2, 5.70-5.89 with 16)
-    constexpr int GROUP = 4;
-    const int64_t group = t / (GROUP * tiles_n);
-    const int64_t first_m = group * GROUP;
-    const int64_t gsz = (tiles_m - first_m < GROUP) ? tiles_m - first_m : GROUP;
-    const int64_t in_g = t % (GROUP * tiles_n);
-    const int64_t m0 = (first_m + in_g % gsz) * BM;
-    const int64_t n0 = (in_g / gsz) * BN;
+    int64_t tm, tn;
+    column_grouped_tile(id % tiles, tiles_m, tiles_n, tm, tn);
     const int64_t kb = split * p.k_per_split;
     const int64_t ke = (kb + p.k_per_split < p.K) ? kb + p.k_per_split : p.K;
-    gemm_tile_fast<V, BM, BN>(p, m0, n0, kb, ke, split, smem);
+    gemm_tile_fast<V, BM, BN>(p, tm * BM, tn * BN, kb, ke, split, smem);
+}
+
+// Split of one operand into the pre-split block layout of gemm_tile_planes
+// (Sec. II-A, exact integer conversion for every element).  Workgroup b
+// writes block b = r * KS + s: rows 128 r .. of the operand (A rows; for
+// TRANS, columns of a K x R row-major B) and k = 32 s .. 32 s + 31, zeros
+// outside R x K.  Each thread converts 16 consecutive k of one row and
+// writes two 16-byte chunks per plane.
+template <int P, bool TRANS>
+__global__ void __launch_bounds__(256)
+split_blocks_kernel(const float *__restrict__ X, int64_t ld, int64_t R, int64_t K, int KS,
+                    uint16_t *__restrict__ out, int64_t plane, bool vec) {
+    const int64_t b = blockIdx.x;
+    const int64_t r = b / KS, ks = b % KS;
+    const int t = threadIdx.x;
+    const int n = TRANS ? (t & 127) : (t >> 1);
+    const int half = TRANS ? (t >> 7) : (t & 1);
+    const int64_t row = r * 128 + n;
+    const int64_t k0 = ks * BK + 16 * half;
+    float v[16];
+    if (!TRANS && vec && row < R && k0 + 16 <= K) {
+        const float4 *src = reinterpret_cast<const float4 *>(X + row * ld + k0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 f = src[i];
+            v[4 * i] = f.x; v[4 * i + 1] = f.y; v[4 * i + 2] = f.z; v[4 * i + 3] = f.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t k = k0 + i;
+            v[i] = (row < R && k < K) ? (TRANS ? X[k * ld + row] : X[row * ld + k]) : 0.0f;
+        }
+    }
+    uint32_t w[3][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        uint32_t x[3], y[3];
+        split3_exact(v[2 * i], x[0], x[1], x[2]);
+        split3_exact(v[2 * i + 1], y[0], y[1], y[2]);
+#pragma unroll
+        for (int pl = 0; pl < P; ++pl) w[pl][i] = x[pl] | (y[pl] << 16);
+    }
+    uint16_t *blk = out + b * 4096;
+#pragma unroll
+    for (int pl = 0; pl < P; ++pl)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            *reinterpret_cast<uint4 *>(blk + pl * plane + swz_off(n, (2 * half + c) * 8)) =
+                make_uint4(w[pl][4 * c], w[pl][4 * c + 1], w[pl][4 * c + 2], w[pl][4 * c + 3]);
+}
+
+// GEMM on pre-split operands (see gemm_tile_planes): one 128 x 128 tile per
+// workgroup, the tile order of gemm_fast_kernel.
+template <int V>
+__global__ void __launch_bounds__(512, 1)
+gemm_planes_kernel(GemmParams p, PlaneArgs q) {
+    extern __shared__ __align__(16) uint16_t smem[];
+    const int64_t tiles_m = ceil_div(p.M, 128), tiles_n = ceil_div(p.N, 128);
+    int64_t tm, tn;
+    column_grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, tm, tn);
+    gemm_tile_planes<V>(p, q, tm, tn, smem);
 }
 
 // Persistent wave-specialised launch for problems made of full 128 x 128
@@ -185,6 +255,69 @@ size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K) {
     return (size_t)(s + split_groups(s)) * 2 * (size_t)M * (size_t)N * sizeof(float);
 }
 
+// Pre-split path (gemm_tile_planes): no split-K, at least 256 output tiles of
+// 128 x 128 and K >= 512, where one O(N^2) split pass per operand is small
+// against the products.  It runs when the caller's workspace holds the
+// planes: P * (M + N) * K BF16 values, M and N padded to 128, K to 32.
+// BFX_GEMM_PLANES=0 in the environment disables it (tests compare the two).
+static const bool g_no_planes = [] {
+    const char *e = getenv("BFX_GEMM_PLANES");
+    return e && e[0] == '0';
+}();
+
+static int prods_p(int variant) { return variant == 1 ? 1 : variant == 3 ? 2 : 3; }
+
+static bool planes_wanted(int64_t M, int64_t N, int64_t K) {
+    const int64_t KS = ceil_div(K, BK);
+    return !g_no_planes && ceil_div(M, 128) * ceil_div(N, 128) >= 256 && K >= 512 &&
+           choose_splits(M, N, K, 128, 128) == 1 && KS * 8192 < (int64_t(1) << 31) &&
+           ceil_div(M, 128) * ceil_div(N, 128) < (int64_t(1) << 31) &&
+           ceil_div(M, 128) * KS < (int64_t(1) << 31) && ceil_div(N, 128) * KS < (int64_t(1) << 31);
+}
+
+static size_t planes_bytes(int variant, int64_t M, int64_t N, int64_t K) {
+    return (size_t)prods_p(variant) * (size_t)(ceil_div(M, 128) + ceil_div(N, 128)) * 128 *
+           (size_t)(ceil_div(K, BK) * BK) * sizeof(uint16_t);
+}
+
+static size_t gemm_ws_bytes_public(int variant, int64_t M, int64_t N, int64_t K) {
+    const size_t s = gemm_ws_bytes(variant, M, N, K);
+    const size_t pl = planes_wanted(M, N, K) ? planes_bytes(variant, M, N, K) : 0;
+    return s > pl ? s : pl;
+}
+
+template <int V>
+static int launch_planes(const GemmParams &p, void *ws, hipStream_t s) {
+    constexpr int P = Prods<V>::P;
+    const int KS = (int)ceil_div(p.K, BK);
+    const int64_t rm = ceil_div(p.M, 128), rn = ceil_div(p.N, 128);
+    PlaneArgs q;
+    q.KS = KS;
+    q.a_plane = rm * KS * 4096;
+    q.b_plane = rn * KS * 4096;
+    uint16_t *pa = (uint16_t *)ws;
+    uint16_t *pb = pa + P * q.a_plane;
+    q.A = pa;
+    q.B = pb;
+    const bool vecA = ((uintptr_t)p.A % 16 == 0) && (p.lda % 4 == 0);
+    hipLaunchKernelGGL((split_blocks_kernel<P, false>), dim3((unsigned)(rm * KS)), dim3(256), 0, s,
+                       p.A, p.lda, p.M, p.K, KS, pa, q.a_plane, vecA);
+    BFX_LAUNCH_CHECK("split_blocks_kernel launch");
+    hipLaunchKernelGGL((split_blocks_kernel<P, true>), dim3((unsigned)(rn * KS)), dim3(256), 0, s,
+                       p.B, p.ldb, p.N, p.K, KS, pb, q.b_plane, false);
+    BFX_LAUNCH_CHECK("split_blocks_kernel launch");
+    const size_t lds = planes_lds_bytes<V>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        BFX_HIP(hipFuncSetAttribute((const void *)gemm_planes_kernel<V>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((gemm_planes_kernel<V>), dim3((unsigned)(rm * rn)), dim3(512), lds, s, p, q);
+    BFX_LAUNCH_CHECK("gemm_planes_kernel launch");
+    return BFX_OK;
+}
+
 template <int V, int BM, int BN>
 static int launch_fast(const GemmParams &p, hipStream_t s) {
     const size_t lds = fast_lds_bytes<V, BM, BN>();
@@ -293,6 +426,16 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
     const int groups = split_groups(p.splits);
     if (p.splits > 1 && (size_t)(p.splits + groups) * 2 * M * N * sizeof(float) > ws_bytes)
         return -14;
+    if (p.splits == 1 && ws && (uintptr_t)ws % 16 == 0 && planes_wanted(M, N, K) &&
+        ws_bytes >= planes_bytes(variant, M, N, K)) {
+        switch (variant) {
+            case 1: return launch_planes<1>(p, ws, stream);
+            case 3: return launch_planes<3>(p, ws, stream);
+            case 6: return launch_planes<6>(p, ws, stream);
+            case 9: return launch_planes<9>(p, ws, stream);
+            default: return -1;
+        }
+    }
     int rc;
     switch (variant) {
         case 1: rc = dispatch_variant<1>(p, BM, BN, stream); break;
@@ -323,7 +466,7 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
 
 extern "C" size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
-    return bfx::gemm_ws_bytes(variant, M, N, K);
+    return bfx::gemm_ws_bytes_public(variant, M, N, K);
 }
 
 extern "C" int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,

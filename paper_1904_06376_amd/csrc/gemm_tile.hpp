@@ -731,4 +731,166 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Pre-split operands (Sec. II-A done once per operand, O(N^2), before the
+// O(N^3) products).  split_blocks_kernel writes each operand's P BF16 planes
+// as whole 128 x 32 blocks of 8 KiB, every block already in the swz_off order
+// of the LDS staging above and zero-padded to whole blocks: block (r, s) of a
+// plane holds rows 128 r .. 128 r + 127 of A (columns of B) and k = 32 s ..
+// 32 s + 31, at element (r * KS + s) * 4096.  The tile below then fills its
+// LDS with plain 16-byte direct-to-LDS loads (no registers, no split
+// arithmetic on the critical path), and its MFMA waves run the instruction
+// sequence of gemm_tile_fast on the same LDS image, so both give the same bits.
+struct PlaneArgs {
+    const uint16_t *A, *B;     // P planes each
+    int64_t a_plane, b_plane;  // elements per plane
+    int KS;                    // K blocks of 32 (K padded to a multiple of 32)
+};
+
+// LDS stages of the pre-split tile: as many 128 x 128 x 32 stages of P
+// planes as fit the 160 KiB of a CU, at most four.
+template <int V>
+constexpr int planes_stages() { return Prods<V>::P == 3 ? 3 : 4; }
+
+template <int V>
+constexpr size_t planes_lds_bytes() {
+    return (size_t)planes_stages<V>() * Prods<V>::P * 2 * 128 * BK * sizeof(uint16_t);
+}
+
+// s_waitcnt with only the vector-memory count limited (gfx9 encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// 512 threads.  Waves 0-3: as in gemm_tile_fast (fragments from LDS, MFMAs,
+// epilogue).  Waves 4-7: direct-to-LDS loads, NS - 1 K-steps ahead into a
+// ring of NS stages; wave 4 + h moves the 1 KiB pieces 2h and 2h + 1 of every
+// 8 KiB block.  Barrier t starts MFMA step t (stage t % NS); right after it
+// the loaders refill stage (t - 1) % NS, which step t - 1 has finished
+// reading, with step t + NS - 1, and before barrier t + 1 they wait until
+// step t + 1's pieces have landed.
+template <int V>
+__device__ __forceinline__ void gemm_tile_planes(const GemmParams &p, const PlaneArgs &q,
+                                                 int64_t tm, int64_t tn, uint16_t *smem) {
+    using PR = Prods<V>;
+    constexpr int P = PR::P;
+    constexpr int NS = planes_stages<V>();
+    constexpr int BM = 128, BN = 128;
+    constexpr int PLANE = (BM + BN) * BK;               // A block, then B block
+    constexpr int TM = BM / 32, TN = BN / 32;
+    constexpr int NI = 4 * P;                           // loads per K-step per loader wave
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int S = q.KS;
+
+    if (wave < 4) {
+        const int wm = wave >> 1, wn = wave & 1;
+        bfx_f32x4 hi[TM][TN], lo[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                hi[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+                lo[i][j] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        const int r16 = lane & 15, kg = lane >> 4;
+        int boff[TN], aoff[TM];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) boff[j] = swz_off(BM + wn * (BN / 2) + j * 16 + r16, kg * 8);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) aoff[i] = swz_off(wm * (BM / 2) + i * 16 + r16, kg * 8);
+        int st = 0;
+        for (int s = 0; s < S; ++s) {
+            __syncthreads();  // stage st holds step s
+            const uint16_t *base = smem + st * P * PLANE;
+            st = (st + 1 == NS) ? 0 : st + 1;
+            bfx_bf16x8 af[P][TM];
+#pragma unroll
+            for (int pl = 0; pl < P; ++pl)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
+#pragma unroll
+            for (int jp = P - 1; jp >= 0; --jp) {
+                bfx_bf16x8 bf[TN];
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(base + jp * PLANE + boff[j]);
+#pragma unroll
+                for (int qq = 0; qq < PR::n; ++qq) {
+                    if (PR::bj[qq] != jp) continue;
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PR::ai[qq]][i], bf[j],
+                                                                                lo[i][j], 0, 0, 0);
+                }
+                if (jp == 0) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[j],
+                                                                                hi[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // matches the loaders' final barrier
+        tile_epilogue<TM, TN, 1>(p, hi, lo, tm * BM + wm * (BM / 2), tn * BN + wn * (BN / 2), kg, r16, 0);
+        return;
+    }
+
+    // ------------------------------ loader waves ------------------------------
+    const int h = wave - 4;
+    __amdgpu_buffer_rsrc_t rs[2 * P];   // blocks of plane pl: A at 2 pl, B at 2 pl + 1
+    const int range = q.KS * 8192;
+#pragma unroll
+    for (int pl = 0; pl < P; ++pl) {
+        rs[2 * pl] = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(q.A + pl * q.a_plane + tm * q.KS * 4096), (short)0, range, 0x00020000);
+        rs[2 * pl + 1] = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(q.B + pl * q.b_plane + tn * q.KS * 4096), (short)0, range, 0x00020000);
+    }
+    const int vo = lane * 16 + h * 2048;   // this lane's 16 bytes of piece 2h
+    typedef __attribute__((address_space(3))) void *lds_ptr;
+    auto issue = [&](int s, int stage) {
+        uint16_t *d = smem + stage * P * PLANE + h * 1024;
+#pragma unroll
+        for (int b = 0; b < 2 * P; ++b)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs[b], (lds_ptr)(d + b * 4096 + jj * 512), 16,
+                                                         vo + jj * 1024, s * 8192, 0, 0);
+    };
+    int ld_stage = 0;   // stage of the next step to load
+    for (int s = 0; s < NS - 1 && s < S; ++s) {
+        issue(s, ld_stage);
+        ld_stage = (ld_stage + 1 == NS) ? 0 : ld_stage + 1;
+    }
+    for (int t = 0; t < S; ++t) {
+        // steps t+1 .. t+NS-2 may still be in flight; step t must have landed
+        const int ahead = (S - 1 - t < NS - 2) ? S - 1 - t : NS - 2;
+        if constexpr (NS == 4) {
+            if (ahead == 2) wait_vmcnt<2 * NI>();
+            else if (ahead == 1) wait_vmcnt<NI>();
+            else wait_vmcnt<0>();
+        } else {
+            if (ahead == 1) wait_vmcnt<NI>();
+            else wait_vmcnt<0>();
+        }
+        // barrier t.  No fence: a workgroup release fence would wait for
+        // every direct-to-LDS load in flight (vmcnt(0)), including the newer
+        // steps'; the wait above already covers step t.
+        __builtin_amdgcn_s_barrier();
+        if (t + NS - 1 < S) {
+            issue(t + NS - 1, ld_stage);
+            ld_stage = (ld_stage + 1 == NS) ? 0 : ld_stage + 1;
+        }
+    }
+    __builtin_amdgcn_s_barrier();  // matches the MFMA waves' final barrier
+}
+
 }  // namespace bfx

@@ -45,4 +45,7 @@ def test_argument_errors_before_device_use():
     assert lib.bfx_split_f32(v, 8, 3, v, v, None, None) == -6
     assert lib.bfx_split_f32(None, 0, 3, None, None, None, None) == 0
     assert lib.bfx_gemm_ws_size(6, 64, 64, 1 << 20) > 0
-    assert lib.bfx_gemm_ws_size(6, 4096, 4096, 4096) == 0
+    assert lib.bfx_gemm_ws_size(6, 512, 512, 256) == 0
+    # pre-split planes: P BF16 planes of A and B, M and N padded to 128, K to 32
+    assert lib.bfx_gemm_ws_size(6, 4096, 4096, 4096) == 3 * (4096 + 4096) * 4096 * 2
+    assert lib.bfx_gemm_ws_size(3, 4000, 4100, 1000) == 2 * (4096 + 4224) * 1024 * 2

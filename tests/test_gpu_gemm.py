@@ -292,3 +292,41 @@ def test_gemm_persistent_equals_one_tile_launch(bfx, variant, K):
     z = ref64(A[rows], B[:, :M])
     bnd = gemm_bound(variant, K) * absref(A[rows], B[:, :M])
     assert np.all(np.abs(Cp[rows] - z) <= bnd)
+
+
+def _gemm_fused(bfx, variant, A, B, C, alpha, beta):
+    """bfx_gemm without a workspace: the in-kernel split (no pre-split planes)."""
+    from paper_1904_06376_amd.api import _stream
+    M, K = A.shape
+    N = B.shape[1]
+    rc = bfx.lib.bfx_gemm(variant, M, N, K, alpha, A.data_ptr(), K, B.data_ptr(), N, beta,
+                          C.data_ptr(), N, None, 0, _stream())
+    assert rc == 0
+
+
+@pytest.mark.parametrize("variant", [1, 3, 6, 9])
+@pytest.mark.parametrize("shape", [(2048, 2048, 512), (2085, 2148, 1000), (2176, 2048, 1536)])
+def test_gemm_presplit_equals_fused(bfx, variant, shape):
+    """With a workspace of bfx_gemm_ws_size bytes, problems of >= 256 output
+    tiles and K >= 512 split each operand once into BF16 planes (zero-padded
+    128 x 32 blocks) and run the products on them; without one, the split
+    happens inside the GEMM kernel.  Both split exactly (Sec. II-A) and
+    accumulate every output in the same order, so the results must be
+    bitwise equal, for beta = 0 and beta != 0, ragged M, N and K included,
+    and with zeros, subnormals, values near FLT_MAX, infinities and NaNs in
+    the operands."""
+    M, N, K = shape
+    A = workloads.normal((M, K), 71)
+    B = workloads.normal((K, N), 72)
+    A[3, :7] = [0.0, -0.0, 1e-39, -3e-41, 3.3e38, np.inf, 1e-30]
+    A[M - 1, K - 5:] = [np.nan, 2.0 ** -126, -2.0 ** -140, 1e38, 5.0]
+    B[:9, N - 1] = [np.inf, -np.inf, 0.0, 1e-40, 3.4e38, -3.4e38, 2.0 ** -130, 7.0, np.nan]
+    C0 = workloads.normal((M, N), 73)
+    assert bfx.gemm_ws_size(variant, M, N, K) > 0
+    tA, tB = dev(A), dev(B)
+    for alpha, beta in ((1.0, 0.0), (-0.75, 1.25)):
+        Cp = dev(C0)
+        bfx.gemm(variant, tA, tB, Cp, alpha=alpha, beta=beta)
+        Cf = dev(C0)
+        _gemm_fused(bfx, variant, tA, tB, Cf, alpha, beta)
+        np.testing.assert_array_equal(host(Cp).view(np.uint32), host(Cf).view(np.uint32))
