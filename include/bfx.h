@@ -73,7 +73,12 @@ int bfx_split_f32(const float *a, int64_t n, int nterms, uint16_t *b0,
 /* beta == 0: C is not read (it may hold NaN).  lda >= max(1,K),             */
 /* ldb >= max(1,N), ldc >= max(1,N).  ws/ws_bytes: device workspace of at    */
 /* least bfx_gemm_ws_size(...) bytes (NULL allowed when that is 0); the      */
-/* library uses it for split-K partial sums of long inner dimensions.        */
+/* library uses it for split-K partial sums of long inner dimensions, and    */
+/* on large problems (>= 256 output tiles of 128 x 128, K >= 512) for the    */
+/* operands' BF16 planes: with a 16-byte aligned workspace of at least       */
+/* bfx_gemm_ws_size bytes, A and B are split once (bfx_split_blocks) and     */
+/* the products run on the planes (bfx_gemm_blocks); with a smaller one the  */
+/* split happens inside the GEMM kernel.  Both give the same bits.           */
 /* Accuracy: |C - alpha A B| <= 2K 2^-24 |alpha| |A||B| componentwise for    */
 /* variants 6 and 9 (K >= 8), plus 3*2^-16 |alpha||A||B| for variant 3.      */
 /* Errors: -1 variant, -2/-3/-4 negative sizes, -6/-8/-11 NULL operands,     */
@@ -84,8 +89,48 @@ int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,
              float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
              void *stream);
 
-/* Workspace bytes bfx_gemm needs for this shape (0 when no split-K). */
+/* Workspace bytes bfx_gemm uses for this shape: the split-K partial sums,  */
+/* or the pre-split planes of both operands; 0 when it needs neither.        */
 size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K);
+
+/* ------------------------------------------------------------------------ */
+/* Pre-split operands (Sec. II-A once per operand, then Sec. II-D, II-G).   */
+/* Splitting costs O(N^2) against the O(N^3) products, so an operand used in */
+/* several products can be split once and reused.                           */
+/* ------------------------------------------------------------------------ */
+/* Block layout: nterms planes, plane t at element t * ceil(R/128) * KS *    */
+/* 4096 (KS = ceil(K/32)).  Plane t holds the t-th BF16 term of every value  */
+/* in 128 x 32 blocks of 4096 BF16: block (r, s) at element (r * KS + s) *   */
+/* 4096 covers rows 128 r .. 128 r + 127 (A rows; B columns) and k = 32 s .. */
+/* 32 s + 31, zeros outside R x K.  Inside a block, row n (0..127) is stored */
+/* at 64-byte row n ^ ((n >> 2) & 1) and its 16-byte chunk c (k = 8c..8c+7) */
+/* at chunk position c ^ ((n >> 1) & 3) of that row.                        */
+/* Bytes of one operand's planes (0 for invalid arguments or R, K <= 0).   */
+size_t bfx_split_blocks_size(int nterms, int64_t R, int64_t K);
+
+/* Split one FP32 operand into that layout, exactly (bfx_split_f32's terms).  */
+/* trans = 0: X is R x K row-major (the A operand, R = M), ld >= max(1,K);    */
+/* trans = 1: X is K x R row-major (the B operand, R = N), ld >= max(1,R).    */
+/* nterms: 1, 2 or 3 (variants 1, 3 and 6/9 read 1, 2 and 3 terms).          */
+/* out: device, 16-byte aligned, out_bytes >= bfx_split_blocks_size.          */
+/* Errors: -1 nterms, -2 trans, -3 R < 0, -4 K < 0 or K, R too large for the  */
+/* 32-bit block offsets (ceil(K/32) * 8192 >= 2^31), -5 X NULL, -6 ld,        */
+/* -7 out NULL or misaligned, -8 out_bytes too small.  R == 0 or K == 0: no   */
+/* work.                                                                      */
+int bfx_split_blocks(int nterms, int trans, int64_t R, int64_t K, const float *X,
+                     int64_t ld, uint16_t *out, size_t out_bytes, void *stream);
+
+/* C = alpha * (A x B) + beta * C from pre-split operands: Ab from            */
+/* bfx_split_blocks(P, 0, M, K, A, ...), Bb from bfx_split_blocks(P, 1, N, K,  */
+/* B, ...), P = 1, 2, 3 for variant 1, 3, 6/9.  Same variants, accumulation   */
+/* order, accuracy and beta rule as bfx_gemm (bitwise equal results).  Ab, Bb  */
+/* device, 16-byte aligned, read only; C device, ldc >= max(1,N).  One        */
+/* 128 x 128 output tile per workgroup, no workspace.                         */
+/* Errors: -1 variant, -2/-3/-4 negative sizes (-4 also for K beyond the       */
+/* block offsets), -6/-7 Ab/Bb NULL or misaligned, -9 C NULL, -10 ldc.        */
+int bfx_gemm_blocks(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+                    const uint16_t *Ab, const uint16_t *Bb, float beta, float *C,
+                    int64_t ldc, void *stream);
 
 /* Plain FP32 GEMM on the vector ALU, one rounding per FMA (Sec. II-C): the   */
 /* comparator the split variants are measured against.  Without split-K      */

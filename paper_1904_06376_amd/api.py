@@ -78,6 +78,35 @@ def gemm(variant: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None 
     return C
 
 
+def split_blocks(X: torch.Tensor, nterms: int, trans: bool = False) -> torch.Tensor:
+    """One operand into `nterms` BF16 planes of the pre-split block layout
+    (Sec. II-A): trans=False for A (M x K), trans=True for B (K x N).  Returns
+    the planes as an int16 tensor of bfx_split_blocks_size / 2 elements."""
+    _dev(X, torch.float32, "X")
+    if trans:
+        K, R = X.shape
+    else:
+        R, K = X.shape
+    nbytes = lib.bfx_split_blocks_size(nterms, R, K)
+    out = torch.empty(max(nbytes // 2, 8), dtype=torch.int16, device=X.device)
+    check(lib.bfx_split_blocks(nterms, int(trans), R, K, X.data_ptr(), _rows(X, "X"),
+                               out.data_ptr(), out.numel() * 2, _stream()), "bfx_split_blocks")
+    return out
+
+
+def gemm_blocks(variant: int, M: int, N: int, K: int, Ab: torch.Tensor, Bb: torch.Tensor,
+                C: torch.Tensor | None = None, alpha: float = 1.0, beta: float = 0.0,
+                device=None):
+    """C = alpha*(A x B) + beta*C from operands pre-split by split_blocks."""
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=device or Ab.device)
+        beta = 0.0
+    _dev(C, torch.float32, "C")
+    check(lib.bfx_gemm_blocks(variant, M, N, K, alpha, Ab.data_ptr(), Bb.data_ptr(), beta,
+                              C.data_ptr(), _rows(C, "C"), _stream()), "bfx_gemm_blocks")
+    return C
+
+
 def sgemm_fp32(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
                alpha: float = 1.0, beta: float = 0.0):
     """Plain FP32 vector-ALU GEMM (the comparator)."""

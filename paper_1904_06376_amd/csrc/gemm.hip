@@ -275,9 +275,13 @@ static bool planes_wanted(int64_t M, int64_t N, int64_t K) {
            ceil_div(M, 128) * KS < (int64_t(1) << 31) && ceil_div(N, 128) * KS < (int64_t(1) << 31);
 }
 
+
+
+static int64_t split_blocks_elems(int nterms, int64_t R, int64_t K);
+
 static size_t planes_bytes(int variant, int64_t M, int64_t N, int64_t K) {
-    return (size_t)prods_p(variant) * (size_t)(ceil_div(M, 128) + ceil_div(N, 128)) * 128 *
-           (size_t)(ceil_div(K, BK) * BK) * sizeof(uint16_t);
+    const int P = prods_p(variant);
+    return (size_t)(split_blocks_elems(P, M, K) + split_blocks_elems(P, N, K)) * sizeof(uint16_t);
 }
 
 static size_t gemm_ws_bytes_public(int variant, int64_t M, int64_t N, int64_t K) {
@@ -286,26 +290,42 @@ static size_t gemm_ws_bytes_public(int variant, int64_t M, int64_t N, int64_t K)
     return s > pl ? s : pl;
 }
 
+static int64_t split_blocks_elems(int nterms, int64_t R, int64_t K) {
+    return (int64_t)nterms * ceil_div(R, 128) * ceil_div(K, BK) * 4096;
+}
+
+// One operand into nterms planes of the pre-split block layout.
+static int launch_split_blocks(int nterms, bool trans, int64_t R, int64_t K, const float *X,
+                               int64_t ld, uint16_t *out, hipStream_t s) {
+    const int KS = (int)ceil_div(K, BK);
+    const int64_t blocks = ceil_div(R, 128) * KS;
+    const int64_t plane = blocks * 4096;
+    const bool vec = !trans && ((uintptr_t)X % 16 == 0) && (ld % 4 == 0);
+    const dim3 grid((unsigned)blocks), block(256);
+#define BFX_SPLIT_BLOCKS(PP)                                                                       \
+    if (trans)                                                                                     \
+        hipLaunchKernelGGL((split_blocks_kernel<PP, true>), grid, block, 0, s, X, ld, R, K, KS, out, plane, vec); \
+    else                                                                                           \
+        hipLaunchKernelGGL((split_blocks_kernel<PP, false>), grid, block, 0, s, X, ld, R, K, KS, out, plane, vec);
+    if (nterms == 1) { BFX_SPLIT_BLOCKS(1) }
+    else if (nterms == 2) { BFX_SPLIT_BLOCKS(2) }
+    else { BFX_SPLIT_BLOCKS(3) }
+#undef BFX_SPLIT_BLOCKS
+    BFX_LAUNCH_CHECK("split_blocks_kernel launch");
+    return BFX_OK;
+}
+
+// The products on pre-split operands (p.A, p.B unused).
 template <int V>
-static int launch_planes(const GemmParams &p, void *ws, hipStream_t s) {
-    constexpr int P = Prods<V>::P;
+static int launch_gemm_blocks(const GemmParams &p, const uint16_t *Ab, const uint16_t *Bb, hipStream_t s) {
     const int KS = (int)ceil_div(p.K, BK);
     const int64_t rm = ceil_div(p.M, 128), rn = ceil_div(p.N, 128);
     PlaneArgs q;
     q.KS = KS;
     q.a_plane = rm * KS * 4096;
     q.b_plane = rn * KS * 4096;
-    uint16_t *pa = (uint16_t *)ws;
-    uint16_t *pb = pa + P * q.a_plane;
-    q.A = pa;
-    q.B = pb;
-    const bool vecA = ((uintptr_t)p.A % 16 == 0) && (p.lda % 4 == 0);
-    hipLaunchKernelGGL((split_blocks_kernel<P, false>), dim3((unsigned)(rm * KS)), dim3(256), 0, s,
-                       p.A, p.lda, p.M, p.K, KS, pa, q.a_plane, vecA);
-    BFX_LAUNCH_CHECK("split_blocks_kernel launch");
-    hipLaunchKernelGGL((split_blocks_kernel<P, true>), dim3((unsigned)(rn * KS)), dim3(256), 0, s,
-                       p.B, p.ldb, p.N, p.K, KS, pb, q.b_plane, false);
-    BFX_LAUNCH_CHECK("split_blocks_kernel launch");
+    q.A = Ab;
+    q.B = Bb;
     const size_t lds = planes_lds_bytes<V>();
     static bool attr_set = false;
     if (!attr_set) {
@@ -316,6 +336,29 @@ static int launch_planes(const GemmParams &p, void *ws, hipStream_t s) {
     hipLaunchKernelGGL((gemm_planes_kernel<V>), dim3((unsigned)(rm * rn)), dim3(512), lds, s, p, q);
     BFX_LAUNCH_CHECK("gemm_planes_kernel launch");
     return BFX_OK;
+}
+
+static int gemm_blocks_dispatch(int variant, const GemmParams &p, const uint16_t *Ab, const uint16_t *Bb,
+                                hipStream_t s) {
+    switch (variant) {
+        case 1: return launch_gemm_blocks<1>(p, Ab, Bb, s);
+        case 3: return launch_gemm_blocks<3>(p, Ab, Bb, s);
+        case 6: return launch_gemm_blocks<6>(p, Ab, Bb, s);
+        case 9: return launch_gemm_blocks<9>(p, Ab, Bb, s);
+        default: return -1;
+    }
+}
+
+// Both operands split into the workspace, then the products.
+static int launch_planes(int variant, const GemmParams &p, void *ws, hipStream_t s) {
+    const int P = prods_p(variant);
+    uint16_t *pa = (uint16_t *)ws;
+    uint16_t *pb = pa + split_blocks_elems(P, p.M, p.K);
+    int rc = launch_split_blocks(P, false, p.M, p.K, p.A, p.lda, pa, s);
+    if (rc != BFX_OK) return rc;
+    rc = launch_split_blocks(P, true, p.N, p.K, p.B, p.ldb, pb, s);
+    if (rc != BFX_OK) return rc;
+    return gemm_blocks_dispatch(variant, p, pa, pb, s);
 }
 
 template <int V, int BM, int BN>
@@ -428,13 +471,7 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
         return -14;
     if (p.splits == 1 && ws && (uintptr_t)ws % 16 == 0 && planes_wanted(M, N, K) &&
         ws_bytes >= planes_bytes(variant, M, N, K)) {
-        switch (variant) {
-            case 1: return launch_planes<1>(p, ws, stream);
-            case 3: return launch_planes<3>(p, ws, stream);
-            case 6: return launch_planes<6>(p, ws, stream);
-            case 9: return launch_planes<9>(p, ws, stream);
-            default: return -1;
-        }
+        return launch_planes(variant, p, ws, stream);
     }
     int rc;
     switch (variant) {
@@ -486,4 +523,55 @@ extern "C" int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alph
     if (!C) return -11;
     return bfx::gemm_launch(variant, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws,
                             ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" size_t bfx_split_blocks_size(int nterms, int64_t R, int64_t K) {
+    if (nterms < 1 || nterms > 3 || R <= 0 || K <= 0) return 0;
+    return (size_t)bfx::split_blocks_elems(nterms, R, K) * sizeof(uint16_t);
+}
+
+extern "C" int bfx_split_blocks(int nterms, int trans, int64_t R, int64_t K, const float *X,
+                                int64_t ld, uint16_t *out, size_t out_bytes, void *stream) {
+    if (nterms < 1 || nterms > 3) return -1;
+    if (trans != 0 && trans != 1) return -2;
+    if (R < 0) return -3;
+    if (K < 0) return -4;
+    if (ld < (trans ? (R > 1 ? R : 1) : (K > 1 ? K : 1))) return -6;
+    if (R == 0 || K == 0) return BFX_OK;
+    if (!X) return -5;
+    if (!out || (uintptr_t)out % 16 != 0) return -7;
+    if (out_bytes < bfx_split_blocks_size(nterms, R, K)) return -8;
+    if (bfx::ceil_div(K, bfx::BK) * 8192 >= (int64_t(1) << 31) ||
+        bfx::ceil_div(R, 128) * bfx::ceil_div(K, bfx::BK) >= (int64_t(1) << 31))
+        return -4;
+    return bfx::launch_split_blocks(nterms, trans != 0, R, K, X, ld, out, (hipStream_t)stream);
+}
+
+extern "C" int bfx_gemm_blocks(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+                               const uint16_t *Ab, const uint16_t *Bb, float beta, float *C,
+                               int64_t ldc, void *stream) {
+    if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
+    if (M < 0) return -2;
+    if (N < 0) return -3;
+    if (K < 0) return -4;
+    if (ldc < (N > 1 ? N : 1)) return -10;
+    if (M == 0 || N == 0) return BFX_OK;
+    if (K == 0) {
+        // no products: C = beta C (alpha * 0), through the general path
+        return bfx::gemm_launch(variant, M, N, 0, alpha, nullptr, 1, nullptr, N, beta, C, ldc, nullptr, 0,
+                                (hipStream_t)stream);
+    }
+    if (!Ab || (uintptr_t)Ab % 16 != 0) return -6;
+    if (!Bb || (uintptr_t)Bb % 16 != 0) return -7;
+    if (!C) return -9;
+    const int64_t KS = bfx::ceil_div(K, bfx::BK);
+    if (KS * 8192 >= (int64_t(1) << 31) || bfx::ceil_div(M, 128) * bfx::ceil_div(N, 128) >= (int64_t(1) << 31))
+        return -4;
+    bfx::GemmParams p = {};
+    p.M = M; p.N = N; p.K = K;
+    p.C = C; p.ldc = ldc;
+    p.alpha = alpha; p.beta = beta;
+    p.splits = 1;
+    p.k_per_split = KS * bfx::BK;
+    return bfx::gemm_blocks_dispatch(variant, p, Ab, Bb, (hipStream_t)stream);
 }

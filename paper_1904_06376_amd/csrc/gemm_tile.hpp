@@ -844,7 +844,7 @@ __device__ __forceinline__ void gemm_tile_planes(const GemmParams &p, const Plan
     }
 
     // ------------------------------ loader waves ------------------------------
-    const int h = wave - 4;
+    const int h = __builtin_amdgcn_readfirstlane(wave) - 4;   // uniform: LDS addresses in SGPRs
     __amdgpu_buffer_rsrc_t rs[2 * P];   // blocks of plane pl: A at 2 pl, B at 2 pl + 1
     const int range = q.KS * 8192;
 #pragma unroll

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads
-from tests.gpu_util import absref, dev, gemm_bound, host, ref64
+from tests.gpu_util import absref, bits16, dev, gemm_bound, host, ref64
 
 pytestmark = pytest.mark.gpu
 
@@ -330,3 +330,66 @@ def test_gemm_presplit_equals_fused(bfx, variant, shape):
         Cf = dev(C0)
         _gemm_fused(bfx, variant, tA, tB, Cf, alpha, beta)
         np.testing.assert_array_equal(host(Cp).view(np.uint32), host(Cf).view(np.uint32))
+
+
+def _unblock(blocks, nterms, R, K):
+    """Host-side reading of the pre-split block layout (include/bfx.h): plane
+    t, block (r, s) at element (t * RB * KS + r * KS + s) * 4096; row n in
+    64-byte row n ^ ((n >> 2) & 1), chunk c at position c ^ ((n >> 1) & 3)."""
+    RB, KS = -(-R // 128), -(-K // 32)
+    b = blocks.reshape(nterms, RB, KS, 128, 4, 8)          # plane, r, s, phys row, chunk pos, k%8
+    n = np.arange(128)
+    phys = n ^ ((n >> 2) & 1)
+    out = np.empty((nterms, RB, 128, KS, 4, 8), np.uint16)
+    for c in range(4):
+        pos = c ^ ((n >> 1) & 3)
+        out[:, :, :, :, c, :] = b[:, :, :, phys, pos, :].transpose(0, 1, 3, 2, 4)
+    full = out.reshape(nterms, RB * 128, KS * 32)
+    return full[:, :R, :K], full
+
+
+@pytest.mark.parametrize("shape", [(200, 77), (128, 32), (1, 1), (257, 1000), (130, 4)])
+@pytest.mark.parametrize("nterms", [1, 2, 3])
+def test_split_blocks_layout_vs_oracle(bfx, orc, shape, nterms):
+    """bfx_split_blocks of A (R x K) and of B (K x R, trans) hold the oracle's
+    Sec. II-A terms of every element at the documented positions, zeros in the
+    padding; special values included."""
+    R, K = shape
+    X = workloads.normal((R, K), 81) * np.float32(3.0)
+    X.ravel()[:6] = [np.inf, -np.nan, 1e-40, 3.4e38, -0.0, 2.0 ** -133][:X.size]
+    ref = orc.split(X, 3)
+    for trans in (False, True):
+        src = X.T.copy() if trans else X
+        got = bits16(bfx.split_blocks(dev(src), nterms, trans=trans))
+        inner, full = _unblock(got, nterms, R, K)
+        for t in range(nterms):
+            np.testing.assert_array_equal(inner[t], ref[t])
+        pad = full.copy()
+        pad[:, :R, :K] = 0
+        assert not pad.any()
+
+
+@pytest.mark.parametrize("variant", [1, 3, 6, 9])
+@pytest.mark.parametrize("shape", [(200, 132, 96), (129, 256, 36), (1, 4, 4), (65, 64, 44),
+                                   (256, 256, 256), (300, 44, 200), (127, 128, 480)])
+def test_gemm_blocks_small_shapes(bfx, orc, variant, shape):
+    """bfx_gemm_blocks on small and ragged shapes: within the bound of the
+    exact product, within twice the bound of the oracle, and bitwise equal to
+    bfx_gemm's in-kernel split (these shapes take its wave-specialised engine
+    without split-K, which accumulates in the same order)."""
+    M, N, K = shape
+    P = {1: 1, 3: 2, 6: 3, 9: 3}[variant]
+    A = workloads.normal((M, K), 91)
+    B = workloads.normal((K, N), 92)
+    C0 = workloads.normal((M, N), 93)
+    tA, tB = dev(A), dev(B)
+    Ab = bfx.split_blocks(tA, P)
+    Bb = bfx.split_blocks(tB, P, trans=True)
+    for alpha, beta in ((1.0, 0.0), (0.5, -2.0)):
+        Cb = dev(C0)
+        bfx.gemm_blocks(variant, M, N, K, Ab, Bb, Cb, alpha=alpha, beta=beta)
+        Cf = dev(C0)
+        _gemm_fused(bfx, variant, tA, tB, Cf, alpha, beta)
+        np.testing.assert_array_equal(host(Cb).view(np.uint32), host(Cf).view(np.uint32))
+    Cb = host(bfx.gemm_blocks(variant, M, N, K, Ab, Bb))
+    _check_bound(variant, A, B, Cb, orc.gemm(variant, A, B))
