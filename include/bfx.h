@@ -95,8 +95,8 @@ size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K);
 
 /* ------------------------------------------------------------------------ */
 /* Pre-split operands (Sec. II-A once per operand, then Sec. II-D, II-G).   */
-/* Splitting costs O(N^2) against the O(N^3) products, so an operand used in */
-/* several products can be split once and reused.                           */
+/* Splitting costs O(N^2) against the O(N^3) products (Sec. V), so an        */
+/* operand used in several products can be split once and reused.           */
 /* ------------------------------------------------------------------------ */
 /* Block layout: nterms planes, plane t at element t * ceil(R/128) * KS *    */
 /* 4096 (KS = ceil(K/32)).  Plane t holds the t-th BF16 term of every value  */

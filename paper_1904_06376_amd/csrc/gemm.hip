@@ -66,53 +66,98 @@ gemm_fast_kernel(GemmParams p) {
 }
 
 // Split of one operand into the pre-split block layout of gemm_tile_planes
-// (Sec. II-A, exact integer conversion for every element).  Workgroup b
-// writes block b = r * KS + s: rows 128 r .. of the operand (A rows; for
-// TRANS, columns of a K x R row-major B) and k = 32 s .. 32 s + 31, zeros
-// outside R x K.  Each thread converts 16 consecutive k of one row and
-// writes two 16-byte chunks per plane.
+// (Sec. II-A, exact integer conversion for every element).  Each workgroup
+// writes one block (r, s): rows 128 r .. of the operand (A rows; for TRANS,
+// columns of a K x R row-major B) and k = 32 s .. 32 s + 31, zeros outside
+// R x K.  A (TRANS false): each thread converts 16 consecutive k of
+// one row (four 16-byte loads) and writes two 16-byte chunks per plane.
+// B (TRANS true): the block is read with 16-byte loads along rows of B into
+// LDS, then converted column by column like A.
 template <int P, bool TRANS>
 __global__ void __launch_bounds__(256)
 split_blocks_kernel(const float *__restrict__ X, int64_t ld, int64_t R, int64_t K, int KS,
                     uint16_t *__restrict__ out, int64_t plane, bool vec) {
-    const int64_t b = blockIdx.x;
-    const int64_t r = b / KS, ks = b % KS;
+    // A: consecutive workgroups take consecutive k blocks of one row band
+    // (rows read as contiguous runs); B: consecutive column bands of one k
+    // band, so that together they read whole rows of B
+    const int64_t RB = (R + 127) / 128;
+    const int64_t r = TRANS ? (int64_t)blockIdx.x % RB : (int64_t)blockIdx.x / KS;
+    const int64_t ks = TRANS ? (int64_t)blockIdx.x / RB : (int64_t)blockIdx.x % KS;
     const int t = threadIdx.x;
-    const int n = TRANS ? (t & 127) : (t >> 1);
-    const int half = TRANS ? (t >> 7) : (t & 1);
-    const int64_t row = r * 128 + n;
-    const int64_t k0 = ks * BK + 16 * half;
-    float v[16];
-    if (!TRANS && vec && row < R && k0 + 16 <= K) {
-        const float4 *src = reinterpret_cast<const float4 *>(X + row * ld + k0);
+    uint16_t *blk = out + (r * KS + ks) * 4096;
+    if constexpr (TRANS) {
+        // 32 k rows x 128 columns through LDS: 16-byte loads along rows of B
+        // (a wave reads two 512-byte rows per load), then each thread takes
+        // 16 consecutive k of one column, as the A path does.
+        __shared__ float tile[128][BK + 1];   // [column][k], odd stride: conflict-free column reads
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float4 f = src[i];
-            v[4 * i] = f.x; v[4 * i + 1] = f.y; v[4 * i + 2] = f.z; v[4 * i + 3] = f.w;
+            const int idx = t + 256 * i;
+            const int kr = idx >> 5, c4 = idx & 31;
+            const int64_t k = ks * BK + kr, col = r * 128 + 4 * c4;
+            float f[4];
+            if (vec && k < K && col + 4 <= R) {
+                const float4 g = *reinterpret_cast<const float4 *>(X + k * ld + col);
+                f[0] = g.x; f[1] = g.y; f[2] = g.z; f[3] = g.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) f[j] = (k < K && col + j < R) ? X[k * ld + col + j] : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tile[4 * c4 + j][kr] = f[j];
         }
+        __syncthreads();
+        const int n = t & 127, half = t >> 7;
+        uint32_t w[3][8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint32_t x[3], y[3];
+            split3_exact(tile[n][16 * half + 2 * i], x[0], x[1], x[2]);
+            split3_exact(tile[n][16 * half + 2 * i + 1], y[0], y[1], y[2]);
+#pragma unroll
+            for (int pl = 0; pl < P; ++pl) w[pl][i] = x[pl] | (y[pl] << 16);
+        }
+#pragma unroll
+        for (int pl = 0; pl < P; ++pl)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                *reinterpret_cast<uint4 *>(blk + pl * plane + swz_off(n, (2 * half + c) * 8)) =
+                    make_uint4(w[pl][4 * c], w[pl][4 * c + 1], w[pl][4 * c + 2], w[pl][4 * c + 3]);
     } else {
+        const int n = t >> 1, half = t & 1;
+        const int64_t row = r * 128 + n;
+        const int64_t k0 = ks * BK + 16 * half;
+        float v[16];
+        if (vec && row < R && k0 + 16 <= K) {
+            const float4 *src = reinterpret_cast<const float4 *>(X + row * ld + k0);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t k = k0 + i;
-            v[i] = (row < R && k < K) ? (TRANS ? X[k * ld + row] : X[row * ld + k]) : 0.0f;
+            for (int i = 0; i < 4; ++i) {
+                const float4 f = src[i];
+                v[4 * i] = f.x; v[4 * i + 1] = f.y; v[4 * i + 2] = f.z; v[4 * i + 3] = f.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int64_t k = k0 + i;
+                v[i] = (row < R && k < K) ? X[row * ld + k] : 0.0f;
+            }
         }
+        uint32_t w[3][8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint32_t x[3], y[3];
+            split3_exact(v[2 * i], x[0], x[1], x[2]);
+            split3_exact(v[2 * i + 1], y[0], y[1], y[2]);
+#pragma unroll
+            for (int pl = 0; pl < P; ++pl) w[pl][i] = x[pl] | (y[pl] << 16);
+        }
+#pragma unroll
+        for (int pl = 0; pl < P; ++pl)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                *reinterpret_cast<uint4 *>(blk + pl * plane + swz_off(n, (2 * half + c) * 8)) =
+                    make_uint4(w[pl][4 * c], w[pl][4 * c + 1], w[pl][4 * c + 2], w[pl][4 * c + 3]);
     }
-    uint32_t w[3][8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        uint32_t x[3], y[3];
-        split3_exact(v[2 * i], x[0], x[1], x[2]);
-        split3_exact(v[2 * i + 1], y[0], y[1], y[2]);
-#pragma unroll
-        for (int pl = 0; pl < P; ++pl) w[pl][i] = x[pl] | (y[pl] << 16);
-    }
-    uint16_t *blk = out + b * 4096;
-#pragma unroll
-    for (int pl = 0; pl < P; ++pl)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-            *reinterpret_cast<uint4 *>(blk + pl * plane + swz_off(n, (2 * half + c) * 8)) =
-                make_uint4(w[pl][4 * c], w[pl][4 * c + 1], w[pl][4 * c + 2], w[pl][4 * c + 3]);
 }
 
 // GEMM on pre-split operands (see gemm_tile_planes): one 128 x 128 tile per
@@ -300,7 +345,7 @@ static int launch_split_blocks(int nterms, bool trans, int64_t R, int64_t K, con
     const int KS = (int)ceil_div(K, BK);
     const int64_t blocks = ceil_div(R, 128) * KS;
     const int64_t plane = blocks * 4096;
-    const bool vec = !trans && ((uintptr_t)X % 16 == 0) && (ld % 4 == 0);
+    const bool vec = ((uintptr_t)X % 16 == 0) && (ld % 4 == 0);
     const dim3 grid((unsigned)blocks), block(256);
 #define BFX_SPLIT_BLOCKS(PP)                                                                       \
     if (trans)                                                                                     \

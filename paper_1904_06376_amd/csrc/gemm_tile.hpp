@@ -732,8 +732,8 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
 }
 
 // ---------------------------------------------------------------------------
-// Pre-split operands (Sec. II-A done once per operand, O(N^2), before the
-// O(N^3) products).  split_blocks_kernel writes each operand's P BF16 planes
+// Pre-split operands: the Sec. II-A split done once per operand, O(N^2) work
+// against the O(N^3) products (the cost split of Sec. V).  split_blocks_kernel writes each operand's P BF16 planes
 // as whole 128 x 32 blocks of 8 KiB, every block already in the swz_off order
 // of the LDS staging above and zero-padded to whole blocks: block (r, s) of a
 // plane holds rows 128 r .. 128 r + 127 of A (columns of B) and k = 32 s ..

@@ -393,3 +393,15 @@ def test_gemm_blocks_small_shapes(bfx, orc, variant, shape):
         np.testing.assert_array_equal(host(Cb).view(np.uint32), host(Cf).view(np.uint32))
     Cb = host(bfx.gemm_blocks(variant, M, N, K, Ab, Bb))
     _check_bound(variant, A, B, Cb, orc.gemm(variant, A, B))
+
+
+def test_gemm_blocks_K0_scales_C(bfx):
+    """K = 0: no products, C = beta C (beta = 0: C = 0), the operands unread."""
+    C0 = workloads.normal((70, 40), 95)
+    e = torch.empty(8, dtype=torch.int16, device="cuda")
+    C = dev(C0)
+    bfx.gemm_blocks(6, 70, 40, 0, e, e, C, alpha=2.0, beta=-0.5)
+    np.testing.assert_array_equal(host(C), np.float32(-0.5) * C0)
+    C = dev(C0)
+    bfx.gemm_blocks(6, 70, 40, 0, e, e, C, alpha=2.0, beta=0.0)
+    assert not host(C).any()
