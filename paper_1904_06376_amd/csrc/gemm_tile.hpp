@@ -765,6 +765,40 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
+// Issue order of one K-step's products on pre-split operands (the lo products
+// of Prods<V> grouped by B plane, largest plane first, then the hi product
+// A0 B0: the order gemm_tile_fast uses) and the read group of each operand
+// plane: group 0 = the planes of the first product, group 1 = the planes the
+// second product adds, group 2 = the rest, read once the first product's
+// MFMAs are issued.  Reading in this order lets the first MFMAs of a step
+// start after 5 fragment reads instead of waiting behind all of A's (measured
+// 3-6% at 8192^3 x6).
+template <int V>
+struct PlanesOrder {
+    static constexpr int NPROD = Prods<V>::n + 1;
+    int a[NPROD], b[NPROD];   // A and B plane of product k; product NPROD-1 is the hi product
+    int ga[3], gb[3];         // read group of A plane pl and B plane pl
+    constexpr PlanesOrder() : a(), b(), ga(), gb() {
+        int k = 0;
+        for (int jp = Prods<V>::P - 1; jp >= 0; --jp)
+            for (int q = 0; q < Prods<V>::n; ++q)
+                if (Prods<V>::bj[q] == jp) {
+                    a[k] = Prods<V>::ai[q];
+                    b[k] = jp;
+                    ++k;
+                }
+        a[k] = 0;
+        b[k] = 0;
+        for (int pl = 0; pl < 3; ++pl) ga[pl] = gb[pl] = 2;
+        ga[a[0]] = 0;
+        gb[b[0]] = 0;
+        if (NPROD > 1) {
+            if (ga[a[1]] == 2) ga[a[1]] = 1;
+            if (gb[b[1]] == 2) gb[b[1]] = 1;
+        }
+    }
+};
+
 // 512 threads.  Waves 0-3: as in gemm_tile_fast (fragments from LDS, MFMAs,
 // epilogue).  Waves 4-7: direct-to-LDS loads, NS - 1 K-steps ahead into a
 // ring of NS stages; wave 4 + h moves the 1 KiB pieces 2h and 2h + 1 of every
@@ -801,40 +835,46 @@ __device__ __forceinline__ void gemm_tile_planes(const GemmParams &p, const Plan
         for (int j = 0; j < TN; ++j) boff[j] = swz_off(BM + wn * (BN / 2) + j * 16 + r16, kg * 8);
 #pragma unroll
         for (int i = 0; i < TM; ++i) aoff[i] = swz_off(wm * (BM / 2) + i * 16 + r16, kg * 8);
+        constexpr PlanesOrder<V> O{};
         int st = 0;
         for (int s = 0; s < S; ++s) {
             __syncthreads();  // stage st holds step s
             const uint16_t *base = smem + st * P * PLANE;
             st = (st + 1 == NS) ? 0 : st + 1;
-            bfx_bf16x8 af[P][TM];
+            bfx_bf16x8 af[P][TM], bf[P][TN];
+            auto read_group = [&](int g) {
 #pragma unroll
-            for (int pl = 0; pl < P; ++pl)
+                for (int pl = P - 1; pl >= 0; --pl)
+                    if (O.gb[pl] == g) {
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            bf[pl][j] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + boff[j]);
+                    }
+#pragma unroll
+                for (int pl = 0; pl < P; ++pl)
+                    if (O.ga[pl] == g) {
+#pragma unroll
+                        for (int i = 0; i < TM; ++i)
+                            af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
+                    }
+            };
+            read_group(0);
+            __builtin_amdgcn_sched_barrier(0);
+            read_group(1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < O.NPROD; ++k) {
+                bfx_f32x4 (&acc)[TM][TN] = (k == O.NPROD - 1) ? hi : lo;
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
 #pragma unroll
-            for (int jp = P - 1; jp >= 0; --jp) {
-                bfx_bf16x8 bf[TN];
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(base + jp * PLANE + boff[j]);
-#pragma unroll
-                for (int qq = 0; qq < PR::n; ++qq) {
-                    if (PR::bj[qq] != jp) continue;
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PR::ai[qq]][i], bf[j],
-                                                                                lo[i][j], 0, 0, 0);
-                }
-                if (jp == 0) {
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[j],
-                                                                                hi[i][j], 0, 0, 0);
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[O.a[k]][i], bf[O.b[k]][j],
+                                                                            acc[i][j], 0, 0, 0);
+                if (k == 0) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    read_group(2);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }

@@ -405,3 +405,30 @@ def test_gemm_blocks_K0_scales_C(bfx):
     C = dev(C0)
     bfx.gemm_blocks(6, 70, 40, 0, e, e, C, alpha=2.0, beta=0.0)
     assert not host(C).any()
+
+
+@pytest.mark.parametrize("variant", [3, 6])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_gemm_presplit_strided_views(bfx, variant, offset):
+    """The pre-split path on row-major views with leading dimensions larger
+    than the row length (lda = K + 12, ldb = N + 8, ldc = N + 4) and, with
+    offset 1, operands that start one element past a 16-byte boundary (the
+    splits then take their scalar loads): bitwise equal to the in-kernel
+    split on contiguous copies, columns outside the view untouched."""
+    M, N, K = 2048, 2100, 640
+    A = workloads.normal((M, K + 12 + offset), 101)
+    B = workloads.normal((K, N + 8 + offset), 102)
+    Cw = workloads.normal((M, N + 4), 103)
+    tAw, tBw = dev(A), dev(B)
+    tA = tAw[:, offset:offset + K]
+    tB = tBw[:, offset:offset + N]
+    tCw = dev(Cw)
+    tC = tCw[:, :N]
+    assert bfx.gemm_ws_size(variant, M, N, K) > 0
+    bfx.gemm(variant, tA, tB, tC, alpha=1.5, beta=0.25)
+    Cf = dev(np.ascontiguousarray(Cw[:, :N]))
+    _gemm_fused(bfx, variant, dev(np.ascontiguousarray(A[:, offset:offset + K])),
+                dev(np.ascontiguousarray(B[:, offset:offset + N])), Cf, 1.5, 0.25)
+    got = host(tCw)
+    np.testing.assert_array_equal(got[:, :N].view(np.uint32), host(Cf).view(np.uint32))
+    np.testing.assert_array_equal(got[:, N:], Cw[:, N:])
