@@ -374,6 +374,86 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int64_t m0, int64
 //     register stage is reloaded.
 // ---------------------------------------------------------------------------
 
+// Issue order of one K-step's products (the lo products of Prods<V> grouped
+// by B plane, largest plane first, then the hi product A0 B0) and the read
+// group of each operand
+// plane: group 0 = the planes of the first product, group 1 = the planes the
+// second product adds, group 2 = the rest, read once the first product's
+// MFMAs are issued.  Reading in this order lets the first MFMAs of a step
+// start after 5 fragment reads instead of waiting behind all of A's (measured
+// 3-6% at 8192^3 x6).
+template <int V>
+struct StepOrder {
+    static constexpr int NPROD = Prods<V>::n + 1;
+    int a[NPROD], b[NPROD];   // A and B plane of product k; product NPROD-1 is the hi product
+    int ga[3], gb[3];         // read group of A plane pl and B plane pl
+    constexpr StepOrder() : a(), b(), ga(), gb() {
+        int k = 0;
+        for (int jp = Prods<V>::P - 1; jp >= 0; --jp)
+            for (int q = 0; q < Prods<V>::n; ++q)
+                if (Prods<V>::bj[q] == jp) {
+                    a[k] = Prods<V>::ai[q];
+                    b[k] = jp;
+                    ++k;
+                }
+        a[k] = 0;
+        b[k] = 0;
+        for (int pl = 0; pl < 3; ++pl) ga[pl] = gb[pl] = 2;
+        ga[a[0]] = 0;
+        gb[b[0]] = 0;
+        if (NPROD > 1) {
+            if (ga[a[1]] == 2) ga[a[1]] = 1;
+            if (gb[b[1]] == 2) gb[b[1]] = 1;
+        }
+    }
+};
+
+// One K-step of an MFMA wave's TM x TN block of 16 x 16 tiles: fragments
+// from the LDS planes at `base` (plane pl at pl * PLANE elements; A rows at
+// aoff, B columns at boff), read in StepOrder's groups, and the products in
+// its order (lo, then hi).
+template <int V, int TM, int TN, int PLANE>
+__device__ __forceinline__ void mfma_step(const uint16_t *base, const int (&aoff)[TM], const int (&boff)[TN],
+                                          bfx_f32x4 (&hi)[TM][TN], bfx_f32x4 (&lo)[TM][TN]) {
+    constexpr int P = Prods<V>::P;
+    constexpr StepOrder<V> O{};
+    bfx_bf16x8 af[P][TM], bf[P][TN];
+    auto read_group = [&](int g) {
+#pragma unroll
+        for (int pl = P - 1; pl >= 0; --pl)
+            if (O.gb[pl] == g) {
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    bf[pl][j] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + boff[j]);
+            }
+#pragma unroll
+        for (int pl = 0; pl < P; ++pl)
+            if (O.ga[pl] == g) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
+            }
+    };
+    read_group(0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_group(1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < O.NPROD; ++k) {
+        bfx_f32x4 (&acc)[TM][TN] = (k == O.NPROD - 1) ? hi : lo;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[O.a[k]][i], bf[O.b[k]][j], acc[i][j], 0, 0, 0);
+        if (k == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            read_group(2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 // Packed BF16 pairs of KPT consecutive values -> P planes x KPT/2 dwords.
 // `flag` collects (per 16-bit half, unsigned max) the magnitude of every
 // first term: a half >= 0x7F80 marks an Inf/NaN first term.
@@ -456,40 +536,7 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
         int tile_k = 0, step_in_tile = 0;   // persistent: tile and step within it
         for (int s = 0; s < S; ++s) {
             __syncthreads();  // buffer s&1 holds step s
-            const uint16_t *base = smem + (s & 1) * P * PLANE;
-            bfx_bf16x8 af[P][TM];
-#pragma unroll
-            for (int pl = 0; pl < P; ++pl)
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
-            // B fragments one plane at a time (plane 2, 1, 0): within each B
-            // plane the lo products are issued smallest bin first.
-#pragma unroll
-            for (int jp = P - 1; jp >= 0; --jp) {
-                bfx_bf16x8 bf[TN];
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    bf[j] = *reinterpret_cast<const bfx_bf16x8 *>(base + jp * PLANE + boff[j]);
-#pragma unroll
-                for (int q = 0; q < PR::n; ++q) {
-                    if (PR::bj[q] != jp) continue;
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            lo[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PR::ai[q]][i], bf[j],
-                                                                                lo[i][j], 0, 0, 0);
-                }
-                if (jp == 0) {
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            hi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[j],
-                                                                                hi[i][j], 0, 0, 0);
-                }
-            }
+            mfma_step<V, TM, TN, PLANE>(smem + (s & 1) * P * PLANE, aoff, boff, hi, lo);
             if constexpr (PERSIST) {
                 if (++step_in_tile == KT) {
                     // last K-step of this tile: its epilogue, overlapped with the
@@ -765,40 +812,6 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// Issue order of one K-step's products on pre-split operands (the lo products
-// of Prods<V> grouped by B plane, largest plane first, then the hi product
-// A0 B0: the order gemm_tile_fast uses) and the read group of each operand
-// plane: group 0 = the planes of the first product, group 1 = the planes the
-// second product adds, group 2 = the rest, read once the first product's
-// MFMAs are issued.  Reading in this order lets the first MFMAs of a step
-// start after 5 fragment reads instead of waiting behind all of A's (measured
-// 3-6% at 8192^3 x6).
-template <int V>
-struct PlanesOrder {
-    static constexpr int NPROD = Prods<V>::n + 1;
-    int a[NPROD], b[NPROD];   // A and B plane of product k; product NPROD-1 is the hi product
-    int ga[3], gb[3];         // read group of A plane pl and B plane pl
-    constexpr PlanesOrder() : a(), b(), ga(), gb() {
-        int k = 0;
-        for (int jp = Prods<V>::P - 1; jp >= 0; --jp)
-            for (int q = 0; q < Prods<V>::n; ++q)
-                if (Prods<V>::bj[q] == jp) {
-                    a[k] = Prods<V>::ai[q];
-                    b[k] = jp;
-                    ++k;
-                }
-        a[k] = 0;
-        b[k] = 0;
-        for (int pl = 0; pl < 3; ++pl) ga[pl] = gb[pl] = 2;
-        ga[a[0]] = 0;
-        gb[b[0]] = 0;
-        if (NPROD > 1) {
-            if (ga[a[1]] == 2) ga[a[1]] = 1;
-            if (gb[b[1]] == 2) gb[b[1]] = 1;
-        }
-    }
-};
-
 // 512 threads.  Waves 0-3: as in gemm_tile_fast (fragments from LDS, MFMAs,
 // epilogue).  Waves 4-7: direct-to-LDS loads, NS - 1 K-steps ahead into a
 // ring of NS stages; wave 4 + h moves the 1 KiB pieces 2h and 2h + 1 of every
@@ -835,48 +848,11 @@ __device__ __forceinline__ void gemm_tile_planes(const GemmParams &p, const Plan
         for (int j = 0; j < TN; ++j) boff[j] = swz_off(BM + wn * (BN / 2) + j * 16 + r16, kg * 8);
 #pragma unroll
         for (int i = 0; i < TM; ++i) aoff[i] = swz_off(wm * (BM / 2) + i * 16 + r16, kg * 8);
-        constexpr PlanesOrder<V> O{};
         int st = 0;
         for (int s = 0; s < S; ++s) {
             __syncthreads();  // stage st holds step s
-            const uint16_t *base = smem + st * P * PLANE;
+            mfma_step<V, TM, TN, PLANE>(smem + st * P * PLANE, aoff, boff, hi, lo);
             st = (st + 1 == NS) ? 0 : st + 1;
-            bfx_bf16x8 af[P][TM], bf[P][TN];
-            auto read_group = [&](int g) {
-#pragma unroll
-                for (int pl = P - 1; pl >= 0; --pl)
-                    if (O.gb[pl] == g) {
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            bf[pl][j] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + boff[j]);
-                    }
-#pragma unroll
-                for (int pl = 0; pl < P; ++pl)
-                    if (O.ga[pl] == g) {
-#pragma unroll
-                        for (int i = 0; i < TM; ++i)
-                            af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
-                    }
-            };
-            read_group(0);
-            __builtin_amdgcn_sched_barrier(0);
-            read_group(1);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int k = 0; k < O.NPROD; ++k) {
-                bfx_f32x4 (&acc)[TM][TN] = (k == O.NPROD - 1) ? hi : lo;
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[O.a[k]][i], bf[O.b[k]][j],
-                                                                            acc[i][j], 0, 0, 0);
-                if (k == 0) {
-                    __builtin_amdgcn_sched_barrier(0);
-                    read_group(2);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
         }
         __syncthreads();  // matches the loaders' final barrier
         tile_epilogue<TM, TN, 1>(p, hi, lo, tm * BM + wm * (BM / 2), tn * BN + wn * (BN / 2), kg, r16, 0);
