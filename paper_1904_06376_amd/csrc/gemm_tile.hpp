@@ -378,10 +378,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int64_t m0, int64
 // by B plane, largest plane first, then the hi product A0 B0) and the read
 // group of each operand
 // plane: group 0 = the planes of the first product, group 1 = the planes the
-// second product adds, group 2 = the rest, read once the first product's
-// MFMAs are issued.  Reading in this order lets the first MFMAs of a step
-// start after 5 fragment reads instead of waiting behind all of A's (measured
-// 3-6% at 8192^3 x6).
+// second product adds, group 2 = the rest.  Reading in this order lets the
+// first MFMAs of a step start after 5 fragment reads instead of waiting
+// behind all of A's (measured 3-6% at 8192^3 x6), and spreading groups 1
+// and 2 over the first two products' MFMAs another ~5%.
 template <int V>
 struct StepOrder {
     static constexpr int NPROD = Prods<V>::n + 1;
@@ -408,15 +408,38 @@ struct StepOrder {
     }
 };
 
+// Scheduling request: R LDS reads spread over the MFMAs that follow, one
+// read per M MFMAs (sched_group_barrier masks: 0x100 LDS read, 0x008 MFMA).
+template <int R, int M, int ID>
+__device__ __forceinline__ void interleave_reads() {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, ID);
+        __builtin_amdgcn_sched_group_barrier(0x008, M, ID);
+    }
+}
+
 // One K-step of an MFMA wave's TM x TN block of 16 x 16 tiles: fragments
 // from the LDS planes at `base` (plane pl at pl * PLANE elements; A rows at
-// aoff, B columns at boff), read in StepOrder's groups, and the products in
-// its order (lo, then hi).
+// aoff, B columns at boff) and the products in StepOrder's order (lo, then
+// hi).  Read group 0 is read before the first product; group 1 is read
+// while the first product's MFMAs issue and group 2 while the second's, one
+// read between every few MFMAs (scheduling barriers hold the order).
 template <int V, int TM, int TN, int PLANE>
 __device__ __forceinline__ void mfma_step(const uint16_t *base, const int (&aoff)[TM], const int (&boff)[TN],
                                           bfx_f32x4 (&hi)[TM][TN], bfx_f32x4 (&lo)[TM][TN]) {
     constexpr int P = Prods<V>::P;
+    constexpr int NPROD = StepOrder<V>::NPROD;
     constexpr StepOrder<V> O{};
+    // reads in group g, and MFMAs per read when they are spread over one product
+    constexpr auto reads = [](const StepOrder<V> &o, int g) {
+        int r = 0;
+        for (int pl = 0; pl < Prods<V>::P; ++pl) r += (o.gb[pl] == g ? TN : 0) + (o.ga[pl] == g ? TM : 0);
+        return r;
+    };
+    constexpr int R1 = reads(O, 1), R2 = reads(O, 2);
+    constexpr int M1 = R1 && TM * TN / R1 > 0 ? TM * TN / R1 : 1;
+    constexpr int M2 = R2 && TM * TN / R2 > 0 ? TM * TN / R2 : 1;
     bfx_bf16x8 af[P][TM], bf[P][TN];
     auto read_group = [&](int g) {
 #pragma unroll
@@ -434,23 +457,27 @@ __device__ __forceinline__ void mfma_step(const uint16_t *base, const int (&aoff
                     af[pl][i] = *reinterpret_cast<const bfx_bf16x8 *>(base + pl * PLANE + aoff[i]);
             }
     };
-    read_group(0);
-    __builtin_amdgcn_sched_barrier(0);
-    read_group(1);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < O.NPROD; ++k) {
-        bfx_f32x4 (&acc)[TM][TN] = (k == O.NPROD - 1) ? hi : lo;
+    auto product = [&](int k) {
+        bfx_f32x4 (&acc)[TM][TN] = (k == NPROD - 1) ? hi : lo;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[O.a[k]][i], bf[O.b[k]][j], acc[i][j], 0, 0, 0);
-        if (k == 0) {
-            __builtin_amdgcn_sched_barrier(0);
-            read_group(2);
-            __builtin_amdgcn_sched_barrier(0);
-        }
+    };
+    read_group(0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_group(1);
+    product(0);
+    interleave_reads<R1, M1, 0>();
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (NPROD > 1) {
+        read_group(2);
+        product(1);
+        interleave_reads<R2, M2, 1>();
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 2; k < NPROD; ++k) product(k);
     }
 }
 
