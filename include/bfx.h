@@ -68,8 +68,12 @@ int bfx_split_f32(const float *a, int64_t n, int nterms, uint16_t *b0,
 /* first.  variant = number of BF16 products per scalar product:             */
 /*   3 -> Z0 + Z1            (two terms each)                                */
 /*   6 -> Z0 + (Z1 + Z2)     (three terms, the paper's six-product sum)      */
+/*   7 -> x6 plus A1 B2 (half of bin 3)                                      */
+/*   8 -> Z0 + (Z1 + (Z2 + Z3))  (bins 0-3, eight products)                 */
 /*   9 -> Z0 + (Z1 + (Z2 + (Z3 + Z4)))  (all nine products)                  */
 /*   1 -> Z0 (one term each)                                                 */
+/* The products of bins 1.. accumulate in one FP32 sum, smallest bin first;  */
+/* Z0 in another; X = Z0 + that sum.                                         */
 /* beta == 0: C is not read (it may hold NaN).  lda >= max(1,K),             */
 /* ldb >= max(1,N), ldc >= max(1,N).  ws/ws_bytes: device workspace of at    */
 /* least bfx_gemm_ws_size(...) bytes (NULL allowed when that is 0); the      */
@@ -80,7 +84,7 @@ int bfx_split_f32(const float *a, int64_t n, int nterms, uint16_t *b0,
 /* the products run on the planes (bfx_gemm_blocks); with a smaller one the  */
 /* split happens inside the GEMM kernel.  Both give the same bits.           */
 /* Accuracy: |C - alpha A B| <= 2K 2^-24 |alpha| |A||B| componentwise for    */
-/* variants 6 and 9 (K >= 8), plus 3*2^-16 |alpha||A||B| for variant 3.      */
+/* variants 6-9 (K >= 8), plus 3*2^-16 |alpha||A||B| for variant 3.        */
 /* Errors: -1 variant, -2/-3/-4 negative sizes, -6/-8/-11 NULL operands,     */
 /* -7/-9/-12 leading dimensions, -14 workspace too small (BFX_E_WORKSPACE is */
 /* not used for this case so the argument is named).                         */
@@ -111,7 +115,7 @@ size_t bfx_split_blocks_size(int nterms, int64_t R, int64_t K);
 /* Split one FP32 operand into that layout, exactly (bfx_split_f32's terms).  */
 /* trans = 0: X is R x K row-major (the A operand, R = M), ld >= max(1,K);    */
 /* trans = 1: X is K x R row-major (the B operand, R = N), ld >= max(1,R).    */
-/* nterms: 1, 2 or 3 (variants 1, 3 and 6/9 read 1, 2 and 3 terms).          */
+/* nterms: 1, 2 or 3 (variants 1, 3 and 6-9 read 1, 2 and 3 terms).          */
 /* out: device, 16-byte aligned, out_bytes >= bfx_split_blocks_size.          */
 /* Errors: -1 nterms, -2 trans, -3 R < 0, -4 K < 0 or K, R too large for the  */
 /* 32-bit block offsets (ceil(K/32) * 8192 >= 2^31), -5 X NULL, -6 ld,        */
@@ -122,7 +126,7 @@ int bfx_split_blocks(int nterms, int trans, int64_t R, int64_t K, const float *X
 
 /* C = alpha * (A x B) + beta * C from pre-split operands: Ab from            */
 /* bfx_split_blocks(P, 0, M, K, A, ...), Bb from bfx_split_blocks(P, 1, N, K,  */
-/* B, ...), P = 1, 2, 3 for variant 1, 3, 6/9.  Same variants, accumulation   */
+/* B, ...), P = 1, 2, 3 for variant 1, 3, 6-9.  Same variants, accumulation   */
 /* order, accuracy and beta rule as bfx_gemm (bitwise equal results).  Ab, Bb  */
 /* device, 16-byte aligned, read only; C device, ldc >= max(1,N).  One        */
 /* 128 x 128 output tile per workgroup, no workspace.                         */

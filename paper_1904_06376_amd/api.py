@@ -57,7 +57,7 @@ def gemm_ws_size(variant: int, M: int, N: int, K: int) -> int:
 
 def gemm(variant: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
          alpha: float = 1.0, beta: float = 0.0, ws: torch.Tensor | None = None):
-    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,9}."""
+    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,7,8,9}."""
     _dev(A, torch.float32, "A")
     _dev(B, torch.float32, "B")
     M, K = A.shape

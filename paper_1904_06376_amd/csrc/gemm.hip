@@ -389,6 +389,8 @@ static int gemm_blocks_dispatch(int variant, const GemmParams &p, const uint16_t
         case 1: return launch_gemm_blocks<1>(p, Ab, Bb, s);
         case 3: return launch_gemm_blocks<3>(p, Ab, Bb, s);
         case 6: return launch_gemm_blocks<6>(p, Ab, Bb, s);
+        case 7: return launch_gemm_blocks<7>(p, Ab, Bb, s);
+        case 8: return launch_gemm_blocks<8>(p, Ab, Bb, s);
         case 9: return launch_gemm_blocks<9>(p, Ab, Bb, s);
         default: return -1;
     }
@@ -523,6 +525,8 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
         case 1: rc = dispatch_variant<1>(p, BM, BN, stream); break;
         case 3: rc = dispatch_variant<3>(p, BM, BN, stream); break;
         case 6: rc = dispatch_variant<6>(p, BM, BN, stream); break;
+        case 7: rc = dispatch_variant<7>(p, BM, BN, stream); break;
+        case 8: rc = dispatch_variant<8>(p, BM, BN, stream); break;
         case 9: rc = dispatch_variant<9>(p, BM, BN, stream); break;
         default: return -1;
     }
@@ -555,7 +559,7 @@ extern "C" int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alph
                         const float *A, int64_t lda, const float *B, int64_t ldb,
                         float beta, float *C, int64_t ldc, void *ws,
                         size_t ws_bytes, void *stream) {
-    if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
+    if (variant != 1 && variant != 3 && variant != 6 && variant != 7 && variant != 8 && variant != 9) return -1;
     if (M < 0) return -2;
     if (N < 0) return -3;
     if (K < 0) return -4;
@@ -595,7 +599,7 @@ extern "C" int bfx_split_blocks(int nterms, int trans, int64_t R, int64_t K, con
 extern "C" int bfx_gemm_blocks(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                                const uint16_t *Ab, const uint16_t *Bb, float beta, float *C,
                                int64_t ldc, void *stream) {
-    if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
+    if (variant != 1 && variant != 3 && variant != 6 && variant != 7 && variant != 8 && variant != 9) return -1;
     if (M < 0) return -2;
     if (N < 0) return -3;
     if (K < 0) return -4;

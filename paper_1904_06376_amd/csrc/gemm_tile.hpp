@@ -37,6 +37,15 @@ template <> struct Prods<6> {
     static constexpr int P = 3, n = 5;
     static constexpr int ai[5] = {2, 1, 0, 1, 0}, bj[5] = {0, 1, 2, 0, 1};
 };
+// x7: x6 plus A1 B2 (bin 3); x8: all of bins 0-3 (Sec. II-D, IV-A).
+template <> struct Prods<7> {
+    static constexpr int P = 3, n = 6;
+    static constexpr int ai[6] = {1, 2, 1, 0, 1, 0}, bj[6] = {2, 0, 1, 2, 0, 1};
+};
+template <> struct Prods<8> {
+    static constexpr int P = 3, n = 7;
+    static constexpr int ai[7] = {1, 2, 2, 1, 0, 1, 0}, bj[7] = {2, 1, 0, 1, 2, 0, 1};
+};
 template <> struct Prods<9> {
     static constexpr int P = 3, n = 8;
     static constexpr int ai[8] = {2, 2, 1, 2, 1, 0, 1, 0};

@@ -53,7 +53,7 @@ def test_gemm_parity_uniform(bfx, orc, variant, shape):
 
 
 @pytest.mark.parametrize("gen", ["normal", "wide", "gauss_exp"])
-@pytest.mark.parametrize("variant", [3, 6, 9])
+@pytest.mark.parametrize("variant", [3, 6, 7, 8, 9])
 def test_gemm_parity_distributions(bfx, orc, gen, variant):
     f = getattr(workloads, gen)
     A = f((160, 300), 21)
@@ -304,7 +304,7 @@ def _gemm_fused(bfx, variant, A, B, C, alpha, beta):
     assert rc == 0
 
 
-@pytest.mark.parametrize("variant", [1, 3, 6, 9])
+@pytest.mark.parametrize("variant", [1, 3, 6, 7, 8, 9])
 @pytest.mark.parametrize("shape", [(2048, 2048, 512), (2085, 2148, 1000), (2176, 2048, 1536)])
 def test_gemm_presplit_equals_fused(bfx, variant, shape):
     """With a workspace of bfx_gemm_ws_size bytes, problems of >= 256 output
@@ -432,3 +432,35 @@ def test_gemm_presplit_strided_views(bfx, variant, offset):
     got = host(tCw)
     np.testing.assert_array_equal(got[:, :N].view(np.uint32), host(Cf).view(np.uint32))
     np.testing.assert_array_equal(got[:, N:], Cw[:, N:])
+
+
+@pytest.mark.parametrize("variant", [7, 8])
+@pytest.mark.parametrize("shape", [(256, 256, 256), (200, 132, 96), (129, 257, 33), (65, 63, 44),
+                                   (64, 64, 1000)])
+def test_gemm_x7_x8_vs_oracle(bfx, orc, variant, shape):
+    """Variants 7 (x6 plus A1 B2) and 8 (bins 0-3) of Sec. II-D / IV-A:
+    within the bound of the exact product and twice of it from the oracle's
+    bin-by-bin sum, on the wave-specialised, general and split-K engines
+    (the shapes select them)."""
+    M, N, K = shape
+    A = workloads.wide((M, K), 111)
+    B = workloads.wide((K, N), 112)
+    C = host(bfx.gemm(variant, dev(A), dev(B)))
+    _check_bound(variant, A, B, C, orc.gemm(variant, A, B))
+
+
+def test_gemm_x7_x8_errors_between_x3_and_x9(bfx):
+    """On wide-range operands (2^u, u ~ U[-20, 20]) the summed absolute
+    errors against FP64 of x6, x7, x8 and x9 agree within 25% (the FP32
+    accumulation dominates once bins 0-2 are in, Sec. II-D, II-G) and all are
+    far below x3's (which drops bin 2, about 2^-16 of the product)."""
+    A = workloads.wide((256, 512), 121)
+    B = workloads.wide((512, 256), 122)
+    z = ref64(A, B)
+    err = {}
+    for v in (3, 6, 7, 8, 9):
+        err[v] = float(np.sum(np.abs(host(bfx.gemm(v, dev(A), dev(B))).astype(np.float64) - z)))
+    hi = max(err[v] for v in (6, 7, 8, 9))
+    lo = min(err[v] for v in (6, 7, 8, 9))
+    assert hi <= 1.25 * lo, err
+    assert err[3] > 8 * hi, err
