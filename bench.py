@@ -225,7 +225,7 @@ def main():
         log(f"[bench] 256^3 {small}")
 
         variants = {}
-        for v in (3, 9):
+        for v in (3, 7, 8, 9):
             for _ in range(2):
                 step(v)
             ms, _ = time_launches(torch, lambda: step(v), 5, stream)
