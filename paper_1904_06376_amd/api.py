@@ -57,7 +57,11 @@ def gemm_ws_size(variant: int, M: int, N: int, K: int) -> int:
 
 def gemm(variant: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
          alpha: float = 1.0, beta: float = 0.0, ws: torch.Tensor | None = None):
-    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,7,8,9}."""
+    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,7,8,9}.
+
+    `ws`: optional uint8 device tensor of at least gemm_ws_size(...) bytes,
+    allocated here when missing or too small; it holds split-K partial sums,
+    or, for large products, both operands' BF16 planes (split once per call)."""
     _dev(A, torch.float32, "A")
     _dev(B, torch.float32, "B")
     M, K = A.shape
