@@ -74,22 +74,21 @@ gemm_fast_kernel(GemmParams p) {
 // B (TRANS true): the block is read with 16-byte loads along rows of B into
 // LDS, then converted column by column like A.
 template <int P, bool TRANS>
-__global__ void __launch_bounds__(256)
-split_blocks_kernel(const float *__restrict__ X, int64_t ld, int64_t R, int64_t K, int KS,
-                    uint16_t *__restrict__ out, int64_t plane, bool vec) {
-    // A: consecutive workgroups take consecutive k blocks of one row band
+__device__ __forceinline__ void split_block(const float *__restrict__ X, int64_t ld, int64_t R, int64_t K,
+                                            int KS, uint16_t *__restrict__ out, int64_t plane, bool vec,
+                                            int64_t bid, float (*tile)[BK + 1]) {
+    // A: consecutive block indices take consecutive k blocks of one row band
     // (rows read as contiguous runs); B: consecutive column bands of one k
     // band, so that together they read whole rows of B
     const int64_t RB = (R + 127) / 128;
-    const int64_t r = TRANS ? (int64_t)blockIdx.x % RB : (int64_t)blockIdx.x / KS;
-    const int64_t ks = TRANS ? (int64_t)blockIdx.x / RB : (int64_t)blockIdx.x % KS;
+    const int64_t r = TRANS ? bid % RB : bid / KS;
+    const int64_t ks = TRANS ? bid / RB : bid % KS;
     const int t = threadIdx.x;
     uint16_t *blk = out + (r * KS + ks) * 4096;
     if constexpr (TRANS) {
         // 32 k rows x 128 columns through LDS: 16-byte loads along rows of B
         // (a wave reads two 512-byte rows per load), then each thread takes
         // 16 consecutive k of one column, as the A path does.
-        __shared__ float tile[128][BK + 1];   // [column][k], odd stride: conflict-free column reads
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int idx = t + 256 * i;
@@ -108,12 +107,16 @@ split_blocks_kernel(const float *__restrict__ X, int64_t ld, int64_t R, int64_t 
         }
         __syncthreads();
         const int n = t & 127, half = t >> 7;
+        float v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = tile[n][16 * half + i];
+        __syncthreads();   // the tile is refilled by the workgroup's next block
         uint32_t w[3][8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             uint32_t x[3], y[3];
-            split3_exact(tile[n][16 * half + 2 * i], x[0], x[1], x[2]);
-            split3_exact(tile[n][16 * half + 2 * i + 1], y[0], y[1], y[2]);
+            split3_exact(v[2 * i], x[0], x[1], x[2]);
+            split3_exact(v[2 * i + 1], y[0], y[1], y[2]);
 #pragma unroll
             for (int pl = 0; pl < P; ++pl) w[pl][i] = x[pl] | (y[pl] << 16);
         }
@@ -158,6 +161,34 @@ split_blocks_kernel(const float *__restrict__ X, int64_t ld, int64_t R, int64_t 
                 *reinterpret_cast<uint4 *>(blk + pl * plane + swz_off(n, (2 * half + c) * 8)) =
                     make_uint4(w[pl][4 * c], w[pl][4 * c + 1], w[pl][4 * c + 2], w[pl][4 * c + 3]);
     }
+}
+
+template <int P, bool TRANS>
+__global__ void __launch_bounds__(256)
+split_blocks_kernel(const float *__restrict__ X, int64_t ld, int64_t R, int64_t K, int KS,
+                    uint16_t *__restrict__ out, int64_t plane, bool vec) {
+    __shared__ float tile[128][BK + 1];   // [column][k], odd stride: conflict-free column reads
+    split_block<P, TRANS>(X, ld, R, K, KS, out, plane, vec, blockIdx.x, tile);
+}
+
+// Both operands of one product in one launch: workgroups [0, na) split one
+// block of A each; the other gb workgroups split B's nb blocks with a grid
+// stride (measured at 8192^2: A 144 us one block per workgroup, B 154 us
+// over 4096 workgroups vs 166-184 us one block each; one launch saves the
+// ~25 us between two).
+template <int P>
+__global__ void __launch_bounds__(256)
+split_both_kernel(const float *__restrict__ A, int64_t lda, const float *__restrict__ B, int64_t ldb,
+                  int64_t M, int64_t N, int64_t K, int KS, uint16_t *__restrict__ outA, int64_t planeA,
+                  uint16_t *__restrict__ outB, int64_t planeB, bool vecA, bool vecB, int64_t na, int64_t nb) {
+    __shared__ float tile[128][BK + 1];
+    const int64_t b = blockIdx.x;
+    if (b < na) {
+        split_block<P, false>(A, lda, M, K, KS, outA, planeA, vecA, b, tile);
+        return;
+    }
+    const int64_t gb = (int64_t)gridDim.x - na;
+    for (int64_t q = b - na; q < nb; q += gb) split_block<P, true>(B, ldb, N, K, KS, outB, planeB, vecB, q, tile);
 }
 
 // GEMM on pre-split operands (see gemm_tile_planes): one 128 x 128 tile per
@@ -396,15 +427,25 @@ static int gemm_blocks_dispatch(int variant, const GemmParams &p, const uint16_t
     }
 }
 
-// Both operands split into the workspace, then the products.
+// Both operands split into the workspace (one launch), then the products.
 static int launch_planes(int variant, const GemmParams &p, void *ws, hipStream_t s) {
     const int P = prods_p(variant);
     uint16_t *pa = (uint16_t *)ws;
     uint16_t *pb = pa + split_blocks_elems(P, p.M, p.K);
-    int rc = launch_split_blocks(P, false, p.M, p.K, p.A, p.lda, pa, s);
-    if (rc != BFX_OK) return rc;
-    rc = launch_split_blocks(P, true, p.N, p.K, p.B, p.ldb, pb, s);
-    if (rc != BFX_OK) return rc;
+    const int KS = (int)ceil_div(p.K, BK);
+    const int64_t na = ceil_div(p.M, 128) * KS, nb = ceil_div(p.N, 128) * KS;
+    const int64_t gb = nb < 4096 ? nb : 4096;
+    const bool vecA = ((uintptr_t)p.A % 16 == 0) && (p.lda % 4 == 0);
+    const bool vecB = ((uintptr_t)p.B % 16 == 0) && (p.ldb % 4 == 0);
+    const dim3 grid((unsigned)(na + gb)), block(256);
+#define BFX_SPLIT_BOTH(PP)                                                                          \
+    hipLaunchKernelGGL((split_both_kernel<PP>), grid, block, 0, s, p.A, p.lda, p.B, p.ldb, p.M, p.N, \
+                       p.K, KS, pa, na * 4096, pb, nb * 4096, vecA, vecB, na, nb);
+    if (P == 1) { BFX_SPLIT_BOTH(1) }
+    else if (P == 2) { BFX_SPLIT_BOTH(2) }
+    else { BFX_SPLIT_BOTH(3) }
+#undef BFX_SPLIT_BOTH
+    BFX_LAUNCH_CHECK("split_both_kernel launch");
     return gemm_blocks_dispatch(variant, p, pa, pb, s);
 }
 
