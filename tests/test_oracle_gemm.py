@@ -1,7 +1,8 @@
 """Pins for the oracle's split GEMM (Sec. II-C..II-G, IV-A) and its plain FP32
 comparator.  Checked against: exact integer products, identity and permutation
 invariants, the paper's componentwise error bounds against an FP64 product,
-the exact-Z0 special case, exact-rational emulation on tiny inputs, the worked
+the exact-Z0 special case, exact-rational emulation on tiny inputs (FP32 and
+FP64 bin sums), product-membership probes for every variant, the worked
 example's stated ordering and the Fig. 2 accuracy ordering."""
 import json
 import os
@@ -148,9 +149,13 @@ def test_partial_magnitudes(orc):
                 assert abs(Z[i, j]) <= (1 + gam) * (1 + 2.0 ** -8) ** 2 * 2.0 ** (-8 * (i + j)) * zh
 
 
-def _emulate(variant, x, y):
+def _emulate(variant, x, y, fp64_sum=False):
     """Exact-rational emulation of the Sec. II-D algorithm for one entry: split by
-    nearest-even rounding of rationals, FP32 FMA chains, FP32 bin sums."""
+    nearest-even rounding of rationals, FP32 FMA chains, bin sums in the printed
+    brackets (FP32, or FP64 for the "d" option of Sec. IV-A, whose FP64 result is
+    then rounded once to FP32).  Bins: Z0 = Z00, Z1 = Z01 + Z10,
+    Z2 = Z02 + (Z11 + Z20), Z3 = Z12 + Z21, Z4 = Z22; x7 adds Z12 alone as the
+    bin after Z2."""
     from tests.exact import bf16_nearest
 
     def split(v):
@@ -164,7 +169,8 @@ def _emulate(variant, x, y):
     xs = [split(v) for v in x]
     ys = [split(v) for v in y]
     need = {1: lambda i, j: i + j == 0, 3: lambda i, j: i + j <= 1,
-            6: lambda i, j: i + j <= 2, 9: lambda i, j: True}[variant]
+            6: lambda i, j: i + j <= 2, 7: lambda i, j: i + j <= 2 or (i, j) == (1, 2),
+            8: lambda i, j: i + j <= 3, 9: lambda i, j: True}[variant]
     Z = [[np.float32(0)] * 3 for _ in range(3)]
     for i in range(3):
         for j in range(3):
@@ -174,20 +180,35 @@ def _emulate(variant, x, y):
             for a, b in zip(xs, ys):
                 acc = fma32(a[i], b[j], acc)
             Z[i][j] = acc
+    if fp64_sum:
+        # FP64 additions of exact FP32 values: float(Fraction) rounds to nearest
+        def add(a, b):
+            return float(frac(a) + frac(b))
+    else:
+        add = add32
     Z0 = Z[0][0]
     if variant == 1:
-        return Z0
-    Z1 = add32(Z[0][1], Z[1][0])
-    if variant == 3:
-        return add32(Z0, Z1)
-    Z2 = add32(Z[0][2], add32(Z[1][1], Z[2][0]))
-    if variant == 6:
-        return add32(Z0, add32(Z1, Z2))
-    Z3 = add32(Z[1][2], Z[2][1])
-    return add32(Z0, add32(Z1, add32(Z2, add32(Z3, Z[2][2]))))
+        r = Z0
+    else:
+        Z1 = add(Z[0][1], Z[1][0])
+        if variant == 3:
+            r = add(Z0, Z1)
+        else:
+            Z2 = add(Z[0][2], add(Z[1][1], Z[2][0]))
+            if variant == 6:
+                r = add(Z0, add(Z1, Z2))
+            elif variant == 7:
+                r = add(Z0, add(Z1, add(Z2, Z[1][2])))
+            else:
+                Z3 = add(Z[1][2], Z[2][1])
+                if variant == 8:
+                    r = add(Z0, add(Z1, add(Z2, Z3)))
+                else:
+                    r = add(Z0, add(Z1, add(Z2, add(Z3, Z[2][2]))))
+    return fl32(frac(r)) if fp64_sum else r
 
 
-@pytest.mark.parametrize("variant", (1, 3, 6, 9))
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_exact_rational_emulation_tiny(orc, variant):
     """Brute force on tiny inputs: the C oracle equals an exact-rational emulation
     of the algorithm bit for bit (checks FMA, ordering and the bin brackets)."""
@@ -199,6 +220,98 @@ def test_exact_rational_emulation_tiny(orc, variant):
             for j in range(2):
                 e = _emulate(variant, A[i], B[:, j])
                 assert C[i, j] == e, (variant, seed, i, j, C[i, j], e)
+
+
+def _cancelling_pairs(rows, cols, seed):
+    """Operands whose products cancel in their leading terms: row i of A is
+    (a, a(1 + d)) with |d| <= 1e-3 and column j of B is (b, -b), so the bin-0
+    chain nearly cancels and the lower bins decide the low bits of the result,
+    where an FP32 and an FP64 bin sum round differently."""
+    g = np.random.default_rng(seed)
+    A = g.uniform(-1, 1, (rows, 2)).astype(np.float32)
+    A[:, 1] = A[:, 0] * (1 + g.uniform(-1e-3, 1e-3, rows)).astype(np.float32)
+    B = g.uniform(-1, 1, (2, cols)).astype(np.float32)
+    B[1, :] = -B[0, :]
+    return A, B
+
+
+@pytest.mark.parametrize("variant", (3, 6, 7, 8, 9))
+def test_exact_rational_emulation_fp64_sum(orc, variant):
+    """The "d" option of Sec. IV-A (bins and final sum in FP64, one rounding to
+    FP32 at the end) equals its exact-rational emulation bit for bit, on data
+    where it differs from the FP32 bin sum (an FP32 sum in its place fails; x3
+    has a single addition, which rounds once either way)."""
+    differ = 0
+    for seed in range(6):
+        A, B = _cancelling_pairs(6, 6, 330 + seed)
+        C = orc.gemm(variant, A, B, fp64_sum=True)
+        differ += int(np.sum(C != orc.gemm(variant, A, B)))
+        for i in range(6):
+            for j in range(6):
+                e = _emulate(variant, A[i], B[:, j], fp64_sum=True)
+                assert C[i, j] == e, (variant, seed, i, j, C[i, j], e)
+    if variant >= 6:
+        assert differ > 0, "inputs do not separate the FP64 from the FP32 bin sum"
+    else:
+        assert differ == 0
+
+
+def test_each_product_is_in_exactly_its_variants(orc):
+    """Which products each variant includes (Sec. II-D: x3 = bins 0-1, x6 = bins
+    0-2, x8 = bins 0-3, x9 = all; x7 = x6 + Z^(1,2), the worked example of
+    Sec. II-G), isolated with K = 2 operands built from a = 1 + 2^-9 + 2^-18,
+    a' = 1 + 2^-9 + 2^-19, c = 1 + 2^-9 and c' = 1 + 2^-10, which split as
+    (1, 2^-9, 2^-18), (1, 2^-9, 2^-19), (1, 2^-9, 0) and (1, 2^-10, 0):
+      x = (a, a),  y = (a, -a'):  only Z^(i,2) = a_i 2^-19 survive;
+      x = (a, -a'), y = (a, a):   only Z^(2,j) = 2^-19 a_j survive;
+      x = (a, a),  y = (c, -c'):  only Z^(i,1) = a_i 2^-10 survive;
+      x = (c, -c'), y = (a, a):   only Z^(1,j) = 2^-10 a_j survive.
+    Every chain and bin sum is exact, so the result is the exact sum of the
+    included products; a product dropped from or added to any variant (x8 without
+    Z^(2,1), x7 with Z^(2,1), ...) changes one of the two results."""
+    a = np.float32(1.0 + 2.0 ** -9 + 2.0 ** -18)
+    a2 = np.float32(1.0 + 2.0 ** -9 + 2.0 ** -19)
+    ta = [float(orc.bf16_bits_to_f32(h)[0]) for h in orc.split(np.array([a]))]
+    ta2 = [float(orc.bf16_bits_to_f32(h)[0]) for h in orc.split(np.array([a2]))]
+    c = np.float32(1.0 + 2.0 ** -9)
+    c2 = np.float32(1.0 + 2.0 ** -10)
+    tc = [float(orc.bf16_bits_to_f32(h)[0]) for h in orc.split(np.array([c]))]
+    tc2 = [float(orc.bf16_bits_to_f32(h)[0]) for h in orc.split(np.array([c2]))]
+    assert ta == [1.0, 2.0 ** -9, 2.0 ** -18] and ta2 == [1.0, 2.0 ** -9, 2.0 ** -19]
+    assert tc == [1.0, 2.0 ** -9, 0.0] and tc2 == [1.0, 2.0 ** -10, 0.0]
+    included = {
+        1: {(0, 0)},
+        3: {(0, 0), (0, 1), (1, 0)},
+        6: {(i, j) for i in range(3) for j in range(3) if i + j <= 2},
+        7: {(i, j) for i in range(3) for j in range(3) if i + j <= 2} | {(1, 2)},
+        8: {(i, j) for i in range(3) for j in range(3) if i + j <= 3},
+        9: {(i, j) for i in range(3) for j in range(3)},
+    }
+    F = Fraction
+    probes = {
+        "column": (np.array([[a, a]], np.float32), np.array([[a], [-a2]], np.float32),
+                   lambda i, j: F(ta[i]) * (F(ta[j]) - F(ta2[j]))),
+        "row": (np.array([[a, -a2]], np.float32), np.array([[a], [a]], np.float32),
+                lambda i, j: (F(ta[i]) - F(ta2[i])) * F(ta[j])),
+        "column1": (np.array([[a, a]], np.float32), np.array([[c], [-c2]], np.float32),
+                    lambda i, j: F(ta[i]) * (F(tc[j]) - F(tc2[j]))),
+        "row1": (np.array([[c, -c2]], np.float32), np.array([[a], [a]], np.float32),
+                 lambda i, j: (F(tc[i]) - F(tc2[i])) * F(ta[j])),
+    }
+    seen = {}
+    for name, (X, Y, Zij) in probes.items():
+        for v, inc in included.items():
+            exact = sum((Zij(i, j) for (i, j) in inc), F(0))
+            assert fl32(exact) == exact  # representable: the result must be exact
+            seen[(name, v)] = exact
+            for d in (False, True):
+                got = orc.gemm(v, X, Y, fp64_sum=d)[0, 0]
+                assert F(float(got)) == exact, (name, v, d, float(got), float(exact))
+    # the probes separate every pair of variants
+    for v in included:
+        for w in included:
+            if v < w:
+                assert any(seen[(p, v)] != seen[(p, w)] for p in probes), (v, w)
 
 
 def test_worked_example_ordering(orc):
