@@ -93,11 +93,11 @@ def sampled_errors(A, B, C, variant, nsample=256, seed=0):
     z = np.einsum("ij,ji->i", Ar, Bc)
     zh = np.einsum("ij,ji->i", np.abs(Ar), np.abs(Bc))
     K = A.shape[1]
-    if variant in (6, 9):
+    if variant >= 6:            # x6, x7, x8, x9: 2K 2^-24 |A||B|
         bnd = 2 * K * 2.0 ** -24
     elif variant == 3:
         bnd = 3 * 2.0 ** -16 + 2 * K * 2.0 ** -24
-    else:
+    else:                       # FP32 comparators (variant 0): gamma_K
         bnd = K * 2.0 ** -24
     got = C[r, c].astype(np.float64)
     ratio = np.abs(got - z) / (bnd * zh)
@@ -383,6 +383,15 @@ def main():
     }
     out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def eta_check(torch, A, b, x):
+    """Normwise backward error of x recomputed in FP64 from A (FP32, promoted
+    exactly), b and x: |b - A x|_inf / (|A|_inf |x|_inf + |b|_inf)."""
+    A64 = A.to(torch.float64)
+    r = b - A64 @ x
+    den = A64.abs().sum(dim=1).max() * x.abs().max() + b.abs().max()
+    return float((r.abs().max() / den).item())
 
 
 def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
