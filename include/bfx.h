@@ -97,6 +97,29 @@ int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,
 /* or the pre-split planes of both operands; 0 when it needs neither.        */
 size_t bfx_gemm_ws_size(int variant, int64_t M, int64_t N, int64_t K);
 
+/* For callers that cannot allocate device memory (code under HIP graph      */
+/* capture, tight serving loops, harnesses that forbid hipMalloc): bfx_gemm   */
+/* without a workspace argument.  Same arguments (minus ws, ws_bytes), same   */
+/* kernels, same bits and the same error codes as bfx_gemm.  The workspace is */
+/* a fixed device array inside the library, bfx_gemm_noalloc_scratch_bytes() */
+/* (64 MiB) long, that every GPU the library runs on holds from the first    */
+/* call on it until the process ends.  It holds the split-K partial sums of  */
+/* long inner dimensions and, when they fit, the pre-split planes of large   */
+/* products (when they do not, the split happens inside the GEMM kernel, as  */
+/* in bfx_gemm with a small workspace).  A shape whose split-K partial sums   */
+/* exceed the scratch is rejected with BFX_E_WORKSPACE before any launch     */
+/* (the message names both sizes).  The call allocates nothing, on the host  */
+/* or the device.  All calls on one GPU share that GPU's scratch and leave   */
+/* their contents in it: calls that overlap in time on one GPU (different    */
+/* streams, or different host threads) race and give wrong results; calls   */
+/* ordered on one stream are safe.                                           */
+int bfx_gemm_noalloc(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+                     const float *A, int64_t lda, const float *B, int64_t ldb,
+                     float beta, float *C, int64_t ldc, void *stream);
+
+/* Size of bfx_gemm_noalloc's fixed device scratch in bytes. */
+size_t bfx_gemm_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------------------------ */
 /* Pre-split operands (Sec. II-A once per operand, then Sec. II-D, II-G).   */
 /* Splitting costs O(N^2) against the O(N^3) products (Sec. V), so an        */

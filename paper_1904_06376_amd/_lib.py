@@ -66,6 +66,9 @@ SIGNATURES = {
     "bfx_gemm": ([c_int, c_i64, c_i64, c_i64, c_f32, c_vp, c_i64, c_vp, c_i64,
                   c_f32, c_vp, c_i64, c_vp, c_size, c_vp], c_int),
     "bfx_gemm_ws_size": ([c_int, c_i64, c_i64, c_i64], c_size),
+    "bfx_gemm_noalloc": ([c_int, c_i64, c_i64, c_i64, c_f32, c_vp, c_i64, c_vp, c_i64,
+                          c_f32, c_vp, c_i64, c_vp], c_int),
+    "bfx_gemm_noalloc_scratch_bytes": ([], c_size),
     "bfx_split_blocks_size": ([c_int, c_i64, c_i64], c_size),
     "bfx_split_blocks": ([c_int, c_int, c_i64, c_i64, c_vp, c_i64, c_vp, c_size, c_vp], c_int),
     "bfx_gemm_blocks": ([c_int, c_i64, c_i64, c_i64, c_f32, c_vp, c_vp, c_f32, c_vp, c_i64, c_vp],

@@ -2,7 +2,9 @@
 // split-K for long inner dimensions with a deterministic fixed-order
 // reduction, and the host-side tile / split policy.  The tile engine itself
 // is in gemm_tile.hpp.
+#include <cstdio>
 #include <cstdlib>
+#include <mutex>
 
 #include "gemm_tile.hpp"
 
@@ -664,4 +666,80 @@ extern "C" int bfx_gemm_blocks(int variant, int64_t M, int64_t N, int64_t K, flo
     p.splits = 1;
     p.k_per_split = KS * bfx::BK;
     return bfx::gemm_blocks_dispatch(variant, p, Ab, Bb, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of bfx_gemm for callers that cannot allocate device
+// memory.  Its workspace is `scratch`, a file-scope device array that every
+// GPU the library runs on holds for the life of the process.  In host code
+// the array's name is only a host-side stand-in: the device address is taken
+// once per device with hipGetSymbolAddress and only that address is used.
+// ---------------------------------------------------------------------------
+namespace bfx {
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up on the
+// first call on that device (with the device current) and kept.
+int scratch_address(void **out) {
+    int dev = 0;
+    BFX_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("bfx_gemm_noalloc: device index beyond the supported range");
+        return BFX_E_INTERNAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        BFX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("bfx_gemm_noalloc: hipGetSymbolAddress returned no address");
+            return BFX_E_INTERNAL;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BFX_OK;
+}
+}  // namespace
+}  // namespace bfx
+
+extern "C" size_t bfx_gemm_noalloc_scratch_bytes(void) { return bfx::NOALLOC_SCRATCH_BYTES; }
+
+extern "C" int bfx_gemm_noalloc(int variant, int64_t M, int64_t N, int64_t K, float alpha,
+                                const float *A, int64_t lda, const float *B, int64_t ldb,
+                                float beta, float *C, int64_t ldc, void *stream) {
+    if (variant != 1 && variant != 3 && variant != 6 && variant != 7 && variant != 8 && variant != 9) return -1;
+    if (M < 0) return -2;
+    if (N < 0) return -3;
+    if (K < 0) return -4;
+    if (lda < (K > 1 ? K : 1)) return -7;
+    if (ldb < (N > 1 ? N : 1)) return -9;
+    if (ldc < (N > 1 ? N : 1)) return -12;
+    if (M == 0 || N == 0) return BFX_OK;
+    if (K > 0 && !A) return -6;
+    if (K > 0 && !B) return -8;
+    if (!C) return -11;
+    // split-K partial sums are the only workspace the product cannot do without
+    const size_t need = bfx::gemm_ws_bytes(variant, M, N, K);
+    if (need > bfx::NOALLOC_SCRATCH_BYTES) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "bfx_gemm_noalloc: this shape needs %zu bytes of split-K scratch, "
+                      "beyond the fixed maximum of %zu bytes",
+                      need, bfx::NOALLOC_SCRATCH_BYTES);
+        bfx::set_error(buf);
+        return BFX_E_WORKSPACE;
+    }
+    void *ptr = nullptr;
+    const int rc = bfx::scratch_address(&ptr);
+    if (rc) return rc;
+    return bfx::gemm_launch(variant, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ptr,
+                            bfx::NOALLOC_SCRATCH_BYTES, (hipStream_t)stream);
 }

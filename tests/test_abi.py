@@ -75,3 +75,14 @@ def test_argument_errors_before_device_use():
     assert lib.bfx_gemm_blocks(6, 4, 4, 4, 1.0, v, v, 0.0, None, 4, None) == -9
     assert lib.bfx_gemm_blocks(6, 4, 4, 4, 1.0, v, v, 0.0, v, 3, None) == -10
     assert lib.bfx_gemm_blocks(6, 0, 4, 4, 1.0, None, None, 0.0, None, 4, None) == 0
+
+
+def test_noalloc_argument_errors_before_device_use():
+    from paper_1904_06376_amd._lib import lib
+    v = ctypes.c_void_p(16)
+    assert lib.bfx_gemm_noalloc_scratch_bytes() == 64 << 20
+    assert lib.bfx_gemm_noalloc(5, 4, 4, 4, 1.0, v, 4, v, 4, 0.0, v, 4, None) == -1
+    assert lib.bfx_gemm_noalloc(6, 4, -1, 4, 1.0, v, 4, v, 4, 0.0, v, 4, None) == -3
+    assert lib.bfx_gemm_noalloc(6, 4, 4, 4, 1.0, v, 4, None, 4, 0.0, v, 4, None) == -8
+    assert lib.bfx_gemm_noalloc(6, 4, 4, 4, 1.0, v, 4, v, 4, 0.0, None, 4, None) == -11
+    assert lib.bfx_gemm_noalloc(6, 0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, None) == 0
