@@ -250,17 +250,22 @@ typedef struct bfx_ir_opts {
 
 typedef struct bfx_ir_result {
     int32_t iters;     /* corrections applied */
-    int32_t status;    /* 0 converged, 1 max_iter reached, 2 stagnated
-                          (eta did not decrease twice in a row),
-                          3 non-finite residual */
+    int32_t status;    /* 0 converged, 1 max_iter reached (also: not yet
+                          decided), 2 stagnated (eta did not decrease twice
+                          in a row), 3 non-finite residual, 4 a kernel's
+                          bounded wait expired (internal error) */
     double eta;        /* backward error of the returned x */
 } bfx_ir_result;
 
 /* A: the FP32 matrix that was factored (n x n, lda), LU/ipiv: the output of
  * bfx_lu_factor (ldlu), b: n FP64 (device), x: n FP64 (device, output),
- * opts: HOST pointer (NULL = defaults), res: HOST pointer (written before
- * return).  This call synchronises `stream` once per refinement step to read
- * the convergence test.  ws: device workspace of bfx_ir_ws_size(n) bytes.
+ * opts: HOST pointer (NULL = defaults), res: DEVICE pointer to one
+ * bfx_ir_result, written by the convergence test on the device.
+ * Asynchronous: the call queues the whole solve on `stream` and returns
+ * without waiting; the test that stops the refinement runs on the device,
+ * and the steps queued after it return at once.  Read x and *res after the
+ * stream has reached this point.  ws: device workspace of bfx_ir_ws_size(n)
+ * bytes, in use until then.
  * Errors: -1 n, -2 A, -3 lda, -4 LU, -5 ldlu, -6 ipiv, -7 b, -8 x,
  * -9 opts (tol < 0 or max_iter < 0), -10 res, -12 workspace. */
 int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
@@ -282,7 +287,7 @@ size_t bfx_ir_ws_size(int64_t n);
 /* ------------------------------------------------------------------------ */
 typedef struct bfx_gmres_opts {
     double tol;         /* backward error target (default 1e-14) */
-    int32_t max_iter;   /* refinement steps (default 30) */
+    int32_t max_iter;   /* refinement steps (default 10) */
     int32_t restart;    /* GMRES steps per refinement step (default 50) */
     double inner_tol;   /* relative GMRES tolerance (default 1e-8) */
 } bfx_gmres_opts;
@@ -295,10 +300,15 @@ typedef struct bfx_gmres_result {
     double eta;
 } bfx_gmres_result;
 
-/* Arguments as bfx_ir_solve (opts/res are HOST pointers; this call
- * synchronises `stream` once per GMRES step).  ws: bfx_gmres_ir_ws_size(n,
- * restart) bytes.  Errors as bfx_ir_solve; -9 also for restart < 1 or a
- * negative inner_tol. */
+/* Arguments as bfx_ir_solve; res is a DEVICE pointer and the call is
+ * asynchronous in the same way: GMRES orthogonalises the basis (classical
+ * Gram-Schmidt twice), applies the Givens rotations of its Hessenberg
+ * least-squares problem and solves it on the device.  The host queues
+ * max_iter refinement steps of `restart` GMRES steps each; every step after
+ * a cycle or the refinement has stopped costs one empty launch per kernel.
+ * ws: bfx_gmres_ir_ws_size(n, restart) bytes (the basis, (restart+1) n
+ * doubles, and the rotated Hessenberg matrix, restart^2 doubles, dominate).
+ * Errors as bfx_ir_solve; -9 also for restart < 1 or a negative inner_tol. */
 int bfx_gmres_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
                        int64_t ldlu, const int32_t *ipiv, const double *b,
                        double *x, const bfx_gmres_opts *opts,
@@ -341,8 +351,9 @@ int bfx_lu_ir_batched_plan_create(int variant, int64_t count,
 /* All solves as one graph replay on `stream` (asynchronous). */
 int bfx_solve_plan_launch(bfx_solve_plan *plan, void *stream);
 
-/* Same solves with bfx_lu_factor + bfx_ir_solve per problem (the baseline the
- * persistent launch is measured against; synchronises after each problem). */
+/* Same solves with bfx_lu_factor + bfx_ir_solve per problem, queued one
+ * after another on `stream` (the baseline the persistent launch is measured
+ * against). */
 int bfx_solve_plan_launch_per_problem(bfx_solve_plan *plan, void *stream);
 
 /* Synchronises the device and copies the per-problem refinement results and

@@ -209,9 +209,39 @@ def lu_solve_f32(LU: torch.Tensor, ipiv: torch.Tensor, rhs: torch.Tensor):
     return rhs
 
 
+class DeviceResult:
+    """A bfx_ir_result / bfx_gmres_result that the library writes in device
+    memory.  Reading a field copies it to the host (which waits for the
+    solve); ``device`` is the raw byte tensor for callers that stay on the
+    device."""
+
+    def __init__(self, ctype, device):
+        self._ctype = ctype
+        self.device = torch.zeros(ctypes.sizeof(ctype), dtype=torch.uint8, device=device)
+        self._host = None
+
+    def ptr(self):
+        return ctypes.cast(ctypes.c_void_p(self.device.data_ptr()), ctypes.POINTER(self._ctype))
+
+    def to_dict(self):
+        if self._host is None:
+            raw = bytes(self.device.cpu().numpy().tobytes())
+            r = self._ctype.from_buffer_copy(raw)
+            self._host = {name: getattr(r, name) for name, _ in self._ctype._fields_ if name != "reserved"}
+        return self._host
+
+    def __getitem__(self, key):
+        return self.to_dict()[key]
+
+    def __repr__(self):
+        return repr(self.to_dict())
+
+
 def ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Tensor,
              tol: float = 1e-14, max_iter: int = 30, x: torch.Tensor | None = None):
-    """Residual-form iterative refinement; returns (x, dict(iters, status, eta))."""
+    """Residual-form iterative refinement, queued on the current stream
+    without waiting; returns (x, result) where result is a DeviceResult
+    (fields iters, status, eta, read on first access)."""
     n = A.shape[0]
     _dev(b, torch.float64, "b")
     if x is None:
@@ -219,19 +249,21 @@ def ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Ten
     need = lib.bfx_ir_ws_size(n)
     ws = _ws(need, A.device)
     opts = IrOpts(tol, max_iter, 0)
-    res = IrResult()
+    res = DeviceResult(IrResult, A.device)
     check(lib.bfx_ir_solve(n, A.data_ptr(), _rows(A, "A"), LU.data_ptr(), _rows(LU, "LU"),
                            ipiv.data_ptr(), b.data_ptr(), x.data_ptr(), ctypes.byref(opts),
-                           ctypes.byref(res), ws.data_ptr() if ws is not None else None,
+                           res.ptr(), ws.data_ptr() if ws is not None else None,
                            need, _stream()), "bfx_ir_solve")
-    return x, dict(iters=res.iters, status=res.status, eta=res.eta)
+    res._keep = ws
+    return x, res
 
 
 def gmres_ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Tensor,
-                   tol: float = 1e-14, max_iter: int = 30, restart: int = 50,
+                   tol: float = 1e-14, max_iter: int = 10, restart: int = 50,
                    inner_tol: float = 1e-8, x: torch.Tensor | None = None):
-    """Refinement with LU-preconditioned FP64 GMRES as the correction solver;
-    returns (x, dict(iters, inner, status, eta))."""
+    """Refinement with LU-preconditioned FP64 GMRES as the correction solver,
+    queued without waiting; returns (x, DeviceResult with iters, inner,
+    status, eta)."""
     n = A.shape[0]
     _dev(b, torch.float64, "b")
     if x is None:
@@ -239,12 +271,13 @@ def gmres_ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: tor
     need = lib.bfx_gmres_ir_ws_size(n, restart)
     ws = _ws(need, A.device)
     opts = GmresOpts(tol, max_iter, restart, inner_tol)
-    res = GmresResult()
+    res = DeviceResult(GmresResult, A.device)
     check(lib.bfx_gmres_ir_solve(n, A.data_ptr(), _rows(A, "A"), LU.data_ptr(), _rows(LU, "LU"),
                                  ipiv.data_ptr(), b.data_ptr(), x.data_ptr(), ctypes.byref(opts),
-                                 ctypes.byref(res), ws.data_ptr() if ws is not None else None,
+                                 res.ptr(), ws.data_ptr() if ws is not None else None,
                                  need, _stream()), "bfx_gmres_ir_solve")
-    return x, dict(iters=res.iters, inner=res.inner, status=res.status, eta=res.eta)
+    res._keep = ws
+    return x, res
 
 
 class BatchedSolvePlan:

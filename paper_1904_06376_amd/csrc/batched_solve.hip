@@ -511,12 +511,9 @@ extern "C" int bfx_solve_plan_launch_per_problem(bfx_solve_plan *p, void *stream
         int rc = bfx_lu_factor(p->variant, d.n, lu, d.n, p->d_ipiv + p->piv_off[i], p->d_info + i, p->d_ws,
                                p->ws_bytes, s);
         if (rc) return rc;
-        bfx_ir_result r;
-        rc = bfx_ir_solve(d.n, d.A, d.lda, lu, d.n, p->d_ipiv + p->piv_off[i], d.b, d.x, &p->opts, &r,
-                          p->d_ws, p->ws_bytes, s);
+        rc = bfx_ir_solve(d.n, d.A, d.lda, lu, d.n, p->d_ipiv + p->piv_off[i], d.b, d.x, &p->opts,
+                          p->d_res + i, p->d_ws, p->ws_bytes, s);
         if (rc) return rc;
-        BFX_HIP(hipMemcpyAsync(p->d_res + i, &r, sizeof r, hipMemcpyHostToDevice, s));
-        BFX_HIP(hipStreamSynchronize(s));
     }
     return BFX_OK;
 }

@@ -1,21 +1,41 @@
-// Iterative refinement in residual form (Sec. III) and the FP32 LU solve.
+// Iterative refinement in residual form (Sec. III), GMRES-IR (Sec. III,
+// Sec. IV-B) and the FP32 LU solve.
 //
 //   x0 = LUsolve32(b);  repeat: r = b - A x (FP64, A promoted exactly),
 //   eta = |r|_inf / (|A|_inf |x|_inf + |b|_inf), stop when eta <= tol;
-//   s = |r|_inf, d = s * LUsolve32(r / s), x += d (FP64).
+//   LU-IR:    s = |r|_inf, d = s * LUsolve32(r / s), x += d (FP64);
+//   GMRES-IR: d from GMRES on M^-1 A d = M^-1 r (FP64, M = the FP32 factors
+//             applied in FP64 arithmetic), x += d.
 //
 // Only the cubic LU is low precision; every quadratic step is FP64 except the
-// two FP32 triangular solves with the stored factors.  Kernels:
+// FP32 triangular solves of LU-IR.
+//
+// Device residency.  A solve is one stream of kernels that the host queues
+// without waiting: the convergence test runs on the device (ir_check_kernel)
+// and writes the caller's bfx_ir_result / bfx_gmres_result in device memory;
+// once it decides to stop, it sets a flag that every later kernel of the
+// solve reads first and returns on.  The host therefore queues the largest
+// possible number of steps (max_iter corrections, and `restart` GMRES steps
+// per correction); the steps after convergence cost one empty launch each.
+// GMRES keeps its Hessenberg least-squares problem on the device as well
+// (givens_kernel applies the rotations, backsolve_kernel solves R y = g).
+//
+// Kernels:
 //   residual_kernel  one workgroup per row, FP64 FMA, |r|_inf by atomicMax on
 //                    the bit pattern of a non-negative double (order-free);
 //   trsv_kernel      blocked triangular solve without a global barrier: each
 //                    workgroup takes the next block row from a ticket counter,
 //                    waits (bounded) on the completion flags of the blocks it
 //                    depends on, adds their contribution, solves its 128 x 128
-//                    diagonal block in one wave and publishes its flag;
+//                    diagonal block in one wave and publishes its flag.  Flags
+//                    hold the number of the launch that set them, so that no
+//                    launch has to clear them for the next;
 //   perm_kernel      the row permutation of ipiv, composed once per solve
-//                    (every position evaluated in parallel).
-// The host reads |r|_inf and |x|_inf once per step to apply the stopping rule.
+//                    (every position evaluated in parallel);
+//   GMRES            matvec_perm_kernel (P A v, materialising the basis
+//                    vector), dots_kernel / combine_kernel (classical
+//                    Gram-Schmidt applied twice), givens_kernel,
+//                    backsolve_kernel, update with the basis.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -29,8 +49,26 @@ namespace {
 constexpr int TB = 128;
 constexpr size_t TRSV_LDS = sizeof(float) * TB * (TB + 1);
 constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
+constexpr int CROWS = 64;                  // rows per workgroup of the basis kernels
 
 enum { S_NORMA = 0, S_NORMB = 1, S_RN = 2, S_XN = 3, S_NSCAL = 8 };
+
+// Refinement state in device memory.
+struct IrCtrl {
+    int32_t done;      // refinement finished: every later kernel returns at once
+    int32_t iters;     // corrections applied (or about to be)
+    int32_t status;
+    int32_t rises;     // consecutive checks whose eta did not decrease
+    int32_t inner;     // GMRES steps in total
+    int32_t k;         // basis vectors of the current GMRES cycle
+    int32_t gdone;     // the current GMRES cycle has finished
+    int32_t err;       // a bounded wait expired
+    double eta, prev_eta;
+    double rn;         // |r|_inf of the current residual
+    double beta;       // GMRES: |M^-1 r|_2 at the start of the cycle
+    double rinv;       // GMRES: 1 / norm of the next basis vector
+    double pad;
+};
 
 struct IrWs {
     int32_t *perm;
@@ -39,7 +77,8 @@ struct IrWs {
     int32_t *flags;   // [nblk]
     uint32_t *ticket; // [4]
     unsigned long long *scal;  // [S_NSCAL]
-    int32_t *err;
+    IrCtrl *ctrl;
+    double *part;     // [ceil(n / CROWS)]
 };
 
 size_t ir_ws_layout(IrWs *w, void *base, int64_t n) {
@@ -49,14 +88,16 @@ size_t ir_ws_layout(IrWs *w, void *base, int64_t n) {
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const int64_t nb = ceil_div(n > 0 ? n : 1, TB);
-    const size_t o_perm = take(sizeof(int32_t) * (n > 0 ? n : 1));
-    const size_t o_w = take(sizeof(float) * (n > 0 ? n : 1));
-    const size_t o_r = take(sizeof(double) * (n > 0 ? n : 1));
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t nb = ceil_div(nn, TB);
+    const size_t o_perm = take(sizeof(int32_t) * nn);
+    const size_t o_w = take(sizeof(float) * nn);
+    const size_t o_r = take(sizeof(double) * nn);
     const size_t o_f = take(sizeof(int32_t) * nb);
     const size_t o_t = take(sizeof(uint32_t) * 4);
     const size_t o_s = take(sizeof(unsigned long long) * S_NSCAL);
-    const size_t o_e = take(sizeof(int32_t) * 4);
+    const size_t o_c = take(sizeof(IrCtrl));
+    const size_t o_p = take(sizeof(double) * ceil_div(nn, CROWS));
     if (w && base) {
         char *b = (char *)base;
         w->perm = (int32_t *)(b + o_perm);
@@ -65,15 +106,40 @@ size_t ir_ws_layout(IrWs *w, void *base, int64_t n) {
         w->flags = (int32_t *)(b + o_f);
         w->ticket = (uint32_t *)(b + o_t);
         w->scal = (unsigned long long *)(b + o_s);
-        w->err = (int32_t *)(b + o_e);
+        w->ctrl = (IrCtrl *)(b + o_c);
+        w->part = (double *)(b + o_p);
     }
     return off;
+}
+
+// A kernel of the solve returns at once when the refinement has stopped, and
+// a kernel of a GMRES step (inner = 1) also when the current cycle has.
+__device__ __forceinline__ bool stopped(const IrCtrl *c, int inner) {
+    return c && (c->done || (inner && c->gdone));
 }
 }  // namespace
 
 __device__ __forceinline__ void atomic_max_abs(unsigned long long *dst, double v) {
     // |v| as a non-negative double orders like its bit pattern (NaN above Inf)
     atomicMax(dst, (unsigned long long)__double_as_longlong(fabs(v)));
+}
+
+__device__ __forceinline__ double bits_double(unsigned long long u) { return __longlong_as_double((long long)u); }
+
+// Start of a solve: clear the block flags, tickets, reduction scalars and the
+// control block; the caller's result says "not converged" until a check runs.
+__global__ void __launch_bounds__(256)
+ir_begin_kernel(IrCtrl *c, unsigned long long *scal, uint32_t *ticket, int32_t *flags, int64_t nflags) {
+    for (int64_t i = threadIdx.x; i < nflags; i += 256) flags[i] = 0;
+    if (threadIdx.x < 4) ticket[threadIdx.x] = 0u;
+    if (threadIdx.x < S_NSCAL) scal[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) {
+        IrCtrl z;
+        z.done = 0; z.iters = 0; z.status = 1; z.rises = 0;
+        z.inner = 0; z.k = 0; z.gdone = 1; z.err = 0;
+        z.eta = 0.0; z.prev_eta = INFINITY; z.rn = 1.0; z.beta = 0.0; z.rinv = 0.0; z.pad = 0.0;
+        *c = z;
+    }
 }
 
 __global__ void __launch_bounds__(256) zero_i32(int32_t *p, int64_t n) {
@@ -106,9 +172,11 @@ __global__ void __launch_bounds__(256) perm_kernel(const int32_t *ipiv, int64_t 
     perm[pos] = p;
 }
 
-// w[i] = (float)(src[perm[i]] / div)   (src FP64)
+// w[i] = (float)(src[perm[i]] / div), div = 1 or the current |r|_inf.
 __global__ void __launch_bounds__(256)
-gather_f64_to_f32(const double *src, const int32_t *perm, double div, float *w, int64_t n) {
+gather_f64_to_f32(const double *src, const int32_t *perm, const IrCtrl *c, int use_rn, float *w, int64_t n) {
+    if (stopped(c, 0)) return;
+    const double div = use_rn ? c->rn : 1.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         w[i] = (float)(src[perm[i]] / div);
 }
@@ -119,14 +187,23 @@ gather_f32(const float *src, const int32_t *perm, float *w, int64_t n) {
         w[i] = src[perm[i]];
 }
 
+__global__ void __launch_bounds__(256)
+gather_f64(const double *src, const int32_t *perm, double *out, int64_t n, const IrCtrl *c) {
+    if (stopped(c, 0)) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = src[perm[i]];
+}
+
 __global__ void __launch_bounds__(256) copy_f32(const float *src, float *dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         dst[i] = src[i];
 }
 
-// x = (double) w   (init)   or   x += s * (double) w   (update)
+// x = (double) w   (init)   or   x += |r|_inf * (double) w   (update)
 __global__ void __launch_bounds__(256)
-update_x(double *x, const float *w, double s, int init, int64_t n) {
+update_x(double *x, const float *w, const IrCtrl *c, int init, int64_t n) {
+    if (stopped(c, 0)) return;
+    const double s = c->rn;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         x[i] = init ? (double)w[i] : fma(s, (double)w[i], x[i]);
 }
@@ -141,27 +218,34 @@ __device__ __forceinline__ T block_sum_256(T v, T *red) {
     return s;
 }
 
-// r_i = b_i - sum_j A_ij x_j in FP64; |r|_inf into scal[S_RN].
-__global__ void __launch_bounds__(256)
-residual_kernel(const float *A, int64_t lda, int64_t n, const double *b, const double *x,
-                double *r, unsigned long long *scal, int vec) {
-    __shared__ double red[4];
-    const int64_t row = blockIdx.x;
-    const float *a = A + row * lda;
+// Sum_j A[row, j] * (v[j] * scale), A promoted exactly, fixed-order reduction
+// over the workgroup (every thread gets the sum).
+__device__ __forceinline__ double row_dot(const float *a, int64_t n, const double *v, double scale, int vec,
+                                          double *red) {
     double s = 0.0;
     if (vec) {
         for (int64_t j = 4 * threadIdx.x; j + 3 < n; j += 1024) {
-            const float4 v = *reinterpret_cast<const float4 *>(a + j);
-            s = fma((double)v.x, x[j], s);
-            s = fma((double)v.y, x[j + 1], s);
-            s = fma((double)v.z, x[j + 2], s);
-            s = fma((double)v.w, x[j + 3], s);
+            const float4 q = *reinterpret_cast<const float4 *>(a + j);
+            s = fma((double)q.x, v[j] * scale, s);
+            s = fma((double)q.y, v[j + 1] * scale, s);
+            s = fma((double)q.z, v[j + 2] * scale, s);
+            s = fma((double)q.w, v[j + 3] * scale, s);
         }
-        for (int64_t j = (n & ~int64_t(3)) + threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+        for (int64_t j = (n & ~int64_t(3)) + threadIdx.x; j < n; j += 256) s = fma((double)a[j], v[j] * scale, s);
     } else {
-        for (int64_t j = threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+        for (int64_t j = threadIdx.x; j < n; j += 256) s = fma((double)a[j], v[j] * scale, s);
     }
-    s = block_sum_256(s, red);
+    return block_sum_256(s, red);
+}
+
+// r_i = b_i - sum_j A_ij x_j in FP64; |r|_inf into scal[S_RN].
+__global__ void __launch_bounds__(256)
+residual_kernel(const float *A, int64_t lda, int64_t n, const double *b, const double *x,
+                double *r, unsigned long long *scal, int vec, const IrCtrl *c) {
+    __shared__ double red[4];
+    if (stopped(c, 0)) return;
+    const int64_t row = blockIdx.x;
+    const double s = row_dot(A + row * lda, n, x, 1.0, vec, red);
     if (threadIdx.x == 0) {
         const double ri = b[row] - s;
         r[row] = ri;
@@ -181,7 +265,8 @@ mat_norm_kernel(const float *A, int64_t lda, int64_t n, unsigned long long *scal
 }
 
 __global__ void __launch_bounds__(256)
-vec_absmax_kernel(const double *v, int64_t n, unsigned long long *dst) {
+vec_absmax_kernel(const double *v, int64_t n, unsigned long long *dst, const IrCtrl *c) {
+    if (stopped(c, 0)) return;
     double m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const double a = fabs(v[i]);
@@ -192,6 +277,57 @@ vec_absmax_kernel(const double *v, int64_t n, unsigned long long *dst) {
         if (o > m || o != o) m = o;
     }
     if ((threadIdx.x & 63) == 0) atomic_max_abs(dst, m);
+}
+
+// The convergence test of check number `check` (0-based, = corrections
+// applied so far), one thread: eta from the reduced norms, then the stopping
+// rule; writes the caller's result, and either stops the solve or clears the
+// reductions for the next residual.  Status: 0 converged, 1 max_iter
+// reached, 2 stagnated (eta did not decrease twice in a row), 3 non-finite,
+// 4 a bounded wait expired.
+__global__ void __launch_bounds__(64)
+ir_check_kernel(IrCtrl *c, unsigned long long *scal, bfx_ir_result *res, bfx_gmres_result *gres,
+                double tol, int max_iter) {
+    if (threadIdx.x != 0 || c->done) return;
+    const double normA = bits_double(scal[S_NORMA]);
+    const double normb = bits_double(scal[S_NORMB]);
+    const double rn = bits_double(scal[S_RN]);
+    const double xn = bits_double(scal[S_XN]);
+    const double den = normA * xn + normb;
+    const double eta = den > 0.0 ? rn / den : rn;
+    const int rises = (eta >= c->prev_eta) ? c->rises + 1 : 0;
+    c->rises = rises;
+    c->prev_eta = eta;
+    c->eta = eta;
+    c->rn = rn;
+    int st = -1;
+    if (c->err) st = 4;
+    else if (!(eta <= INFINITY) || eta == INFINITY) st = 3;
+    else if (eta <= tol) st = 0;
+    else if (c->iters >= max_iter) st = 1;
+    else if (rises >= 2) st = 2;
+    if (res) {
+        res->iters = c->iters;
+        res->status = st >= 0 ? st : 1;
+        res->eta = eta;
+    }
+    if (gres) {
+        gres->iters = c->iters;
+        gres->inner = c->inner;
+        gres->status = st >= 0 ? st : 1;
+        gres->reserved = 0;
+        gres->eta = eta;
+    }
+    if (st >= 0) {
+        c->status = st;
+        c->done = 1;
+        return;
+    }
+    c->iters += 1;     // the correction queued next is applied
+    c->k = 0;
+    c->gdone = 0;
+    scal[S_RN] = 0ull;
+    scal[S_XN] = 0ull;
 }
 
 // Value of v in lane l (l uniform), through v_readlane.
@@ -216,26 +352,33 @@ __device__ __forceinline__ double bcast_lane(double v, int l) {
 // the wave at the end.  The factor values of the next dependency are loaded
 // before waiting for it.  Diagonal block: one wave, lane l holding rows l and
 // l + 64, substitution in column order with the diagonal block in LDS.
+//
+// `epoch` numbers the launches of one solve (1, 2, ...): a block's flag is set
+// to the epoch of the launch that solved it, launch e takes its tickets from
+// ticket[e % 3] and clears ticket[(e + 1) % 3] for the launch after it (the
+// launch before it, which used that counter, has completed in stream order).
 template <typename T>
 __global__ void __launch_bounds__(512)
 trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32_t *ticket,
-            int32_t *err, int lower) {
+            int32_t epoch, int32_t *err, const IrCtrl *c, int inner, int lower) {
     extern __shared__ float Ld[];   // [TB][TB + 1] diagonal block
     __shared__ int s_blk;
     __shared__ int64_t s_known;
     __shared__ T rhs[TB];
     constexpr int LDD = TB + 1;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (blockIdx.x == 0 && t == 0) ticket[(epoch + 1) % 3] = 0u;
+    if (stopped(c, inner)) return;
     const int64_t nblk = ceil_div(n, TB);
-    if (t == 0) s_blk = (int)atomicAdd(ticket, 1u);
+    if (t == 0) s_blk = (int)atomicAdd(ticket + epoch % 3, 1u);
     __syncthreads();
     const int64_t blk = lower ? s_blk : nblk - 1 - s_blk;
     const int64_t r0 = blk * TB;
     const int rows = (int)((n - r0 < TB) ? n - r0 : TB);
     // diagonal block to LDS (independent of other blocks)
     for (int e = t; e < TB * TB; e += 512) {
-        const int i = e / TB, c = e % TB;
-        Ld[i * LDD + c] = (i < rows && c < rows) ? LU[(r0 + i) * ld + r0 + c] : 0.0f;
+        const int i = e / TB, cc = e % TB;
+        Ld[i * LDD + cc] = (i < rows && cc < rows) ? LU[(r0 + i) * ld + r0 + cc] : 0.0f;
     }
     const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
     // rows 16 wave .. 16 wave + 15 of this block row (clamped: rows past the
@@ -248,11 +391,11 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
     }
     auto col0 = [&](int64_t d) { return (lower ? d : nblk - 1 - d) * TB + 2 * lane; };
     float lc[16][2], ln[16][2];
-    auto load = [&](float (&dst)[16][2], int64_t c) {
+    auto load = [&](float (&dst)[16][2], int64_t col) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            dst[q][0] = (c < n) ? lrow[q][c] : 0.0f;
-            dst[q][1] = (c + 1 < n) ? lrow[q][c + 1] : 0.0f;
+            dst[q][0] = (col < n) ? lrow[q][col] : 0.0f;
+            dst[q][1] = (col + 1 < n) ? lrow[q][col + 1] : 0.0f;
         }
     };
     T acc[16];
@@ -269,7 +412,7 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
             // earlier blocks; polls are relaxed.
             if (t == 0) {
                 unsigned spins = 0;
-                while (__hip_atomic_load(flags + jb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                while (__hip_atomic_load(flags + jb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
                     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
                     if (++spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
                     __builtin_amdgcn_s_sleep(1);
@@ -277,7 +420,7 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
                 int64_t e = d + 1;
                 while (e < nb_dep &&
                        __hip_atomic_load(flags + (lower ? e : nblk - 1 - e), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) != 0)
+                                         __HIP_MEMORY_SCOPE_AGENT) == epoch)
                     ++e;
                 (void)__hip_atomic_load(flags + (lower ? e - 1 : nblk - e), __ATOMIC_ACQUIRE,
                                         __HIP_MEMORY_SCOPE_AGENT);
@@ -286,8 +429,8 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
             __syncthreads();
             known = s_known;
         }
-        const int64_t c = jb * TB + 2 * lane;
-        const T y0 = (c < n) ? y[c] : (T)0, y1 = (c + 1 < n) ? y[c + 1] : (T)0;
+        const int64_t col = jb * TB + 2 * lane;
+        const T y0 = (col < n) ? y[col] : (T)0, y1 = (col + 1 < n) ? y[col + 1] : (T)0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             acc[q] = fma((T)lc[q][0], y0, acc[q]);
@@ -332,11 +475,11 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
                 for (int k = 0; k < 8; ++k) { b0[k] = l0[cn + k]; b1[k] = l1[cn + k]; }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const int c = 8 * ch + k;
-                    const T yc = bcast_lane(c < 64 ? v0 : v1, c & 63);
+                    const int cc = 8 * ch + k;
+                    const T yc = bcast_lane(cc < 64 ? v0 : v1, cc & 63);
                     const T u0 = fma(-(T)a0[k], yc, v0), u1 = fma(-(T)a1[k], yc, v1);
-                    v0 = (lane > c) ? u0 : v0;
-                    v1 = (lane + 64 > c) ? u1 : v1;
+                    v0 = (lane > cc) ? u0 : v0;
+                    v1 = (lane + 64 > cc) ? u1 : v1;
                 }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) { a0[k] = b0[k]; a1[k] = b1[k]; }
@@ -358,12 +501,12 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
                 for (int k = 0; k < 8; ++k) { b0[k] = l0[cn + k]; b1[k] = l1[cn + k]; }
 #pragma unroll
                 for (int k = 7; k >= 0; --k) {
-                    const int c = 8 * ch + k;
-                    if (c < rows) {
-                        const T yc = bcast_lane(c < 64 ? v0 : v1, c & 63);
+                    const int cc = 8 * ch + k;
+                    if (cc < rows) {
+                        const T yc = bcast_lane(cc < 64 ? v0 : v1, cc & 63);
                         const T u0 = fma(-((T)a0[k] * rd0), yc, v0), u1 = fma(-((T)a1[k] * rd1), yc, v1);
-                        v0 = (lane < c) ? u0 : v0;
-                        v1 = (lane + 64 < c) ? u1 : v1;
+                        v0 = (lane < cc) ? u0 : v0;
+                        v1 = (lane + 64 < cc) ? u1 : v1;
                     }
                 }
 #pragma unroll
@@ -374,69 +517,189 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
         if (lane + 64 < rows) y[r0 + 64 + lane] = v1;
         __builtin_amdgcn_wave_barrier();
         // the release covers wave 0's stores of y
-        if (t == 0) __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == 0) __hip_atomic_store(flags + blk, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 
 // ---------------------------------------------------------------------------
-// GMRES-IR pieces (all FP64 vectors).
+// GMRES pieces (all FP64 vectors).
 // ---------------------------------------------------------------------------
-// y = A x, A promoted exactly, one workgroup per row, fixed-order reduction.
+// z[i] = (P A v)[i] = sum_j A[perm[i], j] v[j] with v = w * rinv, the next
+// basis vector, which workgroup i also stores: V_k[i] = w[i] * rinv (the
+// product the dot product uses, so the stored vector is the one multiplied).
 __global__ void __launch_bounds__(256)
-matvec_kernel(const float *A, int64_t lda, int64_t n, const double *x, double *y, int vec) {
+matvec_perm_kernel(const float *A, int64_t lda, int64_t n, const int32_t *perm, const double *w,
+                   double *Vk, double *z, int vec, const IrCtrl *c) {
     __shared__ double red[4];
-    const int64_t row = blockIdx.x;
-    const float *a = A + row * lda;
-    double s = 0.0;
-    if (vec) {
-        for (int64_t j = 4 * threadIdx.x; j + 3 < n; j += 1024) {
-            const float4 v = *reinterpret_cast<const float4 *>(a + j);
-            s = fma((double)v.x, x[j], s);
-            s = fma((double)v.y, x[j + 1], s);
-            s = fma((double)v.z, x[j + 2], s);
-            s = fma((double)v.w, x[j + 3], s);
-        }
-        for (int64_t j = (n & ~int64_t(3)) + threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
-    } else {
-        for (int64_t j = threadIdx.x; j < n; j += 256) s = fma((double)a[j], x[j], s);
+    if (stopped(c, 1)) return;
+    const int64_t i = blockIdx.x;
+    const double rinv = c->rinv;
+    const double s = row_dot(A + (int64_t)perm[i] * lda, n, w, rinv, vec, red);
+    if (threadIdx.x == 0) {
+        z[i] = s;
+        Vk[i] = w[i] * rinv;
     }
-    s = block_sum_256(s, red);
-    if (threadIdx.x == 0) y[row] = s;
 }
 
+// h[j] = <V_j, z>, j < gridDim.x: one workgroup per j, fixed-order tree.
 __global__ void __launch_bounds__(256)
-gather_f64(const double *v, const int32_t *perm, double *out, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        out[i] = v[perm[i]];
-}
-
-// h[j] = <w, V_j>, j < k: one workgroup per j, fixed-order tree (deterministic).
-__global__ void __launch_bounds__(256)
-dots_kernel(const double *V, int64_t ldv, const double *w, int64_t n, double *h) {
+dots_kernel(const double *V, int64_t ldv, const double *z, int64_t n, double *h, const IrCtrl *c) {
     __shared__ double red[4];
+    if (stopped(c, 1)) return;
     const double *v = V + (int64_t)blockIdx.x * ldv;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], w[i], s);
+    for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], z[i], s);
     s = block_sum_256(s, red);
     if (threadIdx.x == 0) h[blockIdx.x] = s;
 }
 
-// w -= sum_{j<k} h_j V_j   (init = 0)   or   x += sum_{j<k} h_j V_j   (sign = +1)
+// out[i] = z[i] + sign * sum_{j < cnt} h[j] V_j[i] over CROWS = 64 rows per
+// workgroup: lane = row, wave q sums j = q, q + 4, ... in increasing j, the
+// four wave sums are added in a fixed order (deterministic).  cnt < 0 takes
+// the count from the control block (the basis size of the finished cycle);
+// part != NULL also stores the workgroup's sum of out^2.  inner selects the
+// gate (a Gram-Schmidt pass of a GMRES step, or the update of x).
 __global__ void __launch_bounds__(256)
-combine_kernel(const double *V, int64_t ldv, const double *h, int k, double *w, int64_t n,
-               double sign) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        double acc = w[i];
-        for (int j = 0; j < k; ++j) acc = fma(sign * h[j], V[(int64_t)j * ldv + i], acc);
-        w[i] = acc;
+combine_kernel(const double *V, int64_t ldv, const double *h, int cnt, const double *z, double *out,
+               int64_t n, double sign, double *part, const IrCtrl *c, int inner) {
+    __shared__ double red[4][CROWS];
+    if (stopped(c, inner)) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * CROWS + lane;
+    const int k = cnt >= 0 ? cnt : c->k;
+    double s = 0.0;
+    if (i < n) {
+        int j = wave;
+        for (; j + 12 < k; j += 16) {
+            const double v0 = V[(int64_t)j * ldv + i], v1 = V[(int64_t)(j + 4) * ldv + i];
+            const double v2 = V[(int64_t)(j + 8) * ldv + i], v3 = V[(int64_t)(j + 12) * ldv + i];
+            s = fma(h[j], v0, s);
+            s = fma(h[j + 4], v1, s);
+            s = fma(h[j + 8], v2, s);
+            s = fma(h[j + 12], v3, s);
+        }
+        for (; j < k; j += 4) s = fma(h[j], V[(int64_t)j * ldv + i], s);
+    }
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0) {
+        double o = 0.0;
+        if (i < n) {
+            const double tot = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+            o = fma(sign, tot, z[i]);
+            out[i] = o;
+        }
+        if (part) {
+            double q = o * o;
+            for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+            if (lane == 0) part[blockIdx.x] = q;
+        }
     }
 }
 
+// part[blockIdx] = sum of v[i]^2 over the workgroup's CROWS rows.
+__global__ void __launch_bounds__(64)
+nrm_part_kernel(const double *v, int64_t n, double *part, const IrCtrl *c) {
+    if (stopped(c, 0)) return;
+    const int64_t i = (int64_t)blockIdx.x * CROWS + threadIdx.x;
+    double q = (i < n) ? v[i] * v[i] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+    if (threadIdx.x == 0) part[blockIdx.x] = q;
+}
+
+// Sum of the partials in a fixed order (one wave; every lane gets it).
+__device__ __forceinline__ double sum_parts(const double *part, int64_t np) {
+    double s = 0.0;
+    for (int64_t p = threadIdx.x; p < np; p += 64) s += part[p];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
+// Start of a GMRES cycle on w = M^-1 r: beta = |w|_2, g = beta e_1.
+__global__ void __launch_bounds__(64)
+gmres_begin_kernel(IrCtrl *c, const double *part, int64_t np, double *g) {
+    if (stopped(c, 0)) return;
+    const double beta = sqrt(sum_parts(part, np));
+    if (threadIdx.x == 0) {
+        c->beta = beta;
+        c->k = 0;
+        c->gdone = (beta > 0.0 && beta < INFINITY) ? 0 : 1;
+        c->rinv = 1.0 / beta;
+        g[0] = beta;
+    }
+}
+
+// Step k of the cycle after Gram-Schmidt: column k of the Hessenberg matrix
+// is h_j = hA_j + hB_j (j <= k), h_{k+1} = |w|_2; the k earlier rotations are
+// applied to it in order, a new rotation zeroes h_{k+1}, and the rotated
+// column is stored as column k of R (column-major, leading dimension m).
+// One wave: the rotations form a chain, walked 64 at a time with the
+// rotation and column values of a chunk loaded in parallel, one per lane,
+// and broadcast with v_readlane.  The cycle ends when |g_{k+1}| <= inner_tol
+// * beta, when the new vector is zero or when the basis is full.
+__global__ void __launch_bounds__(64)
+givens_kernel(IrCtrl *c, const double *hA, const double *hB, const double *part, int64_t np, double *R,
+              int m, double *cs, double *sn, double *g, double inner_tol) {
+    if (stopped(c, 1)) return;
+    const int lane = threadIdx.x;
+    const int k = c->k;
+    const double hn = sqrt(sum_parts(part, np));
+    double *col = R + (int64_t)k * m;
+    // carry: the column entry j after rotations 0 .. j-1
+    double carry = hA[0] + hB[0];
+    for (int j0 = 0; j0 < k; j0 += 64) {
+        const int j = j0 + lane;
+        const double cj = (j < k) ? cs[j] : 1.0, sj = (j < k) ? sn[j] : 0.0;
+        const double hnext = (j < k) ? hA[j + 1] + hB[j + 1] : 0.0;
+        double outv = 0.0;
+        const int cnt = (k - j0 < 64) ? k - j0 : 64;
+        for (int l = 0; l < cnt; ++l) {
+            const double cl = bcast_lane(cj, l), sl = bcast_lane(sj, l), hl = bcast_lane(hnext, l);
+            const double top = cl * carry + sl * hl;
+            carry = -sl * carry + cl * hl;
+            outv = (lane == l) ? top : outv;
+        }
+        if (j < k) col[j] = outv;
+    }
+    if (lane == 0) {
+        const double a = carry, b2 = hn;
+        const double rho = hypot(a, b2);
+        const double ck = rho > 0.0 ? a / rho : 1.0, sk = rho > 0.0 ? b2 / rho : 0.0;
+        cs[k] = ck;
+        sn[k] = sk;
+        col[k] = rho;
+        const double gk = g[k];
+        g[k + 1] = -sk * gk;
+        g[k] = ck * gk;
+        const int kk = k + 1;
+        c->k = kk;
+        c->inner += 1;
+        c->rinv = 1.0 / hn;
+        const bool conv = fabs(g[kk]) <= inner_tol * c->beta || hn == 0.0;
+        c->gdone = (conv || kk >= m) ? 1 : 0;
+    }
+}
+
+// y = R^-1 g for the k x k upper triangle of the finished cycle, column by
+// column from the last (g is overwritten).
 __global__ void __launch_bounds__(256)
-scale_f64(const double *w, double div, double *v, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        v[i] = w[i] / div;
+backsolve_kernel(const IrCtrl *c, const double *R, int m, double *g, double *y) {
+    __shared__ double s_y;
+    if (stopped(c, 0)) return;
+    const int k = c->k;
+    for (int j = k - 1; j >= 0; --j) {
+        if (threadIdx.x == 0) {
+            const double v = g[j] / R[(int64_t)j * m + j];
+            y[j] = v;
+            s_y = v;
+        }
+        __syncthreads();
+        const double yj = s_y;
+        const double *colj = R + (int64_t)j * m;
+        for (int i = threadIdx.x; i < j; i += 256) g[i] = fma(-colj[i], yj, g[i]);
+        __syncthreads();
+    }
 }
 
 static unsigned grid_for(int64_t n) {
@@ -446,65 +709,80 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
-// In-place solve of (LU) y = y: T = float on the workspace vector (LU-IR),
-// T = double for the GMRES preconditioner.
-template <typename T>
-static int lu_solve_vec(int64_t n, const float *LU, int64_t ldlu, T *y, const IrWs &w,
-                        hipStream_t s) {
-    const int64_t nb = ceil_div(n, TB);
-    static bool attr = false;
-    if (!attr) {
-        BFX_HIP(hipFuncSetAttribute((const void *)trsv_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)TRSV_LDS));
-        attr = true;
-    }
-    for (int lower = 1; lower >= 0; --lower) {
-        hipLaunchKernelGGL(zero_i32, dim3(grid_for(nb)), dim3(256), 0, s, w.flags, nb);
-        hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.ticket, 4);
-        hipLaunchKernelGGL(trsv_kernel<T>, dim3((unsigned)nb), dim3(512), TRSV_LDS, s, LU, ldlu, n, y,
-                           w.flags, w.ticket, w.err, lower);
-        BFX_LAUNCH_CHECK("trsv_kernel");
-    }
-    return BFX_OK;
-}
+// One solve's launches: the trsv epoch counter and the shared arguments.
+struct Solver {
+    int64_t n;
+    const float *LU;
+    int64_t ldlu;
+    IrWs w;
+    hipStream_t s;
+    int32_t epoch = 0;
 
-static int lu_solve_ws(int64_t n, const float *LU, int64_t ldlu, const IrWs &w, hipStream_t s) {
-    return lu_solve_vec<float>(n, LU, ldlu, w.w, w, s);
-}
-
-static int compose_perm(int64_t n, const int32_t *ipiv, const IrWs &w, hipStream_t s) {
-    const size_t lds = sizeof(int32_t) * (size_t)n;
-    const int use_lds = lds <= 160 * 1024 - 1024;
-    if (use_lds) {
-        static size_t attr = 0;
-        if (attr < lds) {
-            BFX_HIP(hipFuncSetAttribute((const void *)perm_kernel,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            attr = lds;
+    template <typename T>
+    int trsv_pair(T *y, const IrCtrl *c, int inner) {
+        static bool attr = false;
+        if (!attr) {
+            BFX_HIP(hipFuncSetAttribute((const void *)trsv_kernel<T>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)TRSV_LDS));
+            attr = true;
         }
+        const int64_t nb = ceil_div(n, TB);
+        for (int lower = 1; lower >= 0; --lower) {
+            ++epoch;
+            hipLaunchKernelGGL(trsv_kernel<T>, dim3((unsigned)nb), dim3(512), TRSV_LDS, s, LU, ldlu, n, y,
+                               w.flags, w.ticket, epoch, &w.ctrl->err, c, inner, lower);
+            BFX_LAUNCH_CHECK("trsv_kernel");
+        }
+        return BFX_OK;
     }
-    hipLaunchKernelGGL(perm_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), use_lds ? lds : 0, s, ipiv, n,
-                       w.perm, use_lds);
-    BFX_LAUNCH_CHECK("perm_kernel");
-    return BFX_OK;
-}
 
-static int check_err(const IrWs &w, hipStream_t s) {
-    int32_t e = 0;
-    BFX_HIP(hipMemcpyAsync(&e, w.err, sizeof e, hipMemcpyDeviceToHost, s));
-    BFX_HIP(hipStreamSynchronize(s));
-    if (e) {
-        set_error("triangular solve: a bounded wait on a block flag expired");
-        return BFX_E_INTERNAL;
+    int compose_perm(const int32_t *ipiv) {
+        const size_t lds = sizeof(int32_t) * (size_t)n;
+        const int use_lds = lds <= 160 * 1024 - 1024;
+        if (use_lds) {
+            static size_t attr = 0;
+            if (attr < lds) {
+                BFX_HIP(hipFuncSetAttribute((const void *)perm_kernel,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                attr = lds;
+            }
+        }
+        hipLaunchKernelGGL(perm_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), use_lds ? lds : 0, s, ipiv,
+                           n, w.perm, use_lds);
+        BFX_LAUNCH_CHECK("perm_kernel");
+        return BFX_OK;
     }
-    return BFX_OK;
-}
 
-static double bits_to_double(unsigned long long u) {
-    double d;
-    memcpy(&d, &u, sizeof d);
-    return d;
-}
+    // Clear the state, norms of A and b, the permutation and
+    // x0 = (double) LUsolve32((float) b).
+    int begin(const float *A, int64_t lda, const int32_t *ipiv, const double *b, double *x) {
+        const unsigned g = grid_for(n);
+        hipLaunchKernelGGL(ir_begin_kernel, dim3(1), dim3(256), 0, s, w.ctrl, w.scal, w.ticket, w.flags,
+                           ceil_div(n, TB));
+        hipLaunchKernelGGL(mat_norm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.scal);
+        hipLaunchKernelGGL(vec_absmax_kernel, dim3(g), dim3(256), 0, s, b, n, w.scal + S_NORMB,
+                           (const IrCtrl *)nullptr);
+        int rc = compose_perm(ipiv);
+        if (rc) return rc;
+        hipLaunchKernelGGL(gather_f64_to_f32, dim3(g), dim3(256), 0, s, b, w.perm, w.ctrl, 0, w.w, n);
+        rc = trsv_pair<float>(w.w, w.ctrl, 0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(update_x, dim3(g), dim3(256), 0, s, x, w.w, w.ctrl, 1, n);
+        BFX_LAUNCH_CHECK("refinement start");
+        return BFX_OK;
+    }
+
+    // r = b - A x, |x|_inf and the convergence test.
+    int check(const float *A, int64_t lda, int vec, const double *b, const double *x, bfx_ir_result *res,
+              bfx_gmres_result *gres, double tol, int max_iter) {
+        hipLaunchKernelGGL(residual_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, b, x, w.r, w.scal, vec,
+                           w.ctrl);
+        hipLaunchKernelGGL(vec_absmax_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, w.scal + S_XN, w.ctrl);
+        hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(64), 0, s, w.ctrl, w.scal, res, gres, tol, max_iter);
+        BFX_LAUNCH_CHECK("refinement check");
+        return BFX_OK;
+    }
+};
 
 }  // namespace bfx
 
@@ -522,17 +800,26 @@ extern "C" int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu, const 
     if (!ws || ws_bytes < bfx_ir_ws_size(n)) return -7;
     if (n == 0) return BFX_OK;
     hipStream_t s = (hipStream_t)stream;
-    bfx::IrWs w;
-    bfx::ir_ws_layout(&w, ws, n);
-    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, w.err, 4);
-    int rc = bfx::compose_perm(n, ipiv, w, s);
+    bfx::Solver sv{n, LU, ldlu, {}, s};
+    bfx::ir_ws_layout(&sv.w, ws, n);
+    hipLaunchKernelGGL(bfx::ir_begin_kernel, dim3(1), dim3(256), 0, s, sv.w.ctrl, sv.w.scal, sv.w.ticket,
+                       sv.w.flags, bfx::ceil_div(n, bfx::TB));
+    int rc = sv.compose_perm(ipiv);
     if (rc) return rc;
-    hipLaunchKernelGGL(bfx::gather_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, rhs, w.perm, w.w, n);
-    rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
+    hipLaunchKernelGGL(bfx::gather_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, rhs, sv.w.perm, sv.w.w, n);
+    rc = sv.trsv_pair<float>(sv.w.w, sv.w.ctrl, 0);
     if (rc) return rc;
-    hipLaunchKernelGGL(bfx::copy_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, w.w, rhs, n);
+    hipLaunchKernelGGL(bfx::copy_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, sv.w.w, rhs, n);
     BFX_LAUNCH_CHECK("copy_f32");
-    return bfx::check_err(w, s);
+    // The only synchronisation of this utility: report an expired bounded wait.
+    int32_t e = 0;
+    BFX_HIP(hipMemcpyAsync(&e, &sv.w.ctrl->err, sizeof e, hipMemcpyDeviceToHost, s));
+    BFX_HIP(hipStreamSynchronize(s));
+    if (e) {
+        bfx::set_error("triangular solve: a bounded wait on a block flag expired");
+        return BFX_E_INTERNAL;
+    }
+    return BFX_OK;
 }
 
 extern "C" int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float *LU,
@@ -552,94 +839,80 @@ extern "C" int bfx_ir_solve(int64_t n, const float *A, int64_t lda, const float 
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -9;
     if (!res) return -10;
     if (!ws || ws_bytes < bfx_ir_ws_size(n)) return -12;
-    res->iters = 0;
-    res->status = 0;
-    res->eta = 0.0;
-    if (n == 0) return BFX_OK;
     hipStream_t s = (hipStream_t)stream;
-    bfx::IrWs w;
-    bfx::ir_ws_layout(&w, ws, n);
-    const unsigned g = bfx::grid_for(n);
-    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, w.err, 4);
-    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.scal, 2 * bfx::S_NSCAL);
-    hipLaunchKernelGGL(bfx::mat_norm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.scal);
-    hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(g), dim3(256), 0, s, b, n, w.scal + bfx::S_NORMB);
-    int rc = bfx::compose_perm(n, ipiv, w, s);
-    if (rc) return rc;
-    // x0 = LUsolve32(b)
-    hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(g), dim3(256), 0, s, b, w.perm, 1.0, w.w, n);
-    rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(bfx::update_x, dim3(g), dim3(256), 0, s, x, w.w, 0.0, 1, n);
-    BFX_LAUNCH_CHECK("ir init");
-
-    const int vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
-    unsigned long long h[bfx::S_NSCAL];
-    double prev_eta = INFINITY, eta = 0.0;
-    int it = 0, rises = 0, status = 1;
-    for (;;) {
-        hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)(w.scal + bfx::S_RN), 4);
-        hipLaunchKernelGGL(bfx::residual_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, b, x,
-                           w.r, w.scal, vec);
-        hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(g), dim3(256), 0, s, x, n, w.scal + bfx::S_XN);
-        BFX_LAUNCH_CHECK("residual");
-        BFX_HIP(hipMemcpyAsync(h, w.scal, sizeof h, hipMemcpyDeviceToHost, s));
-        BFX_HIP(hipStreamSynchronize(s));
-        const double normA = bfx::bits_to_double(h[bfx::S_NORMA]);
-        const double normb = bfx::bits_to_double(h[bfx::S_NORMB]);
-        const double rn = bfx::bits_to_double(h[bfx::S_RN]);
-        const double xn = bfx::bits_to_double(h[bfx::S_XN]);
-        const double den = normA * xn + normb;
-        eta = den > 0.0 ? rn / den : rn;
-        rises = (eta >= prev_eta) ? rises + 1 : 0;
-        prev_eta = eta;
-        if (!std::isfinite(eta)) { status = 3; break; }
-        if (eta <= o.tol) { status = 0; break; }
-        if (it >= o.max_iter) { status = 1; break; }
-        if (rises >= 2) { status = 2; break; }
-        hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(g), dim3(256), 0, s, w.r, w.perm, rn,
-                           w.w, n);
-        rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
-        if (rc) return rc;
-        hipLaunchKernelGGL(bfx::update_x, dim3(g), dim3(256), 0, s, x, w.w, rn, 0, n);
-        BFX_LAUNCH_CHECK("ir update");
-        ++it;
+    if (n == 0) {
+        const bfx_ir_result z = {0, 0, 0.0};
+        BFX_HIP(hipMemcpyAsync(res, &z, sizeof z, hipMemcpyHostToDevice, s));
+        return BFX_OK;
     }
-    res->iters = it;
-    res->status = status;
-    res->eta = eta;
-    return bfx::check_err(w, s);
+    bfx::Solver sv{n, LU, ldlu, {}, s};
+    bfx::ir_ws_layout(&sv.w, ws, n);
+    const bfx::IrWs &w = sv.w;
+    const unsigned g = bfx::grid_for(n);
+    const int vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+    int rc = sv.begin(A, lda, ipiv, b, x);
+    if (rc) return rc;
+    for (int it = 0;; ++it) {
+        rc = sv.check(A, lda, vec, b, x, res, nullptr, o.tol, o.max_iter);
+        if (rc) return rc;
+        if (it >= o.max_iter) break;
+        // d = |r|_inf LUsolve32(r / |r|_inf), x += d
+        hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(g), dim3(256), 0, s, w.r, w.perm, w.ctrl, 1, w.w, n);
+        rc = sv.trsv_pair<float>(w.w, w.ctrl, 0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(bfx::update_x, dim3(g), dim3(256), 0, s, x, w.w, w.ctrl, 0, n);
+        BFX_LAUNCH_CHECK("ir update");
+    }
+    return BFX_OK;
 }
 
 // ---------------------------------------------------------------------------
 // GMRES-IR (Sec. III, Sec. IV-B): refinement whose correction equation is
 // solved by GMRES on M^{-1} A d = M^{-1} r with M the low-precision LU,
 // FP64 throughout GMRES; the preconditioner applies the FP32 factors in FP64.
-// The host keeps only the O(restart) Hessenberg least-squares state (Givens
-// rotations); vectors and every O(n) / O(n^2) step stay on the device.
 // ---------------------------------------------------------------------------
 namespace bfx {
 namespace {
 struct GmresWs {
     IrWs ir;
-    double *V;    // (m+1) x n
+    double *V;    // (m+1) x n basis
     double *z;    // n
-    double *h;    // 2*(m+1) + 8 scalars: hA, hB, |w|^2
+    double *wv;   // n: the vector the next basis vector is made from
+    double *hA, *hB;   // m+1 each: the two Gram-Schmidt passes
+    double *R;    // m x m, column-major: rotated Hessenberg columns
+    double *cs, *sn;   // m each
+    double *g;    // m+1
     double *y;    // m
 };
 size_t gmres_ws_layout(GmresWs *g, void *base, int64_t n, int m) {
     size_t off = ir_ws_layout(g ? &g->ir : nullptr, base, n);
-    off = (off + 255) & ~size_t(255);
     const int64_t nn = n > 0 ? n : 1;
-    const size_t o_V = off; off += ((sizeof(double) * nn * (m + 1)) + 255) & ~size_t(255);
-    const size_t o_z = off; off += ((sizeof(double) * nn) + 255) & ~size_t(255);
-    const size_t o_h = off; off += ((sizeof(double) * (2 * (m + 1) + 8)) + 255) & ~size_t(255);
-    const size_t o_y = off; off += ((sizeof(double) * (m + 1)) + 255) & ~size_t(255);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_V = take(sizeof(double) * nn * (size_t)(m + 1));
+    const size_t o_z = take(sizeof(double) * nn);
+    const size_t o_w = take(sizeof(double) * nn);
+    const size_t o_hA = take(sizeof(double) * (m + 1));
+    const size_t o_hB = take(sizeof(double) * (m + 1));
+    const size_t o_R = take(sizeof(double) * (size_t)m * (size_t)m);
+    const size_t o_cs = take(sizeof(double) * m);
+    const size_t o_sn = take(sizeof(double) * m);
+    const size_t o_g = take(sizeof(double) * (m + 1));
+    const size_t o_y = take(sizeof(double) * m);
     if (g && base) {
         char *b = (char *)base;
         g->V = (double *)(b + o_V);
         g->z = (double *)(b + o_z);
-        g->h = (double *)(b + o_h);
+        g->wv = (double *)(b + o_w);
+        g->hA = (double *)(b + o_hA);
+        g->hB = (double *)(b + o_hB);
+        g->R = (double *)(b + o_R);
+        g->cs = (double *)(b + o_cs);
+        g->sn = (double *)(b + o_sn);
+        g->g = (double *)(b + o_g);
         g->y = (double *)(b + o_y);
     }
     return off;
@@ -656,7 +929,7 @@ extern "C" int bfx_gmres_ir_solve(int64_t n, const float *A, int64_t lda, const 
                                   int64_t ldlu, const int32_t *ipiv, const double *b, double *x,
                                   const bfx_gmres_opts *opts, bfx_gmres_result *res, void *ws,
                                   size_t ws_bytes, void *stream) {
-    bfx_gmres_opts o = {1e-14, 30, 50, 1e-8};
+    bfx_gmres_opts o = {1e-14, 10, 50, 1e-8};
     if (opts) o = *opts;
     if (n < 0) return -1;
     if (n > 0 && !A) return -2;
@@ -670,131 +943,56 @@ extern "C" int bfx_gmres_ir_solve(int64_t n, const float *A, int64_t lda, const 
     if (!res) return -10;
     const int m = o.restart;
     if (!ws || ws_bytes < bfx_gmres_ir_ws_size(n, m)) return -12;
-    res->iters = 0;
-    res->inner = 0;
-    res->status = 0;
-    res->eta = 0.0;
-    if (n == 0) return BFX_OK;
     hipStream_t s = (hipStream_t)stream;
-    bfx::GmresWs g;
-    bfx::gmres_ws_layout(&g, ws, n, m);
-    const bfx::IrWs &w = g.ir;
-    const unsigned gr = bfx::grid_for(n);
-    const int vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
-    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, w.err, 4);
-    hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)w.scal, 2 * bfx::S_NSCAL);
-    hipLaunchKernelGGL(bfx::mat_norm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.scal);
-    hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(gr), dim3(256), 0, s, b, n, w.scal + bfx::S_NORMB);
-    int rc = bfx::compose_perm(n, ipiv, w, s);
-    if (rc) return rc;
-    // x0 = LUsolve32(b)
-    hipLaunchKernelGGL(bfx::gather_f64_to_f32, dim3(gr), dim3(256), 0, s, b, w.perm, 1.0, w.w, n);
-    rc = bfx::lu_solve_ws(n, LU, ldlu, w, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(bfx::update_x, dim3(gr), dim3(256), 0, s, x, w.w, 0.0, 1, n);
-    BFX_LAUNCH_CHECK("gmres init");
-
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
-    std::vector<double> hh(2 * (m + 1) + 8);
-    unsigned long long hs[bfx::S_NSCAL];
-    double prev_eta = INFINITY, eta = 0.0;
-    int it = 0, rises = 0, status = 1, inner_total = 0;
-    auto precond = [&](double *v) -> int {   // v = M^{-1} v, via gather into z
-        hipLaunchKernelGGL(bfx::gather_f64, dim3(gr), dim3(256), 0, s, v, w.perm, g.z, n);
-        int r2 = bfx::lu_solve_vec<double>(n, LU, ldlu, g.z, w, s);
-        if (r2) return r2;
-        hipLaunchKernelGGL(bfx::scale_f64, dim3(gr), dim3(256), 0, s, g.z, 1.0, v, n);
-        BFX_LAUNCH_CHECK("gmres precond");
+    if (n == 0) {
+        const bfx_gmres_result z = {0, 0, 0, 0, 0.0};
+        BFX_HIP(hipMemcpyAsync(res, &z, sizeof z, hipMemcpyHostToDevice, s));
         return BFX_OK;
-    };
-    for (;;) {
-        hipLaunchKernelGGL(bfx::zero_i32, dim3(1), dim3(256), 0, s, (int32_t *)(w.scal + bfx::S_RN), 4);
-        hipLaunchKernelGGL(bfx::residual_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, b, x,
-                           w.r, w.scal, vec);
-        hipLaunchKernelGGL(bfx::vec_absmax_kernel, dim3(gr), dim3(256), 0, s, x, n, w.scal + bfx::S_XN);
-        BFX_LAUNCH_CHECK("gmres residual");
-        BFX_HIP(hipMemcpyAsync(hs, w.scal, sizeof hs, hipMemcpyDeviceToHost, s));
-        BFX_HIP(hipStreamSynchronize(s));
-        const double normA = bfx::bits_to_double(hs[bfx::S_NORMA]);
-        const double normb = bfx::bits_to_double(hs[bfx::S_NORMB]);
-        const double rn = bfx::bits_to_double(hs[bfx::S_RN]);
-        const double xn = bfx::bits_to_double(hs[bfx::S_XN]);
-        const double den = normA * xn + normb;
-        eta = den > 0.0 ? rn / den : rn;
-        rises = (eta >= prev_eta) ? rises + 1 : 0;
-        prev_eta = eta;
-        if (!std::isfinite(eta)) { status = 3; break; }
-        if (eta <= o.tol) { status = 0; break; }
-        if (it >= o.max_iter) { status = 1; break; }
-        if (rises >= 2) { status = 2; break; }
-        // GMRES on M^{-1} A d = M^{-1} r, d0 = 0; V_0 = M^{-1} r / beta
-        rc = precond(w.r);
-        if (rc) return rc;
-        hipLaunchKernelGGL(bfx::dots_kernel, dim3(1), dim3(256), 0, s, w.r, n, w.r, n, g.h);
-        BFX_HIP(hipMemcpyAsync(hh.data(), g.h, sizeof(double), hipMemcpyDeviceToHost, s));
-        BFX_HIP(hipStreamSynchronize(s));
-        const double beta = std::sqrt(hh[0]);
-        int k = 0;
-        if (beta > 0.0) {
-            hipLaunchKernelGGL(bfx::scale_f64, dim3(gr), dim3(256), 0, s, w.r, beta, g.V, n);
-            std::fill(gv.begin(), gv.end(), 0.0);
-            gv[0] = beta;
-            for (k = 0; k < m; ++k) {
-                double *vk = g.V + (int64_t)k * n;
-                double *wv = w.r;   // the residual is recomputed next step: reuse as w
-                hipLaunchKernelGGL(bfx::matvec_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n,
-                                   vk, wv, vec);
-                rc = precond(wv);
-                if (rc) return rc;
-                double *hA = g.h, *hB = g.h + (m + 1), *nw = g.h + 2 * (m + 1);
-                hipLaunchKernelGGL(bfx::dots_kernel, dim3(k + 1), dim3(256), 0, s, g.V, n, wv, n, hA);
-                hipLaunchKernelGGL(bfx::combine_kernel, dim3(gr), dim3(256), 0, s, g.V, n, hA, k + 1,
-                                   wv, n, -1.0);
-                hipLaunchKernelGGL(bfx::dots_kernel, dim3(k + 1), dim3(256), 0, s, g.V, n, wv, n, hB);
-                hipLaunchKernelGGL(bfx::combine_kernel, dim3(gr), dim3(256), 0, s, g.V, n, hB, k + 1,
-                                   wv, n, -1.0);
-                hipLaunchKernelGGL(bfx::dots_kernel, dim3(1), dim3(256), 0, s, wv, n, wv, n, nw);
-                BFX_LAUNCH_CHECK("gmres arnoldi");
-                BFX_HIP(hipMemcpyAsync(hh.data(), g.h, sizeof(double) * (2 * (m + 1) + 1),
-                                       hipMemcpyDeviceToHost, s));
-                BFX_HIP(hipStreamSynchronize(s));
-                const double hn = std::sqrt(hh[2 * (m + 1)]);
-                for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = hh[j] + hh[(m + 1) + j];
-                H[(size_t)(k + 1) * m + k] = hn;
-                for (int j = 0; j < k; ++j) {
-                    const double a = H[(size_t)j * m + k], c2 = H[(size_t)(j + 1) * m + k];
-                    H[(size_t)j * m + k] = cs[j] * a + sn[j] * c2;
-                    H[(size_t)(j + 1) * m + k] = -sn[j] * a + cs[j] * c2;
-                }
-                const double a = H[(size_t)k * m + k], c2 = H[(size_t)(k + 1) * m + k];
-                const double rho = std::hypot(a, c2);
-                cs[k] = rho > 0.0 ? a / rho : 1.0;
-                sn[k] = rho > 0.0 ? c2 / rho : 0.0;
-                H[(size_t)k * m + k] = rho;
-                H[(size_t)(k + 1) * m + k] = 0.0;
-                gv[k + 1] = -sn[k] * gv[k];
-                gv[k] = cs[k] * gv[k];
-                ++inner_total;
-                if (hn > 0.0)
-                    hipLaunchKernelGGL(bfx::scale_f64, dim3(gr), dim3(256), 0, s, wv, hn,
-                                       g.V + (int64_t)(k + 1) * n, n);
-                if (std::fabs(gv[k + 1]) <= o.inner_tol * beta || hn == 0.0) { ++k; break; }
-            }
-            for (int j = k - 1; j >= 0; --j) {
-                double acc = gv[j];
-                for (int q = j + 1; q < k; ++q) acc -= H[(size_t)j * m + q] * yv[q];
-                yv[j] = acc / H[(size_t)j * m + j];
-            }
-            BFX_HIP(hipMemcpyAsync(g.y, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(bfx::combine_kernel, dim3(gr), dim3(256), 0, s, g.V, n, g.y, k, x, n, 1.0);
-            BFX_LAUNCH_CHECK("gmres update");
-            BFX_HIP(hipStreamSynchronize(s));
-        }
-        ++it;
     }
-    res->iters = it;
-    res->inner = inner_total;
-    res->status = status;
-    res->eta = eta;
-    return bfx::check_err(w, s);
+    bfx::GmresWs gw;
+    bfx::gmres_ws_layout(&gw, ws, n, m);
+    bfx::Solver sv{n, LU, ldlu, gw.ir, s};
+    const bfx::IrWs &w = sv.w;
+    bfx::IrCtrl *c = w.ctrl;
+    const unsigned gr = bfx::grid_for(n);
+    const unsigned gc = (unsigned)bfx::ceil_div(n, bfx::CROWS);
+    const int vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+    int rc = sv.begin(A, lda, ipiv, b, x);
+    if (rc) return rc;
+    for (int it = 0;; ++it) {
+        rc = sv.check(A, lda, vec, b, x, nullptr, res, o.tol, o.max_iter);
+        if (rc) return rc;
+        if (it >= o.max_iter) break;
+        // wv = M^-1 r = U^-1 L^-1 P r, beta = |wv|_2
+        hipLaunchKernelGGL(bfx::gather_f64, dim3(gr), dim3(256), 0, s, w.r, w.perm, gw.wv, n, c);
+        rc = sv.trsv_pair<double>(gw.wv, c, 0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(bfx::nrm_part_kernel, dim3(gc), dim3(64), 0, s, gw.wv, n, w.part, c);
+        hipLaunchKernelGGL(bfx::gmres_begin_kernel, dim3(1), dim3(64), 0, s, c, w.part, (int64_t)gc, gw.g);
+        BFX_LAUNCH_CHECK("gmres begin");
+        for (int k = 0; k < m; ++k) {
+            double *Vk = gw.V + (int64_t)k * n;
+            // z = M^-1 A v_k with v_k = wv / |wv|_2 stored as V_k
+            hipLaunchKernelGGL(bfx::matvec_perm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.perm,
+                               gw.wv, Vk, gw.z, vec, c);
+            rc = sv.trsv_pair<double>(gw.z, c, 1);
+            if (rc) return rc;
+            // classical Gram-Schmidt, twice; the second pass writes wv and |wv|^2
+            hipLaunchKernelGGL(bfx::dots_kernel, dim3(k + 1), dim3(256), 0, s, gw.V, n, gw.z, n, gw.hA, c);
+            hipLaunchKernelGGL(bfx::combine_kernel, dim3(gc), dim3(256), 0, s, gw.V, n, gw.hA, k + 1, gw.z, gw.z,
+                               n, -1.0, (double *)nullptr, c, 1);
+            hipLaunchKernelGGL(bfx::dots_kernel, dim3(k + 1), dim3(256), 0, s, gw.V, n, gw.z, n, gw.hB, c);
+            hipLaunchKernelGGL(bfx::combine_kernel, dim3(gc), dim3(256), 0, s, gw.V, n, gw.hB, k + 1, gw.z, gw.wv,
+                               n, -1.0, w.part, c, 1);
+            hipLaunchKernelGGL(bfx::givens_kernel, dim3(1), dim3(64), 0, s, c, gw.hA, gw.hB, w.part, (int64_t)gc,
+                               gw.R, m, gw.cs, gw.sn, gw.g, o.inner_tol);
+            BFX_LAUNCH_CHECK("gmres step");
+        }
+        // d = V y with R y = g; x += d
+        hipLaunchKernelGGL(bfx::backsolve_kernel, dim3(1), dim3(256), 0, s, c, gw.R, m, gw.g, gw.y);
+        hipLaunchKernelGGL(bfx::combine_kernel, dim3(gc), dim3(256), 0, s, gw.V, n, gw.y, -1, x, x, n, 1.0,
+                           (double *)nullptr, c, 0);
+        BFX_LAUNCH_CHECK("gmres update");
+    }
+    return BFX_OK;
 }

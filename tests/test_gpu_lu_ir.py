@@ -201,3 +201,86 @@ def test_gmres_full_krylov_kappa_1e12(bfx):
     A, b, _ = workloads.conditioned_system(n, 1e12, 1200)
     x, res = _gmres(bfx, A, b, restart=n, inner_tol=0.0)
     assert res["status"] == 0 and res["eta"] <= 1e-14, res
+
+
+def _eta(A, b, x):
+    r = b - A.astype(np.float64) @ x
+    return np.abs(r).max() / (np.abs(A.astype(np.float64)).sum(1).max() * np.abs(x).max() + np.abs(b).max())
+
+
+@pytest.mark.parametrize("solver", ["ir", "gmres"])
+def test_solve_is_asynchronous_with_device_result(bfx, solver):
+    """The refinement is queued without waiting: behind ~20 ms of GEMMs the call
+    returns while the stream is still busy, and the result struct appears in
+    device memory when the stream gets there (Sec. III; the convergence test
+    runs on the device)."""
+    n = 512
+    A, b, _ = workloads.conditioned_system(n, 1e4, 41)
+    tA, tb = dev(A), dev(b)
+    tLU = tA.clone()
+    _, ipiv, _ = bfx.lu_factor(tLU, 6)
+    big = torch.randn(8192, 8192, device="cuda")
+    C = torch.empty_like(big)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        bfx.gemm(9, big, big, C)
+    if solver == "ir":
+        x, res = bfx.ir_solve(tA, tLU, ipiv, tb)
+    else:
+        x, res = bfx.gmres_ir_solve(tA, tLU, ipiv, tb, restart=40)
+    ev = torch.cuda.Event()
+    ev.record()
+    pending = not ev.query()
+    torch.cuda.synchronize()
+    assert pending, "the solve waited for the stream"
+    raw = res.device.cpu().numpy()
+    assert raw.size in (16, 24)
+    assert res["status"] == 0 and res["eta"] <= 1e-14, res
+    assert _eta(A, b, host(x)) <= 1.01e-14
+
+
+@pytest.mark.parametrize("n,kappa", [(1024, 1e8), (1024, 1e12), (2048, 1e8)])
+def test_gmres_ir_full_krylov_large(bfx, orc, n, kappa):
+    """kappa = 1e8 and 1e12 (kappa * 2^-24 >> 1): with a Krylov space as large
+    as the problem needs, GMRES-IR reaches eta <= 1e-14; eta recomputed from x,
+    refinement steps and GMRES steps against the oracle's."""
+    A, b, xt = workloads.conditioned_system(n, kappa, 1300 + n)
+    x, res = _gmres(bfx, A, b, restart=n, max_iter=4)
+    assert res["status"] == 0 and res["eta"] <= 1e-14, res
+    assert _eta(A, b, x) <= 1.01e-14
+    LU, ipiv, _ = orc.lu(A, 6, 128)
+    ro = orc.gmres_ir(A, LU, ipiv, b, restart=n, max_iter=4)
+    assert ro["status"] == 0
+    assert abs(ro["iters"] - res["iters"]) <= 1, (ro, res)
+    assert abs(ro["inner"] - res["inner"]) <= max(8, 0.1 * ro["inner"]), (ro, res)
+
+
+def test_lu_ir_n8192_sixteen_panel_workgroups(bfx):
+    """n = 8192: the panel runs 16 cooperating workgroups.  Valid pivots, LU
+    backward error componentwise within 2n 2^-24 |L||U| (checked in FP64 with
+    torch on the GPU), and LU-IR to eta <= 1e-14 at kappa = 1e4 with eta
+    recomputed from the returned x."""
+    n = 8192
+    dv = torch.device("cuda")
+    A, b = workloads.conditioned_system_torch(n, 1e4, 4242, dv)
+    LU = A.clone()
+    _, ipiv, info = bfx.lu_factor(LU, 6)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    piv = ipiv.cpu().numpy()
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    p = perm_from_ipiv(piv, n)
+    L = torch.tril(LU.double(), -1) + torch.eye(n, dtype=torch.float64, device=dv)
+    U = torch.triu(LU.double())
+    R = (A.double()[torch.from_numpy(p).to(dv)] - L @ U).abs()
+    scale = L.abs() @ U.abs()
+    ratio = float((R / (2 * n * 2.0 ** -24 * scale + 1e-300)).max().item())
+    del L, U, R, scale
+    assert ratio <= 1.0, ratio
+    x, res = bfx.ir_solve(A, LU, ipiv, b)
+    torch.cuda.synchronize()
+    assert res["status"] == 0, res
+    A64 = A.double()
+    eta = float(((b - A64 @ x).abs().max() /
+                 (A64.abs().sum(1).max() * x.abs().max() + b.abs().max())).item())
+    assert eta <= 1.01e-14, eta
