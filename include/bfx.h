@@ -327,7 +327,10 @@ int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu,
 /* ------------------------------------------------------------------------ */
 /* Many independent solves A x = b in one persistent, graph-captured launch:  */
 /* split-BF16 blocked LU (Sec. I, IV-A) + FP64-residual refinement (Sec. III) */
-/* for each problem, one workgroup per problem, longest problems first.       */
+/* for each problem, one workgroup per problem, longest problems first.  A    */
+/* problem that LU-IR leaves unconverged (max_iter reached or stagnation)     */
+/* continues from its current x with GMRES-IR (Sec. III, Sec. IV-B) when      */
+/* gmres_max_iter > 0, in the same workgroup.                                 */
 /* ------------------------------------------------------------------------ */
 typedef struct bfx_solve_desc {
     int64_t n;                     /* 1 <= n <= 1024 */
@@ -336,30 +339,44 @@ typedef struct bfx_solve_desc {
     double *x;                     /* device, n FP64, output */
 } bfx_solve_desc;
 
+typedef struct bfx_batched_solve_opts {
+    double tol;              /* backward error target (default 1e-14) */
+    int32_t max_iter;        /* LU-IR corrections (default 30) */
+    int32_t gmres_max_iter;  /* GMRES-IR steps after LU-IR fails (default 10;
+                                0 = LU-IR only) */
+    int32_t restart;         /* GMRES steps per cycle (default 0 = n, a full
+                                Krylov space) */
+    double inner_tol;        /* relative GMRES tolerance (default 1e-8) */
+} bfx_batched_solve_opts;
+
 typedef struct bfx_solve_plan bfx_solve_plan;
 
-/* descs: HOST array (copied).  opts: HOST pointer (NULL = tol 1e-14,
- * max_iter 30).  The plan owns the factor storage (sum of n^2 FP32), the
- * pivots and the per-problem results until bfx_solve_plan_destroy.  The
- * stopping rule and status codes are those of bfx_ir_solve.
+/* descs: HOST array (copied).  opts: HOST pointer (NULL = defaults).  The
+ * plan owns the factor storage (sum of n^2 FP32), the pivots, the
+ * per-problem results and, when GMRES is enabled, one scratch slice per
+ * workgroup for the GMRES basis and Hessenberg matrix ((m+1) nmax + m^2
+ * doubles, m = restart or nmax) until bfx_solve_plan_destroy.  The stopping
+ * rule and status codes are those of bfx_ir_solve.
  * Errors: -1 variant, -2 count < 0, -3 descs NULL, -4 opts invalid, -5 out
  * NULL, -(100+i) when descriptor i is invalid. */
 int bfx_lu_ir_batched_plan_create(int variant, int64_t count,
                                   const bfx_solve_desc *descs,
-                                  const bfx_ir_opts *opts, bfx_solve_plan **out);
+                                  const bfx_batched_solve_opts *opts,
+                                  bfx_solve_plan **out);
 
 /* All solves as one graph replay on `stream` (asynchronous). */
 int bfx_solve_plan_launch(bfx_solve_plan *plan, void *stream);
 
 /* Same solves with bfx_lu_factor + bfx_ir_solve per problem, queued one
  * after another on `stream` (the baseline the persistent launch is measured
- * against). */
+ * against; LU-IR only). */
 int bfx_solve_plan_launch_per_problem(bfx_solve_plan *plan, void *stream);
 
-/* Synchronises the device and copies the per-problem refinement results and
- * LU info (HOST arrays of `count` entries, in descriptor order; either may be
- * NULL). */
-int bfx_solve_plan_results(const bfx_solve_plan *plan, bfx_ir_result *results,
+/* Synchronises the device and copies the per-problem results (iters =
+ * refinement steps of LU-IR and GMRES-IR together, inner = GMRES steps,
+ * status, eta) and LU info (HOST arrays of `count` entries, in descriptor
+ * order; either may be NULL). */
+int bfx_solve_plan_results(const bfx_solve_plan *plan, bfx_gmres_result *results,
                            int32_t *info);
 
 int bfx_solve_plan_destroy(bfx_solve_plan *plan);

@@ -50,6 +50,11 @@ class GmresOpts(ctypes.Structure):
                 ("inner_tol", c_f64)]
 
 
+class BatchedSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", c_f64), ("max_iter", ctypes.c_int32), ("gmres_max_iter", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("inner_tol", c_f64)]
+
+
 class GmresResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("inner", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("eta", c_f64)]
@@ -94,10 +99,10 @@ SIGNATURES = {
     "bfx_gmres_ir_ws_size": ([c_i64, c_int], c_size),
     "bfx_lu_solve_f32": ([c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_size, c_vp], c_int),
     "bfx_lu_ir_batched_plan_create": ([c_int, c_i64, ctypes.POINTER(SolveDesc),
-                                       ctypes.POINTER(IrOpts), ctypes.POINTER(c_vp)], c_int),
+                                       ctypes.POINTER(BatchedSolveOpts), ctypes.POINTER(c_vp)], c_int),
     "bfx_solve_plan_launch": ([c_vp, c_vp], c_int),
     "bfx_solve_plan_launch_per_problem": ([c_vp, c_vp], c_int),
-    "bfx_solve_plan_results": ([c_vp, ctypes.POINTER(IrResult), ctypes.POINTER(ctypes.c_int32)], c_int),
+    "bfx_solve_plan_results": ([c_vp, ctypes.POINTER(GmresResult), ctypes.POINTER(ctypes.c_int32)], c_int),
     "bfx_solve_plan_destroy": ([c_vp], c_int),
 }
 

@@ -8,7 +8,8 @@ import os
 
 import torch
 
-from ._lib import GemmDesc, GmresOpts, GmresResult, IrOpts, IrResult, SolveDesc, check, lib
+from ._lib import (BatchedSolveOpts, GemmDesc, GmresOpts, GmresResult, IrOpts, IrResult, SolveDesc,
+                   check, lib)
 
 
 def _stream() -> int:
@@ -281,11 +282,14 @@ def gmres_ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: tor
 
 
 class BatchedSolvePlan:
-    """Many LU + refinement solves in one persistent, graph-captured launch.
+    """Many LU + refinement solves in one persistent, graph-captured launch;
+    problems that LU-IR leaves unconverged continue with GMRES-IR when
+    gmres_max_iter > 0 (restart 0 = a full Krylov space).
 
     problems: list of (A float32 n x n, b float64 n, x float64 n) GPU tensors."""
 
-    def __init__(self, variant: int, problems, tol: float = 1e-14, max_iter: int = 30):
+    def __init__(self, variant: int, problems, tol: float = 1e-14, max_iter: int = 30,
+                 gmres_max_iter: int = 10, restart: int = 0, inner_tol: float = 1e-8):
         self._keep = problems
         descs = (SolveDesc * len(problems))()
         for i, (A, b, x) in enumerate(problems):
@@ -293,7 +297,7 @@ class BatchedSolvePlan:
             _dev(b, torch.float64, "b")
             _dev(x, torch.float64, "x")
             descs[i] = SolveDesc(A.shape[0], A.data_ptr(), _rows(A, "A"), b.data_ptr(), x.data_ptr())
-        opts = IrOpts(tol, max_iter, 0)
+        opts = BatchedSolveOpts(tol, max_iter, gmres_max_iter, restart, inner_tol)
         h = ctypes.c_void_p()
         check(lib.bfx_lu_ir_batched_plan_create(variant, len(problems), descs, ctypes.byref(opts),
                                                  ctypes.byref(h)), "solve_plan_create")
@@ -307,10 +311,10 @@ class BatchedSolvePlan:
         check(lib.bfx_solve_plan_launch_per_problem(self._h, _stream()), "solve_per_problem")
 
     def results(self):
-        res = (IrResult * max(self.count, 1))()
+        res = (GmresResult * max(self.count, 1))()
         info = (ctypes.c_int32 * max(self.count, 1))()
         check(lib.bfx_solve_plan_results(self._h, res, info), "bfx_solve_plan_results")
-        return [dict(iters=r.iters, status=r.status, eta=r.eta, info=int(i))
+        return [dict(iters=r.iters, inner=r.inner, status=r.status, eta=r.eta, info=int(i))
                 for r, i in zip(list(res)[: self.count], list(info)[: self.count])]
 
     def close(self):

@@ -1,6 +1,8 @@
 // Many independent dense solves A x = b (n <= 1024) in one persistent,
 // graph-captured launch: split-BF16 blocked LU (Sec. I, IV-A) followed by
-// FP64-residual iterative refinement (Sec. III), one workgroup per problem.
+// FP64-residual iterative refinement (Sec. III), and GMRES-IR (Sec. III,
+// Sec. IV-B) for the systems that LU-IR leaves unconverged, one workgroup per
+// problem.
 //
 // Per problem, inside one 256-thread workgroup:
 //   LU     panels of 32 columns held in LDS (pivot search by wave shuffles and
@@ -11,7 +13,13 @@
 //   IR     |A|_inf and |b|_inf, the permutation from ipiv, then
 //          x0 = LUsolve32(b) and refinement steps with an FP64 residual (one
 //          wave per row) and FP32 triangular solves in 64-row blocks (the
-//          diagonal block in LDS, solved by one wave).
+//          diagonal block in LDS, solved by one wave);
+//   GMRES  when LU-IR stops without converging (max_iter reached or
+//          stagnation) and GMRES is enabled: refinement from the current x
+//          with FP64 GMRES on M^-1 A d = M^-1 r, M the FP32 factors applied
+//          in FP64 arithmetic, classical Gram-Schmidt twice, Givens
+//          rotations; the basis and the rotated Hessenberg matrix live in the
+//          workgroup's slice of the plan's scratch, the vectors in LDS.
 // Problems are taken from a work counter in descending n (longest first);
 // every workgroup loops until the list is exhausted.
 #include <algorithm>
@@ -38,9 +46,33 @@ struct SolveItem {
     double *x;
     float *LU;        // n x n, leading dimension n
     int32_t *ipiv;
-    bfx_ir_result *res;
+    bfx_gmres_result *res;
     int32_t *info;
 };
+
+// GMRES fallback settings shared by the launch.
+struct GmresCfg {
+    int max_iter;      // refinement steps with GMRES (0: no fallback)
+    int restart;       // basis size per cycle (0: n, a full Krylov space)
+    double inner_tol;  // relative GMRES tolerance
+    int64_t m_cap;     // basis capacity of a workgroup's scratch slice
+    double *scratch;   // gridDim.x slices of per_wg doubles
+    int64_t per_wg;
+};
+
+// LDS byte offsets of the refinement phases (inside the LU panel's space).
+constexpr int L_Y = 0;          // n floats (LU-IR solve vector)
+constexpr int L_R = 4096;       // n doubles: residual
+constexpr int L_PERM = 12288;   // n ints: row permutation
+constexpr int L_D = 16384;      // 64 x 65 floats: diagonal block of a solve
+constexpr int L_V = 33024;      // n doubles: current basis vector
+constexpr int L_W = 41216;      // n doubles: GMRES work vector
+constexpr int L_HA = 49408;     // m + 1 doubles: first Gram-Schmidt pass
+constexpr int L_HB = 57608;     // m + 1 doubles: second pass
+constexpr int L_CS = 65808;     // m doubles: rotation cosines
+constexpr int L_SN = 74000;     // m doubles: rotation sines
+constexpr int L_G = 82192;      // m + 1 doubles: rotated right-hand side
+constexpr int L_END = 90392;
 }  // namespace
 
 __device__ __forceinline__ void argmax_better(float &v, int &i, float v2, int i2) {
@@ -76,9 +108,10 @@ __device__ __forceinline__ double block_max_d(double v, double *sd) {
     return m;
 }
 
-// In-place FP32 solve of (L or U) y = y with y in LDS, factors in global LU.
-template <bool LOWER>
-__device__ void block_trsv(const float *LU, int n, float *y, float *D) {
+// In-place solve of (L or U) y = y with y in LDS (T = float for LU-IR, double
+// for the GMRES preconditioner), FP32 factors in global LU.
+template <typename T, bool LOWER>
+__device__ void block_trsv(const float *LU, int n, T *y, float *D) {
     const int t = threadIdx.x, lane = t & 63;
     const int nblk = (n + STB - 1) / STB;
     for (int bb = 0; bb < nblk; ++bb) {
@@ -91,17 +124,17 @@ __device__ void block_trsv(const float *LU, int n, float *y, float *D) {
         }
         __syncthreads();
         if (t < 64) {
-            float v = (lane < rows) ? y[k0 + lane] : 0.0f;
+            T v = (lane < rows) ? y[k0 + lane] : (T)0;
             if (LOWER) {
                 for (int c = 0; c < rows; ++c) {
-                    const float yc = __shfl(v, c);
-                    if (lane > c) v = fmaf(-D[lane * (STB + 1) + c], yc, v);
+                    const T yc = __shfl(v, c);
+                    if (lane > c) v = fma(-(T)D[lane * (STB + 1) + c], yc, v);
                 }
             } else {
                 for (int c = rows - 1; c >= 0; --c) {
-                    if (lane == c) v = v / D[c * (STB + 1) + c];
-                    const float yc = __shfl(v, c);
-                    if (lane < c) v = fmaf(-D[lane * (STB + 1) + c], yc, v);
+                    if (lane == c) v = v / (T)D[c * (STB + 1) + c];
+                    const T yc = __shfl(v, c);
+                    if (lane < c) v = fma(-(T)D[lane * (STB + 1) + c], yc, v);
                 }
             }
             if (lane < rows) y[k0 + lane] = v;
@@ -111,16 +144,204 @@ __device__ void block_trsv(const float *LU, int n, float *y, float *D) {
         const int lo = LOWER ? k0 + rows : 0, hi = LOWER ? n : k0;
         for (int i = lo + t; i < hi; i += 256) {
             const float *row = LU + (int64_t)i * n + k0;
-            float acc = 0.0f;
-            for (int c = 0; c < rows; ++c) acc = fmaf(row[c], y[k0 + c], acc);
+            T acc = (T)0;
+            for (int c = 0; c < rows; ++c) acc = fma((T)row[c], y[k0 + c], acc);
             y[i] -= acc;
         }
         __syncthreads();
     }
 }
 
+__device__ __forceinline__ double block_sum_d(double v, double *sd) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) sd[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double s = (sd[0] + sd[1]) + (sd[2] + sd[3]);
+    __syncthreads();
+    return s;
+}
+
+// r = b - A x (FP64, one wave per row) into LDS; returns |r|_inf.
+__device__ double residual_wg(const SolveItem &it, int n, double *r, double *sd) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double rl = 0.0;
+    for (int row = wave; row < n; row += 4) {
+        double s = 0.0;
+        for (int c = lane; c < n; c += 64) s = fma((double)it.A[(int64_t)row * it.lda + c], it.x[c], s);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        const double ri = it.b[row] - s;
+        if (lane == 0) r[row] = ri;
+        const double a = fabs(ri);
+        if (a > rl || a != a) rl = a;
+    }
+    return block_max_d(rl, sd);
+}
+
+__device__ double absmax_x_wg(const SolveItem &it, int n, double *sd) {
+    double xl = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double a = fabs(it.x[i]);
+        if (a > xl || a != a) xl = a;
+    }
+    return block_max_d(xl, sd);
+}
+
+// The stopping rule of the refinement (status as bfx_ir_result; -1: go on).
+__device__ __forceinline__ int ir_decide(double eta, double tol, int iters, int max_iter, int rises) {
+    if (!(eta <= INFINITY) || eta == INFINITY) return 3;
+    if (eta <= tol) return 0;
+    if (iters >= max_iter) return 1;
+    if (rises >= 2) return 2;
+    return -1;
+}
+
+// GMRES-IR from the current x (Sec. III, Sec. IV-B): each refinement step
+// solves A d = r by one GMRES cycle on M^-1 A d = M^-1 r (d0 = 0), M = the
+// FP32 factors applied in FP64; x += d.  Returns the status; adds the
+// refinement and GMRES steps taken to iters and inner; eta is the last one.
+__device__ int gmres_phase(const SolveItem &it, const GmresCfg &cfg, double normA, double normb, double tol,
+                           uint16_t *smem, int &iters, int &inner, double &eta) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int n = (int)it.n;
+    const float *LU = it.LU;
+    char *sb = reinterpret_cast<char *>(smem);
+    double *r = reinterpret_cast<double *>(sb + L_R);
+    const int32_t *perm = reinterpret_cast<const int32_t *>(sb + L_PERM);
+    float *D = reinterpret_cast<float *>(sb + L_D);
+    double *v = reinterpret_cast<double *>(sb + L_V);
+    double *w = reinterpret_cast<double *>(sb + L_W);
+    double *hA = reinterpret_cast<double *>(sb + L_HA);
+    double *hB = reinterpret_cast<double *>(sb + L_HB);
+    double *cs = reinterpret_cast<double *>(sb + L_CS);
+    double *sn = reinterpret_cast<double *>(sb + L_SN);
+    double *g = reinterpret_cast<double *>(sb + L_G);
+    __shared__ double s_d[4];
+    __shared__ double s_hn;
+    __shared__ int s_conv;
+    const int m = (int)((cfg.restart > 0 && cfg.restart < n) ? cfg.restart : n);
+    double *V = cfg.scratch + (int64_t)blockIdx.x * cfg.per_wg;          // (m_cap + 1) x n
+    double *R = V + (cfg.m_cap + 1) * (int64_t)n;                         // m_cap x m_cap, column-major
+    const int64_t ldr = cfg.m_cap;
+    int steps = 0, rises = 0, status = 1;
+    double prev_eta = INFINITY;
+    for (;;) {
+        const double rn = residual_wg(it, n, r, s_d);
+        const double xn = absmax_x_wg(it, n, s_d);
+        const double den = normA * xn + normb;
+        eta = den > 0.0 ? rn / den : rn;
+        rises = (eta >= prev_eta) ? rises + 1 : 0;
+        prev_eta = eta;
+        status = ir_decide(eta, tol, steps, cfg.max_iter, rises);
+        if (status >= 0) break;
+        // w = M^-1 r = U^-1 L^-1 P r
+        for (int i = t; i < n; i += 256) w[i] = r[perm[i]];
+        __syncthreads();
+        block_trsv<double, true>(LU, n, w, D);
+        block_trsv<double, false>(LU, n, w, D);
+        double q = 0.0;
+        for (int i = t; i < n; i += 256) q = fma(w[i], w[i], q);
+        const double beta = sqrt(block_sum_d(q, s_d));
+        int k = 0;
+        if (beta > 0.0 && beta < INFINITY) {
+            const double rb = 1.0 / beta;
+            for (int i = t; i < n; i += 256) {
+                const double vi = w[i] * rb;
+                v[i] = vi;
+                V[i] = vi;
+            }
+            if (t == 0) g[0] = beta;
+            __syncthreads();
+            for (k = 0; k < m;) {
+                // w = P A v
+                for (int row = wave; row < n; row += 4) {
+                    const float *a = it.A + (int64_t)perm[row] * it.lda;
+                    double s = 0.0;
+                    for (int c = lane; c < n; c += 64) s = fma((double)a[c], v[c], s);
+                    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                    if (lane == 0) w[row] = s;
+                }
+                __syncthreads();
+                block_trsv<double, true>(LU, n, w, D);
+                block_trsv<double, false>(LU, n, w, D);
+                // classical Gram-Schmidt, twice
+                for (int pass = 0; pass < 2; ++pass) {
+                    double *h = pass ? hB : hA;
+                    for (int j = wave; j <= k; j += 4) {
+                        const double *vj = V + (int64_t)j * n;
+                        double s = 0.0;
+                        for (int i = lane; i < n; i += 64) s = fma(vj[i], w[i], s);
+                        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                        if (lane == 0) h[j] = s;
+                    }
+                    __syncthreads();
+                    for (int i = t; i < n; i += 256) {
+                        double acc = 0.0;
+                        for (int j = 0; j <= k; ++j) acc = fma(h[j], V[(int64_t)j * n + i], acc);
+                        w[i] -= acc;
+                    }
+                    __syncthreads();
+                }
+                double qq = 0.0;
+                for (int i = t; i < n; i += 256) qq = fma(w[i], w[i], qq);
+                const double hn = sqrt(block_sum_d(qq, s_d));
+                if (t == 0) {
+                    // earlier rotations on column k, then a new one
+                    double *col = R + (int64_t)k * ldr;
+                    double carry = hA[0] + hB[0];
+                    for (int j = 0; j < k; ++j) {
+                        const double hj1 = hA[j + 1] + hB[j + 1];
+                        col[j] = cs[j] * carry + sn[j] * hj1;
+                        carry = -sn[j] * carry + cs[j] * hj1;
+                    }
+                    const double rho = hypot(carry, hn);
+                    const double ck = rho > 0.0 ? carry / rho : 1.0, sk = rho > 0.0 ? hn / rho : 0.0;
+                    cs[k] = ck;
+                    sn[k] = sk;
+                    col[k] = rho;
+                    const double gk = g[k];
+                    g[k + 1] = -sk * gk;
+                    g[k] = ck * gk;
+                    s_conv = (fabs(g[k + 1]) <= cfg.inner_tol * beta || hn == 0.0) ? 1 : 0;
+                    s_hn = hn;
+                }
+                __syncthreads();
+                ++k;
+                ++inner;
+                if (s_conv || k >= m) break;
+                const double rh = 1.0 / s_hn;
+                double *Vk = V + (int64_t)k * n;
+                for (int i = t; i < n; i += 256) {
+                    const double vi = w[i] * rh;
+                    v[i] = vi;
+                    Vk[i] = vi;
+                }
+                __syncthreads();
+            }
+            // y = R^-1 g (column by column from the last; y in hA), x += V y
+            double *y = hA;
+            for (int j = k - 1; j >= 0; --j) {
+                if (t == 0) y[j] = g[j] / R[(int64_t)j * ldr + j];
+                __syncthreads();
+                const double yj = y[j];
+                const double *colj = R + (int64_t)j * ldr;
+                for (int i = t; i < j; i += 256) g[i] = fma(-colj[i], yj, g[i]);
+                __syncthreads();
+            }
+            for (int i = t; i < n; i += 256) {
+                double acc = 0.0;
+                for (int j = 0; j < k; ++j) acc = fma(y[j], V[(int64_t)j * n + i], acc);
+                it.x[i] += acc;
+            }
+            __syncthreads();
+        }
+        ++steps;
+    }
+    iters += steps;
+    return status;
+}
+
 template <int V>
-__device__ void solve_one(const SolveItem &it, double tol, int max_iter, uint16_t *smem) {
+__device__ void solve_one(const SolveItem &it, double tol, int max_iter, const GmresCfg &cfg, uint16_t *smem) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int n = (int)it.n;
     float *LU = it.LU;
@@ -240,10 +461,11 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, uint16_
     }
 
     // ---- iterative refinement (Sec. III)
-    float *y = reinterpret_cast<float *>(smem);                  // n floats
-    double *r = reinterpret_cast<double *>(smem + 2 * SMAXN);    // n doubles (byte offset 4096)
-    int32_t *perm = reinterpret_cast<int32_t *>(smem + 6 * SMAXN);  // n ints (byte offset 12288)
-    float *D = reinterpret_cast<float *>(smem + 8 * SMAXN);      // 64 x 65 (byte offset 16384)
+    char *sb = reinterpret_cast<char *>(smem);
+    float *y = reinterpret_cast<float *>(sb + L_Y);
+    double *r = reinterpret_cast<double *>(sb + L_R);
+    int32_t *perm = reinterpret_cast<int32_t *>(sb + L_PERM);
+    float *D = reinterpret_cast<float *>(sb + L_D);
     const float *A = it.A;
     // norms
     double rowmax = 0.0;
@@ -270,54 +492,51 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, uint16_
     __syncthreads();
     for (int i = t; i < n; i += 256) y[i] = (float)it.b[perm[i]];
     __syncthreads();
-    block_trsv<true>(LU, n, y, D);
-    block_trsv<false>(LU, n, y, D);
+    block_trsv<float, true>(LU, n, y, D);
+    block_trsv<float, false>(LU, n, y, D);
     for (int i = t; i < n; i += 256) it.x[i] = (double)y[i];
     __syncthreads();
 
-    int iters = 0, rises = 0, status = 1;
+    int iters = 0, rises = 0, status = 1, inner = 0;
     double eta = 0.0, prev_eta = INFINITY;
     for (;;) {
-        double rl = 0.0;
-        for (int row = wave; row < n; row += 4) {
-            double s = 0.0;
-            for (int c = lane; c < n; c += 64) s = fma((double)A[(int64_t)row * it.lda + c], it.x[c], s);
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            const double ri = it.b[row] - s;
-            if (lane == 0) r[row] = ri;
-            const double a = fabs(ri);
-            if (a > rl || a != a) rl = a;
-        }
-        const double rn = block_max_d(rl, s_d);
-        double xl = 0.0;
-        for (int i = t; i < n; i += 256) {
-            const double a = fabs(it.x[i]);
-            if (a > xl || a != a) xl = a;
-        }
-        const double xn = block_max_d(xl, s_d);
+        const double rn = residual_wg(it, n, r, s_d);
+        const double xn = absmax_x_wg(it, n, s_d);
         const double den = normA * xn + normb;
         eta = den > 0.0 ? rn / den : rn;
         rises = (eta >= prev_eta) ? rises + 1 : 0;
         prev_eta = eta;
-        if (!(eta <= INFINITY)) { status = 3; break; }   // NaN
-        if (eta == INFINITY) { status = 3; break; }
-        if (eta <= tol) { status = 0; break; }
-        if (iters >= max_iter) { status = 1; break; }
-        if (rises >= 2) { status = 2; break; }
+        status = ir_decide(eta, tol, iters, max_iter, rises);
+        if (status >= 0) break;
         for (int i = t; i < n; i += 256) y[i] = (float)(r[perm[i]] / rn);
         __syncthreads();
-        block_trsv<true>(LU, n, y, D);
-        block_trsv<false>(LU, n, y, D);
+        block_trsv<float, true>(LU, n, y, D);
+        block_trsv<float, false>(LU, n, y, D);
         for (int i = t; i < n; i += 256) it.x[i] = fma(rn, (double)y[i], it.x[i]);
         __syncthreads();
         ++iters;
     }
+    if ((status == 1 || status == 2) && cfg.max_iter > 0)
+        status = gmres_phase(it, cfg, normA, normb, tol, smem, iters, inner, eta);
     if (t == 0) {
         it.res->iters = iters;
+        it.res->inner = inner;
         it.res->status = status;
+        it.res->reserved = 0;
         it.res->eta = eta;
     }
     __syncthreads();
+}
+
+// Per-problem baseline results (bfx_ir_solve's) in the plan's result type.
+__global__ void __launch_bounds__(64) ir_to_gmres_result(const bfx_ir_result *src, bfx_gmres_result *dst) {
+    if (threadIdx.x == 0) {
+        dst->iters = src->iters;
+        dst->inner = 0;
+        dst->status = src->status;
+        dst->reserved = 0;
+        dst->eta = src->eta;
+    }
 }
 
 __global__ void __launch_bounds__(64) solve_zero_counter(uint32_t *c) {
@@ -327,7 +546,7 @@ __global__ void __launch_bounds__(64) solve_zero_counter(uint32_t *c) {
 template <int V>
 __global__ void __launch_bounds__(256, 1)
 persistent_solve_kernel(const SolveItem *__restrict__ items, int64_t count, uint32_t *counter,
-                        double tol, int max_iter) {
+                        double tol, int max_iter, GmresCfg cfg) {
     extern __shared__ __align__(16) uint16_t smem[];
     __shared__ int64_t s_idx;
     for (;;) {
@@ -336,7 +555,7 @@ persistent_solve_kernel(const SolveItem *__restrict__ items, int64_t count, uint
         const int64_t idx = s_idx;
         __syncthreads();
         if (idx >= count) break;
-        solve_one<V>(items[idx], tol, max_iter, smem);
+        solve_one<V>(items[idx], tol, max_iter, cfg, smem);
     }
 }
 
@@ -345,14 +564,17 @@ persistent_solve_kernel(const SolveItem *__restrict__ items, int64_t count, uint
 struct bfx_solve_plan {
     int variant = 6;
     int64_t count = 0;
-    bfx_ir_opts opts = {1e-14, 30, 0};
+    bfx_batched_solve_opts opts = {1e-14, 30, 10, 0, 1e-8};
     std::vector<bfx_solve_desc> h_desc;
     std::vector<int64_t> lu_off, piv_off;   // host copies of per-problem offsets
     bfx::SolveItem *d_items = nullptr;
     float *d_lu = nullptr;
     int32_t *d_ipiv = nullptr;
-    bfx_ir_result *d_res = nullptr;
+    bfx_gmres_result *d_res = nullptr;
+    bfx_ir_result *d_res_ir = nullptr;     // per-problem baseline
     int32_t *d_info = nullptr;
+    double *d_scratch = nullptr;           // GMRES basis and Hessenberg, per workgroup
+    int64_t m_cap = 0, per_wg = 0;
     uint32_t *d_counter = nullptr;
     void *d_ws = nullptr;
     size_t ws_bytes = 0;
@@ -374,7 +596,9 @@ void solve_plan_free(bfx_solve_plan *p) {
     if (p->d_lu) (void)hipFree(p->d_lu);
     if (p->d_ipiv) (void)hipFree(p->d_ipiv);
     if (p->d_res) (void)hipFree(p->d_res);
+    if (p->d_res_ir) (void)hipFree(p->d_res_ir);
     if (p->d_info) (void)hipFree(p->d_info);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->d_counter) (void)hipFree(p->d_counter);
     if (p->d_ws) (void)hipFree(p->d_ws);
     delete p;
@@ -385,12 +609,14 @@ const void *solve_kernel_for() { return (const void *)persistent_solve_kernel<V>
 }  // namespace bfx
 
 extern "C" int bfx_lu_ir_batched_plan_create(int variant, int64_t count, const bfx_solve_desc *descs,
-                                             const bfx_ir_opts *opts, bfx_solve_plan **out) {
+                                             const bfx_batched_solve_opts *opts, bfx_solve_plan **out) {
     using namespace bfx;
     if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
     if (count < 0) return -2;
     if (count > 0 && !descs) return -3;
-    if (opts && (!(opts->tol >= 0.0) || opts->max_iter < 0)) return -4;
+    if (opts && (!(opts->tol >= 0.0) || opts->max_iter < 0 || opts->gmres_max_iter < 0 ||
+                 opts->restart < 0 || !(opts->inner_tol >= 0.0)))
+        return -4;
     if (!out) return -5;
     *out = nullptr;
     for (int64_t i = 0; i < count; ++i) {
@@ -431,8 +657,10 @@ extern "C" int bfx_lu_ir_batched_plan_create(int variant, int64_t count, const b
         return fail(e, "hipMalloc(plan factors)");
     if ((e = hipMalloc(&p->d_ipiv, sizeof(int32_t) * (piv_total > 0 ? piv_total : 1))) != hipSuccess)
         return fail(e, "hipMalloc(plan ipiv)");
-    if ((e = hipMalloc(&p->d_res, sizeof(bfx_ir_result) * cn)) != hipSuccess)
+    if ((e = hipMalloc(&p->d_res, sizeof(bfx_gmres_result) * cn)) != hipSuccess)
         return fail(e, "hipMalloc(plan results)");
+    if ((e = hipMalloc(&p->d_res_ir, sizeof(bfx_ir_result) * cn)) != hipSuccess)
+        return fail(e, "hipMalloc(plan baseline results)");
     if ((e = hipMalloc(&p->d_info, sizeof(int32_t) * cn)) != hipSuccess) return fail(e, "hipMalloc(plan info)");
     if ((e = hipMalloc(&p->d_counter, 256)) != hipSuccess) return fail(e, "hipMalloc(plan counter)");
     if ((e = hipMalloc(&p->d_items, sizeof(SolveItem) * cn)) != hipSuccess) return fail(e, "hipMalloc(plan items)");
@@ -468,6 +696,15 @@ extern "C" int bfx_lu_ir_batched_plan_create(int variant, int64_t count, const b
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return fail(e, "hipDeviceGetAttribute");
     p->grid = (int)std::min<int64_t>(cus, cn);
+    if (p->opts.gmres_max_iter > 0 && count > 0) {
+        // one slice per workgroup: basis (m_cap + 1) x nmax and R m_cap x m_cap
+        int64_t nmax = 0;
+        for (int64_t i = 0; i < count; ++i) nmax = std::max<int64_t>(nmax, descs[i].n);
+        p->m_cap = p->opts.restart > 0 ? std::min<int64_t>(p->opts.restart, nmax) : nmax;
+        p->per_wg = (p->m_cap + 1) * nmax + p->m_cap * p->m_cap;
+        if ((e = hipMalloc(&p->d_scratch, sizeof(double) * p->per_wg * p->grid)) != hipSuccess)
+            return fail(e, "hipMalloc(plan GMRES scratch)");
+    }
     if ((e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) != hipSuccess)
         return fail(e, "hipStreamCreate(solve plan)");
     *out = p;
@@ -483,7 +720,14 @@ extern "C" int bfx_solve_plan_launch(bfx_solve_plan *p, void *stream) {
         hipLaunchKernelGGL(solve_zero_counter, dim3(1), dim3(64), 0, p->cap, p->d_counter);
         double tol = p->opts.tol;
         int max_iter = p->opts.max_iter;
-        void *args[] = {&p->d_items, &p->count, &p->d_counter, &tol, &max_iter};
+        GmresCfg cfg;
+        cfg.max_iter = p->d_scratch ? p->opts.gmres_max_iter : 0;
+        cfg.restart = (int)p->m_cap;
+        cfg.inner_tol = p->opts.inner_tol;
+        cfg.m_cap = p->m_cap;
+        cfg.scratch = p->d_scratch;
+        cfg.per_wg = p->per_wg;
+        void *args[] = {&p->d_items, &p->count, &p->d_counter, &tol, &max_iter, &cfg};
         hipError_t el = hipLaunchKernel(p->kernel, dim3(p->grid), dim3(256), args, SOLVE_LDS, p->cap);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(p->cap, &g);
@@ -511,19 +755,22 @@ extern "C" int bfx_solve_plan_launch_per_problem(bfx_solve_plan *p, void *stream
         int rc = bfx_lu_factor(p->variant, d.n, lu, d.n, p->d_ipiv + p->piv_off[i], p->d_info + i, p->d_ws,
                                p->ws_bytes, s);
         if (rc) return rc;
-        rc = bfx_ir_solve(d.n, d.A, d.lda, lu, d.n, p->d_ipiv + p->piv_off[i], d.b, d.x, &p->opts,
-                          p->d_res + i, p->d_ws, p->ws_bytes, s);
+        const bfx_ir_opts io = {p->opts.tol, p->opts.max_iter, 0};
+        rc = bfx_ir_solve(d.n, d.A, d.lda, lu, d.n, p->d_ipiv + p->piv_off[i], d.b, d.x, &io,
+                          p->d_res_ir + i, p->d_ws, p->ws_bytes, s);
         if (rc) return rc;
+        hipLaunchKernelGGL(ir_to_gmres_result, dim3(1), dim3(64), 0, s, p->d_res_ir + i, p->d_res + i);
+        BFX_LAUNCH_CHECK("per-problem result");
     }
     return BFX_OK;
 }
 
-extern "C" int bfx_solve_plan_results(const bfx_solve_plan *p, bfx_ir_result *results, int32_t *info) {
+extern "C" int bfx_solve_plan_results(const bfx_solve_plan *p, bfx_gmres_result *results, int32_t *info) {
     using namespace bfx;
     if (!p) return -1;
     BFX_HIP(hipDeviceSynchronize());
     if (results && p->count)
-        BFX_HIP(hipMemcpy(results, p->d_res, sizeof(bfx_ir_result) * p->count, hipMemcpyDeviceToHost));
+        BFX_HIP(hipMemcpy(results, p->d_res, sizeof(bfx_gmres_result) * p->count, hipMemcpyDeviceToHost));
     if (info && p->count)
         BFX_HIP(hipMemcpy(info, p->d_info, sizeof(int32_t) * p->count, hipMemcpyDeviceToHost));
     return BFX_OK;

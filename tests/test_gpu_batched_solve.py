@@ -2,7 +2,8 @@
 every problem converges to eta <= 1e-14 (recomputed in numpy), agrees with
 LAPACK's FP64 solve within the conditioning, takes about as many refinement
 steps as the oracle, matches the one-problem-at-a-time path, and replays
-bit-identically."""
+bit-identically.  At kappa = 1e8 and 1e12 the systems LU-IR cannot finish
+continue with GMRES-IR in the same launch and reach eta <= 1e-14 too."""
 import numpy as np
 import pytest
 import torch
@@ -78,7 +79,7 @@ def test_batched_solves_singular_and_limits(bfx):
     As[:, 5] = 0
     probs = [(dev(As), dev(b), torch.empty(80, dtype=torch.float64, device="cuda")),
              (dev(A), dev(b), torch.empty(80, dtype=torch.float64, device="cuda"))]
-    plan = bfx.BatchedSolvePlan(6, probs, max_iter=0)
+    plan = bfx.BatchedSolvePlan(6, probs, max_iter=0, gmres_max_iter=0)
     plan.launch()
     r = plan.results()
     assert r[0]["info"] == 6 and r[0]["status"] == 3
@@ -88,3 +89,32 @@ def test_batched_solves_singular_and_limits(bfx):
     with pytest.raises(Exception):
         bfx.BatchedSolvePlan(6, [(big, torch.zeros(1025, dtype=torch.float64, device="cuda"),
                                   torch.zeros(1025, dtype=torch.float64, device="cuda"))])
+
+
+@pytest.mark.parametrize("kappa", [1e8, 1e12])
+def test_batched_solves_gmres_fallback_high_kappa(bfx, orc, kappa):
+    """kappa * 2^-24 >> 1: LU-IR stalls (Sec. III); the fallback to GMRES-IR
+    with a full Krylov space brings every size up to 1024 to eta <= 1e-14
+    (recomputed), and the solution agrees with LAPACK's FP64 solve within the
+    conditioning.  The oracle's GMRES-IR converges on the same systems."""
+    sizes = [1, 2, 17, 64, 129, 255, 333, 512, 700, 1024]
+    systems = _systems(sizes, kappa, 970)
+    probs = [(dev(A), dev(b), torch.empty(len(b), dtype=torch.float64, device="cuda"))
+             for (A, b, _) in systems]
+    plan = bfx.BatchedSolvePlan(6, probs)
+    plan.launch()
+    res = plan.results()
+    used = 0
+    for (A, b, xt), (_, _, tx), r, n in zip(systems, probs, res, sizes):
+        x = host(tx)
+        assert r["status"] == 0 and r["info"] == 0, (n, r)
+        assert r["eta"] <= 1e-14 and _eta(A, b, x) <= 1.01e-14, (n, r)
+        xr = np.linalg.solve(A.astype(np.float64), b)
+        assert np.max(np.abs(x - xr)) <= 100 * kappa * 2.0 ** -52 * max(n, 1) ** 0.5 * np.max(np.abs(xr)), n
+        used += r["inner"] > 0
+        if 64 <= n <= 333:
+            LU, ipiv, _ = orc.lu(A, 6, 32)
+            ro = orc.gmres_ir(A, LU, ipiv, b, restart=n)
+            assert ro["status"] == 0, (n, ro)
+    assert used >= (1 if kappa < 1e10 else len(sizes) // 2), res
+    plan.close()
