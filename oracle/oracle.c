@@ -126,16 +126,28 @@ void orc_split(const float *a, int64_t n, uint16_t *b0, uint16_t *b1,
 /*   7: Z0 + (Z1 + (Z2 + Z12))       (R-x7, worked example Sec. II-G)   */
 /*   8: Z0 + (Z1 + (Z2 + Z3))        (Z_3 of Sec. II-D)                 */
 /*   9: Z0 + (Z1 + (Z2 + (Z3 + Z4))) (R-bins)                           */
+/*  12, 13, 21, 23, 31, 32: per-operand split counts (see per_operand)   */
 /* ------------------------------------------------------------------ */
+/* Per-operand split counts (Sec. II-G, "a different number of splits"):  */
+/* variant 10 pa + pb (pa != pb, both in 1..3) takes pa BF16 terms of A   */
+/* and pb of B and the products a_i b_j with i < pa, j < pb and i + j <= 2 */
+/* (bins 0-2); its bins and their order are those of x6 (x3 when both    */
+/* counts are at most 2), an absent product being a +0 chain.             */
+static int per_operand(int v)
+{
+    return v == 12 || v == 13 || v == 21 || v == 23 || v == 31 || v == 32;
+}
+
 static int variant_ok(int v)
 {
-    return v == 1 || v == 3 || v == 6 || v == 7 || v == 8 || v == 9;
+    return v == 1 || v == 3 || v == 6 || v == 7 || v == 8 || v == 9 || per_operand(v);
 }
 
 /* Which (i,j) partial inner products a variant needs (Sec. II-D). */
 static int needs(int v, int i, int j)
 {
     int lvl = i + j;
+    if (per_operand(v)) return i < v / 10 && j < v % 10 && lvl <= 2;
     if (v == 1) return lvl == 0;
     if (v == 3) return lvl <= 1 && i <= 1 && j <= 1;
     if (v == 6) return lvl <= 2;
@@ -148,6 +160,7 @@ static int needs(int v, int i, int j)
 /* first.  Z[i][j] holds the FP32 partial inner products.               */
 static float combine_bins(int v, float Z[3][3])
 {
+    if (per_operand(v)) v = (v / 10 <= 2 && v % 10 <= 2) ? 3 : 6;
     float Z0 = Z[0][0];
     if (v == 1) return Z0;
     float Z1 = Z[0][1] + Z[1][0];
@@ -165,6 +178,7 @@ static float combine_bins(int v, float Z[3][3])
 /* option of the Sec. IV-A GEMM); the partial products stay FP32 chains.*/
 static double combine_bins_f64(int v, float Z[3][3])
 {
+    if (per_operand(v)) v = (v / 10 <= 2 && v % 10 <= 2) ? 3 : 6;
     double Z0 = Z[0][0];
     if (v == 1) return Z0;
     double Z1 = (double)Z[0][1] + (double)Z[1][0];

@@ -17,6 +17,8 @@ from tests.exact import add32, fl32, fma32, frac
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 U = 2.0 ** -24
 VARIANTS = (1, 3, 6, 7, 8, 9)
+# per-operand split counts (Sec. II-G): 10 * (terms of A) + (terms of B)
+PER_OPERAND = (12, 13, 21, 23, 31, 32)
 
 
 def ref64(A, B):
@@ -168,9 +170,15 @@ def _emulate(variant, x, y, fp64_sum=False):
 
     xs = [split(v) for v in x]
     ys = [split(v) for v in y]
-    need = {1: lambda i, j: i + j == 0, 3: lambda i, j: i + j <= 1,
-            6: lambda i, j: i + j <= 2, 7: lambda i, j: i + j <= 2 or (i, j) == (1, 2),
-            8: lambda i, j: i + j <= 3, 9: lambda i, j: True}[variant]
+    if variant in PER_OPERAND:
+        pa, pb = divmod(variant, 10)
+        need = lambda i, j: i < pa and j < pb and i + j <= 2  # noqa: E731
+        # bins and brackets of x3 (both counts <= 2) or x6, absent products as +0 chains
+        variant = 3 if max(pa, pb) <= 2 else 6
+    else:
+        need = {1: lambda i, j: i + j == 0, 3: lambda i, j: i + j <= 1,
+                6: lambda i, j: i + j <= 2, 7: lambda i, j: i + j <= 2 or (i, j) == (1, 2),
+                8: lambda i, j: i + j <= 3, 9: lambda i, j: True}[variant]
     Z = [[np.float32(0)] * 3 for _ in range(3)]
     for i in range(3):
         for j in range(3):
@@ -208,7 +216,7 @@ def _emulate(variant, x, y, fp64_sum=False):
     return fl32(frac(r)) if fp64_sum else r
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS + PER_OPERAND)
 def test_exact_rational_emulation_tiny(orc, variant):
     """Brute force on tiny inputs: the C oracle equals an exact-rational emulation
     of the algorithm bit for bit (checks FMA, ordering and the bin brackets)."""
@@ -287,6 +295,9 @@ def test_each_product_is_in_exactly_its_variants(orc):
         8: {(i, j) for i in range(3) for j in range(3) if i + j <= 3},
         9: {(i, j) for i in range(3) for j in range(3)},
     }
+    for v in PER_OPERAND:
+        pa, pb = divmod(v, 10)
+        included[v] = {(i, j) for i in range(pa) for j in range(pb) if i + j <= 2}
     F = Fraction
     probes = {
         "column": (np.array([[a, a]], np.float32), np.array([[a], [-a2]], np.float32),
@@ -409,3 +420,41 @@ def test_argument_errors(orc):
         orc.gemm(5, A, A)
     with pytest.raises(ValueError):
         orc.gemm(2, A, A)
+
+
+def _terms(X, nterms):
+    """X rounded to its first `nterms` BF16 terms (values with no further terms)."""
+    planes = orc_split_planes(X)
+    out = np.zeros(X.shape, np.float64)
+    for p in planes[:nterms]:
+        out += p
+    return out.astype(np.float32)
+
+
+def orc_split_planes(X):
+    import oracle
+    return [oracle.bf16_bits_to_f32(h).reshape(X.shape).astype(np.float64) for h in oracle.split(X.ravel())]
+
+
+@pytest.mark.parametrize("variant", PER_OPERAND)
+def test_per_operand_equals_full_when_dropped_terms_vanish(orc, variant):
+    """Sec. II-G, different split counts per operand: when A has no terms beyond
+    its pa-th and B none beyond its pb-th, the products the variant drops are
+    exactly zero and it returns the bits of the variant with all terms (x6, or
+    x3 when both counts are at most 2); on general data it does not (the
+    dropped products matter), and its error is within the bound of the weaker
+    operand's count."""
+    pa, pb = divmod(variant, 10)
+    full = 3 if max(pa, pb) <= 2 else 6
+    for seed in range(3):
+        A = workloads.gauss_exp((17, 33), 700 + seed, sigma=2)
+        B = workloads.gauss_exp((33, 9), 800 + seed, sigma=2)
+        At, Bt = _terms(A, pa), _terms(B, pb)
+        np.testing.assert_array_equal(orc.gemm(variant, At, Bt).view(np.uint32),
+                                      orc.gemm(full, At, Bt).view(np.uint32))
+        assert np.any(orc.gemm(variant, A, B) != orc.gemm(full, A, B))
+        K = A.shape[1]
+        z = A.astype(np.float64) @ B.astype(np.float64)
+        zh = np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64))
+        bnd = (3 * 2.0 ** -8 if min(pa, pb) == 1 else 3 * 2.0 ** -16) + 2 * K * U
+        assert np.all(np.abs(orc.gemm(variant, A, B) - z) <= bnd * zh)
