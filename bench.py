@@ -65,6 +65,8 @@ def parse():
                     help="only the timed step, roofline and CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--full-krylov", action="store_true",
+                    help="also run GMRES-IR at n = 16384, kappa = 1e12 (a Krylov space of ~n, minutes)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 1 GiB device-to-device copy (calibration "
                          "of the HBM byte counters) followed by one x6 GEMM, no timing")
@@ -336,7 +338,7 @@ def main():
 
         # LU + IR solves
         try:
-            extras["solves"] = bench_solves(torch, bfx, workloads, dev, stream)
+            extras["solves"] = bench_solves(torch, bfx, workloads, dev, stream, full_krylov=args.full_krylov)
         except Exception as e:  # report, do not hide
             extras["solves"] = {"error": repr(e)}
         log(f"[bench] solves {extras['solves']}")
@@ -394,9 +396,11 @@ def eta_check(torch, A, b, x):
     return float((r.abs().max() / den).item())
 
 
-def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
+def bench_solves(torch, bfx, workloads, dev, stream, n=16384, full_krylov=False):
     """One n x n system per kappa: LU (bf16x6 trailing updates) + LU-IR, and
-    for kappa >= 1e8 also GMRES-IR (bounded budget at 1e12, status reported)."""
+    for kappa >= 1e8 GMRES-IR with a Krylov space large enough to converge
+    (kappa = 1e12 needs about n GMRES steps: run at n = 16384 only with
+    full_krylov, else at n = 4096).  eta is recomputed in FP64 from x."""
     res = {}
     for kappa in (1e1, 1e4, 1e8, 1e12):
         t0 = time.perf_counter()
@@ -415,27 +419,59 @@ def bench_solves(torch, bfx, workloads, dev, stream, n=16384):
         row = {"lu_ms": round(t_lu * 1e3, 2), "lu_tflops_fp32eq": round(2 / 3 * n ** 3 / t_lu / 1e12, 2),
                "info": int(info.item()),
                "lu_ir": {"ms": round(t_ir * 1e3, 2), "iters": r["iters"], "status": r["status"],
-                         "eta": r["eta"], "solves_per_s": round(1.0 / (t_lu + t_ir), 3)}}
-        if kappa >= 1e8:
-            budget = dict(max_iter=2, restart=120) if kappa >= 1e12 else dict(max_iter=4, restart=120)
+                         "eta": r["eta"], "eta_recomputed": eta_check(torch, A, b, x),
+                         "solves_per_s": round(1.0 / (t_lu + t_ir), 3)}}
+        del x
+        if kappa >= 1e8 and (kappa < 1e12 or full_krylov):
+            budget = dict(max_iter=3, restart=n if kappa >= 1e12 else 4096)
+            log(f"[bench] n={n} kappa={kappa:g}: GMRES-IR {budget}")
             t0 = time.perf_counter()
             xg, g = bfx.gmres_ir_solve(A, LU, ipiv, b, **budget)
             torch.cuda.synchronize()
             t_g = time.perf_counter() - t0
             row["gmres_ir"] = {"ms": round(t_g * 1e3, 2), "iters": g["iters"], "inner": g["inner"],
-                               "status": g["status"], "eta": g["eta"], "budget": budget,
-                               "solves_per_s": round(1.0 / (t_lu + t_g), 3)}
+                               "status": g["status"], "eta": g["eta"],
+                               "eta_recomputed": eta_check(torch, A, b, xg), "budget": budget,
+                               "ms_per_gmres_step": round(t_g * 1e3 / max(g["inner"], 1), 3),
+                               "solves_per_s": round(1.0 / (t_lu + t_g), 4)}
             del xg
         res[f"n{n}_kappa{kappa:g}"] = row
         log(f"[bench] n={n} kappa={kappa:g}: {row}")
-        del A, b, LU, x
+        del A, b, LU
+        torch.cuda.empty_cache()
+    if not full_krylov:
+        # kappa = 1e12: GMRES-IR with a full Krylov space at n = 4096
+        m = 4096
+        A, b = workloads.conditioned_system_torch(m, 1e12, 7, dev)
+        LU = A.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ipiv, info = bfx.lu_factor(LU, 6)
+        torch.cuda.synchronize()
+        t_lu = time.perf_counter() - t0
+        budget = dict(max_iter=3, restart=m)
+        t0 = time.perf_counter()
+        xg, g = bfx.gmres_ir_solve(A, LU, ipiv, b, **budget)
+        torch.cuda.synchronize()
+        t_g = time.perf_counter() - t0
+        res[f"n{m}_kappa1e+12"] = {
+            "lu_ms": round(t_lu * 1e3, 2), "info": int(info.item()),
+            "gmres_ir": {"ms": round(t_g * 1e3, 2), "iters": g["iters"], "inner": g["inner"],
+                         "status": g["status"], "eta": g["eta"],
+                         "eta_recomputed": eta_check(torch, A, b, xg), "budget": budget,
+                         "ms_per_gmres_step": round(t_g * 1e3 / max(g["inner"], 1), 3),
+                         "solves_per_s": round(1.0 / (t_lu + t_g), 4)}}
+        log(f"[bench] n={m} kappa=1e12: {res[f'n{m}_kappa1e+12']}")
+        del A, b, LU, xg
         torch.cuda.empty_cache()
     return res
 
 
 def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512):
     """512 systems, n uniform in [64, 1024], one persistent launch of LU + IR
-    per kappa; one launch per problem timed on a 64-system subset at 1e4."""
+    per kappa (GMRES-IR with a full Krylov space for the systems LU-IR leaves
+    unconverged); one launch per problem timed on a 64-system subset at 1e4.
+    eta is recomputed in FP64 from every x."""
     out = {}
     for kappa in (1e1, 1e4, 1e8, 1e12):
         t0 = time.perf_counter()
@@ -448,10 +484,15 @@ def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512):
         res = plan.results()
         ms, _ = time_launches(torch, plan.launch, 3, stream)
         conv = sum(1 for r in res if r["status"] == 0)
+        etas = [eta_check(torch, A, b, x) for (A, b, x) in probs]
         row = {"ms": round(ms, 3), "solves_per_s": round(count / (ms * 1e-3), 1),
                "converged": conv, "count": count,
-               "max_eta": max(r["eta"] for r in res),
+               "max_eta": max(r["eta"] for r in res), "max_eta_recomputed": max(etas),
+               "converged_recomputed": sum(1 for e in etas if e <= 1e-14),
                "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+               "gmres_used": sum(1 for r in res if r["inner"] > 0),
+               "mean_gmres_steps_when_used": round(float(np.mean([r["inner"] for r in res if r["inner"] > 0]
+                                                                 or [0])), 1),
                "lu_flop_fp32eq": float(sum(2.0 / 3.0 * int(n) ** 3 for n in sizes))}
         plan.close()
         if kappa == 1e4:

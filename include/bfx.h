@@ -72,6 +72,14 @@ int bfx_split_f32(const float *a, int64_t n, int nterms, uint16_t *b0,
 /*   8 -> Z0 + (Z1 + (Z2 + Z3))  (bins 0-3, eight products)                 */
 /*   9 -> Z0 + (Z1 + (Z2 + (Z3 + Z4)))  (all nine products)                  */
 /*   1 -> Z0 (one term each)                                                 */
+/* Per-operand split counts (Sec. II-G, a different number of terms per      */
+/* operand): variant 10 * pa + pb in {12, 13, 21, 23, 31, 32} takes pa terms */
+/* of A and pb of B and the products a_i b_j with i < pa, j < pb, i + j <= 2 */
+/* (bins 0-2; e.g. 23 = a0 b0; a0 b1, a1 b0; a0 b2, a1 b1: five products).   */
+/* They run on the general engine (in-kernel split) or, with the workspace  */
+/* of bfx_gemm_ws_size, on pre-split operands; accuracy as variant 1 when    */
+/* min(pa, pb) = 1 and as variant 3 when it is 2, plus what the dropped      */
+/* terms of the operand with more terms contribute.                          */
 /* The products of bins 1.. accumulate in one FP32 sum, smallest bin first;  */
 /* Z0 in another; X = Z0 + that sum.                                         */
 /* beta == 0: C is not read (it may hold NaN).  lda >= max(1,K),             */
@@ -84,7 +92,8 @@ int bfx_split_f32(const float *a, int64_t n, int nterms, uint16_t *b0,
 /* the products run on the planes (bfx_gemm_blocks); with a smaller one the  */
 /* split happens inside the GEMM kernel.  Both give the same bits.           */
 /* Accuracy: |C - alpha A B| <= 2K 2^-24 |alpha| |A||B| componentwise for    */
-/* variants 6-9 (K >= 8), plus 3*2^-16 |alpha||A||B| for variant 3.        */
+/* variants 6-9 (K >= 8), plus 3*2^-16 |alpha||A||B| for variant 3 and       */
+/* 3*2^-8 |alpha||A||B| for variant 1.                                       */
 /* Errors: -1 variant, -2/-3/-4 negative sizes, -6/-8/-11 NULL operands,     */
 /* -7/-9/-12 leading dimensions, -14 workspace too small (BFX_E_WORKSPACE is */
 /* not used for this case so the argument is named).                         */
@@ -92,6 +101,19 @@ int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alpha,
              const float *A, int64_t lda, const float *B, int64_t ldb,
              float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
              void *stream);
+
+/* bfx_gemm with options.  flags: 0 or BFX_GEMM_FP64_SUM, the "d" option of  */
+/* Sec. IV-A: the final sum X = Z0 + (bins 1..) and the alpha/beta           */
+/* combination are formed in FP64 and rounded to FP32 once.  The two FP32   */
+/* accumulators are added exactly in FP64, so with alpha = 1 and beta = 0   */
+/* the result has the bits of bfx_gemm; otherwise it avoids the rounding of */
+/* X and of beta C.  Errors as bfx_gemm, and -2 for unknown flags (the       */
+/* negative-size codes of M, N, K stay -2, -3, -4 after the flags check).    */
+#define BFX_GEMM_FP64_SUM 1
+int bfx_gemm_ex(int variant, int flags, int64_t M, int64_t N, int64_t K,
+                float alpha, const float *A, int64_t lda, const float *B,
+                int64_t ldb, float beta, float *C, int64_t ldc, void *ws,
+                size_t ws_bytes, void *stream);
 
 /* Workspace bytes bfx_gemm uses for this shape: the split-K partial sums,  */
 /* or the pre-split planes of both operands; 0 when it needs neither.        */
@@ -138,7 +160,8 @@ size_t bfx_split_blocks_size(int nterms, int64_t R, int64_t K);
 /* Split one FP32 operand into that layout, exactly (bfx_split_f32's terms).  */
 /* trans = 0: X is R x K row-major (the A operand, R = M), ld >= max(1,K);    */
 /* trans = 1: X is K x R row-major (the B operand, R = N), ld >= max(1,R).    */
-/* nterms: 1, 2 or 3 (variants 1, 3 and 6-9 read 1, 2 and 3 terms).          */
+/* nterms: 1, 2 or 3 (variants 1, 3 and 6-9 read 1, 2 and 3 terms; the     */
+/* per-operand variants 10 pa + pb read max(pa, pb) terms of both operands). */
 /* out: device, 16-byte aligned, out_bytes >= bfx_split_blocks_size.          */
 /* Errors: -1 nterms, -2 trans, -3 R < 0, -4 K < 0 or K, R too large for the  */
 /* 32-bit block offsets (ceil(K/32) * 8192 >= 2^31), -5 X NULL, -6 ld,        */
@@ -149,7 +172,8 @@ int bfx_split_blocks(int nterms, int trans, int64_t R, int64_t K, const float *X
 
 /* C = alpha * (A x B) + beta * C from pre-split operands: Ab from            */
 /* bfx_split_blocks(P, 0, M, K, A, ...), Bb from bfx_split_blocks(P, 1, N, K,  */
-/* B, ...), P = 1, 2, 3 for variant 1, 3, 6-9.  Same variants, accumulation   */
+/* B, ...), P = 1, 2, 3 for variant 1, 3, 6-9, P = max(pa, pb) for variant   */
+/* 10 pa + pb (the kernel reads P planes of both).  Same variants, accumulation */
 /* order, accuracy and beta rule as bfx_gemm (bitwise equal results).  Ab, Bb  */
 /* device, 16-byte aligned, read only; C device, ldc >= max(1,N).  One        */
 /* 128 x 128 output tile per workgroup, no workspace.                         */

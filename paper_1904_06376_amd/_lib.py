@@ -70,6 +70,8 @@ SIGNATURES = {
     "bfx_split_f32": ([c_vp, c_i64, c_int, c_vp, c_vp, c_vp, c_vp], c_int),
     "bfx_gemm": ([c_int, c_i64, c_i64, c_i64, c_f32, c_vp, c_i64, c_vp, c_i64,
                   c_f32, c_vp, c_i64, c_vp, c_size, c_vp], c_int),
+    "bfx_gemm_ex": ([c_int, c_int, c_i64, c_i64, c_i64, c_f32, c_vp, c_i64, c_vp, c_i64,
+                     c_f32, c_vp, c_i64, c_vp, c_size, c_vp], c_int),
     "bfx_gemm_ws_size": ([c_int, c_i64, c_i64, c_i64], c_size),
     "bfx_gemm_noalloc": ([c_int, c_i64, c_i64, c_i64, c_f32, c_vp, c_i64, c_vp, c_i64,
                           c_f32, c_vp, c_i64, c_vp], c_int),

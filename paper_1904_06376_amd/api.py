@@ -56,9 +56,15 @@ def gemm_ws_size(variant: int, M: int, N: int, K: int) -> int:
     return lib.bfx_gemm_ws_size(variant, M, N, K)
 
 
+FP64_SUM = 1   # bfx_gemm_ex flag: the "d" option (final sum and epilogue in FP64)
+
+
 def gemm(variant: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
-         alpha: float = 1.0, beta: float = 0.0, ws: torch.Tensor | None = None):
-    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,7,8,9}.
+         alpha: float = 1.0, beta: float = 0.0, ws: torch.Tensor | None = None,
+         fp64_sum: bool = False):
+    """Split-BF16 GEMM C = alpha*(A x B) + beta*C with `variant` in {1,3,6,7,8,9}
+    or a per-operand split count 10*pa + pb in {12,13,21,23,31,32}; fp64_sum
+    selects the "d" option.
 
     `ws`: optional uint8 device tensor of at least gemm_ws_size(...) bytes,
     allocated here when missing or too small; it holds split-K partial sums,
@@ -76,10 +82,11 @@ def gemm(variant: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None 
     need = gemm_ws_size(variant, M, N, K)
     if ws is None or ws.numel() < need:
         ws = _ws(need, A.device)
-    check(lib.bfx_gemm(variant, M, N, K, alpha, A.data_ptr(), _rows(A, "A"),
-                       B.data_ptr(), _rows(B, "B"), beta, C.data_ptr(), _rows(C, "C"),
-                       ws.data_ptr() if ws is not None else None, need, _stream()),
-          "bfx_gemm")
+    check(lib.bfx_gemm_ex(variant, FP64_SUM if fp64_sum else 0, M, N, K, alpha, A.data_ptr(),
+                          _rows(A, "A"), B.data_ptr(), _rows(B, "B"), beta, C.data_ptr(),
+                          _rows(C, "C"), ws.data_ptr() if ws is not None else None, need,
+                          _stream()),
+          "bfx_gemm_ex")
     return C
 
 
@@ -99,10 +106,22 @@ def split_blocks(X: torch.Tensor, nterms: int, trans: bool = False) -> torch.Ten
     return out
 
 
+def planes(variant: int) -> int:
+    """BF16 terms of each operand that `variant` reads (bfx_split_blocks' nterms)."""
+    if variant >= 10:
+        return max(divmod(variant, 10))
+    return {1: 1, 3: 2}.get(variant, 3)
+
+
 def gemm_blocks(variant: int, M: int, N: int, K: int, Ab: torch.Tensor, Bb: torch.Tensor,
                 C: torch.Tensor | None = None, alpha: float = 1.0, beta: float = 0.0,
                 device=None):
-    """C = alpha*(A x B) + beta*C from operands pre-split by split_blocks."""
+    """C = alpha*(A x B) + beta*C from operands pre-split by split_blocks (with
+    planes(variant) terms each: the kernel reads that many planes of both)."""
+    P = planes(variant)
+    if (Ab.numel() * Ab.element_size() < lib.bfx_split_blocks_size(P, M, K)
+            or Bb.numel() * Bb.element_size() < lib.bfx_split_blocks_size(P, N, K)):
+        raise ValueError(f"variant {variant} reads {P} planes of each operand: split them with nterms={P}")
     if C is None:
         C = torch.empty((M, N), dtype=torch.float32, device=device or Ab.device)
         beta = 0.0

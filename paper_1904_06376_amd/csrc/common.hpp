@@ -144,7 +144,9 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                 const float *A, int64_t lda, const float *B, int64_t ldb,
                 float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
-                hipStream_t stream);
+                hipStream_t stream, int flags = 0);
+// 1, 3, 6, 7, 8, 9 and the per-operand split counts 12, 13, 21, 23, 31, 32.
+bool variant_valid(int variant);
 size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K);
 
 }  // namespace bfx

@@ -261,7 +261,7 @@ splitk_group_kernel(const float *__restrict__ partial, int splits, int64_t MN,
 
 __global__ void __launch_bounds__(256)
 splitk_final_kernel(const float *__restrict__ src, int count, int64_t M, int64_t N,
-                    float alpha, float beta, float *C, int64_t ldc) {
+                    float alpha, float beta, float *C, int64_t ldc, int fp64_sum) {
     const int64_t MN = M * N;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= MN) return;
@@ -271,9 +271,14 @@ splitk_final_kernel(const float *__restrict__ src, int count, int64_t M, int64_t
         h += src[(int64_t)(2 * s) * MN + e];
         l += src[(int64_t)(2 * s + 1) * MN + e];
     }
-    const float X = h + l;
     const int64_t row = e / N, col = e % N;
     float *c = C + row * ldc + col;
+    if (fp64_sum) {
+        const double X = (double)h + (double)l;
+        *c = (beta == 0.0f) ? (float)((double)alpha * X) : (float)fma((double)alpha, X, (double)beta * (double)*c);
+        return;
+    }
+    const float X = h + l;
     *c = (beta == 0.0f) ? alpha * X : fmaf(alpha, X, beta * *c);
 }
 
@@ -343,7 +348,15 @@ static const bool g_no_planes = [] {
     return e && e[0] == '0';
 }();
 
-static int prods_p(int variant) { return variant == 1 ? 1 : variant == 3 ? 2 : 3; }
+bool variant_valid(int v) {
+    return v == 1 || v == 3 || v == 6 || v == 7 || v == 8 || v == 9 || v == 12 || v == 13 || v == 21 ||
+           v == 23 || v == 31 || v == 32;
+}
+
+static int prods_p(int variant) {
+    if (variant >= 10) return (variant / 10 > variant % 10) ? variant / 10 : variant % 10;
+    return variant == 1 ? 1 : variant == 3 ? 2 : 3;
+}
 
 static bool planes_wanted(int64_t M, int64_t N, int64_t K) {
     const int64_t KS = ceil_div(K, BK);
@@ -425,6 +438,12 @@ static int gemm_blocks_dispatch(int variant, const GemmParams &p, const uint16_t
         case 7: return launch_gemm_blocks<7>(p, Ab, Bb, s);
         case 8: return launch_gemm_blocks<8>(p, Ab, Bb, s);
         case 9: return launch_gemm_blocks<9>(p, Ab, Bb, s);
+        case 12: return launch_gemm_blocks<12>(p, Ab, Bb, s);
+        case 13: return launch_gemm_blocks<13>(p, Ab, Bb, s);
+        case 21: return launch_gemm_blocks<21>(p, Ab, Bb, s);
+        case 23: return launch_gemm_blocks<23>(p, Ab, Bb, s);
+        case 31: return launch_gemm_blocks<31>(p, Ab, Bb, s);
+        case 32: return launch_gemm_blocks<32>(p, Ab, Bb, s);
         default: return -1;
     }
 }
@@ -539,10 +558,18 @@ static int dispatch_variant(GemmParams &p, int BM, int BN, hipStream_t s) {
     return launch_tiles<V, 128, 128, 2, 2>(p, s);
 }
 
+// Per-operand split counts: the general engine (and the pre-split products
+// when the workspace holds the planes).
+template <int V>
+static int dispatch_general(GemmParams &p, int BM, hipStream_t s) {
+    if (BM == 64) return launch_tiles<V, 64, 64, 2, 2>(p, s);
+    return launch_tiles<V, 128, 128, 2, 2>(p, s);
+}
+
 int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                 const float *A, int64_t lda, const float *B, int64_t ldb,
                 float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
-                hipStream_t stream) {
+                hipStream_t stream, int flags) {
     if (M == 0 || N == 0) return BFX_OK;
     int BM, BN;
     tile_for(M, N, BM, BN);
@@ -556,6 +583,7 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
     p.partial = (float *)ws;
     p.vecA = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
     p.vecB = ((uintptr_t)B % 16 == 0) && (ldb % 4 == 0);
+    p.fp64_sum = (flags & BFX_GEMM_FP64_SUM) ? 1 : 0;
     const int groups = split_groups(p.splits);
     if (p.splits > 1 && (size_t)(p.splits + groups) * 2 * M * N * sizeof(float) > ws_bytes)
         return -14;
@@ -571,6 +599,12 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
         case 7: rc = dispatch_variant<7>(p, BM, BN, stream); break;
         case 8: rc = dispatch_variant<8>(p, BM, BN, stream); break;
         case 9: rc = dispatch_variant<9>(p, BM, BN, stream); break;
+        case 12: rc = dispatch_general<12>(p, BM, stream); break;
+        case 13: rc = dispatch_general<13>(p, BM, stream); break;
+        case 21: rc = dispatch_general<21>(p, BM, stream); break;
+        case 23: rc = dispatch_general<23>(p, BM, stream); break;
+        case 31: rc = dispatch_general<31>(p, BM, stream); break;
+        case 32: rc = dispatch_general<32>(p, BM, stream); break;
         default: return -1;
     }
     if (rc != BFX_OK || p.splits <= 1) return rc;
@@ -586,7 +620,7 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
         count = groups;
     }
     hipLaunchKernelGGL(splitk_final_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       src, count, M, N, alpha, beta, C, ldc);
+                       src, count, M, N, alpha, beta, C, ldc, p.fp64_sum);
     BFX_LAUNCH_CHECK("splitk_final_kernel launch");
     return BFX_OK;
 }
@@ -602,7 +636,15 @@ extern "C" int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alph
                         const float *A, int64_t lda, const float *B, int64_t ldb,
                         float beta, float *C, int64_t ldc, void *ws,
                         size_t ws_bytes, void *stream) {
-    if (variant != 1 && variant != 3 && variant != 6 && variant != 7 && variant != 8 && variant != 9) return -1;
+    return bfx_gemm_ex(variant, 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream);
+}
+
+extern "C" int bfx_gemm_ex(int variant, int flags, int64_t M, int64_t N, int64_t K, float alpha,
+                           const float *A, int64_t lda, const float *B, int64_t ldb,
+                           float beta, float *C, int64_t ldc, void *ws,
+                           size_t ws_bytes, void *stream) {
+    if (!bfx::variant_valid(variant)) return -1;
+    if (flags & ~BFX_GEMM_FP64_SUM) return -2;
     if (M < 0) return -2;
     if (N < 0) return -3;
     if (K < 0) return -4;
@@ -614,7 +656,7 @@ extern "C" int bfx_gemm(int variant, int64_t M, int64_t N, int64_t K, float alph
     if (K > 0 && !B) return -8;
     if (!C) return -11;
     return bfx::gemm_launch(variant, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws,
-                            ws_bytes, (hipStream_t)stream);
+                            ws_bytes, (hipStream_t)stream, flags);
 }
 
 extern "C" size_t bfx_split_blocks_size(int nterms, int64_t R, int64_t K) {
@@ -642,7 +684,7 @@ extern "C" int bfx_split_blocks(int nterms, int trans, int64_t R, int64_t K, con
 extern "C" int bfx_gemm_blocks(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                                const uint16_t *Ab, const uint16_t *Bb, float beta, float *C,
                                int64_t ldc, void *stream) {
-    if (variant != 1 && variant != 3 && variant != 6 && variant != 7 && variant != 8 && variant != 9) return -1;
+    if (!bfx::variant_valid(variant)) return -1;
     if (M < 0) return -2;
     if (N < 0) return -3;
     if (K < 0) return -4;
@@ -715,7 +757,7 @@ extern "C" size_t bfx_gemm_noalloc_scratch_bytes(void) { return bfx::NOALLOC_SCR
 extern "C" int bfx_gemm_noalloc(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                                 const float *A, int64_t lda, const float *B, int64_t ldb,
                                 float beta, float *C, int64_t ldc, void *stream) {
-    if (variant != 1 && variant != 3 && variant != 6 && variant != 7 && variant != 8 && variant != 9) return -1;
+    if (!bfx::variant_valid(variant)) return -1;
     if (M < 0) return -2;
     if (N < 0) return -3;
     if (K < 0) return -4;

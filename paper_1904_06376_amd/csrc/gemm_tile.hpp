@@ -51,6 +51,34 @@ template <> struct Prods<9> {
     static constexpr int ai[8] = {2, 2, 1, 2, 1, 0, 1, 0};
     static constexpr int bj[8] = {2, 1, 2, 0, 1, 2, 0, 1};
 };
+// Per-operand split counts (Sec. II-G): variant 10 pa + pb takes pa BF16
+// terms of A and pb of B and the products a_i b_j, i < pa, j < pb,
+// i + j <= 2.  P = max(pa, pb) planes of both operands are formed; the planes
+// of the operand with fewer terms beyond its count are not used.
+template <> struct Prods<12> {
+    static constexpr int P = 2, n = 1;
+    static constexpr int ai[1] = {0}, bj[1] = {1};
+};
+template <> struct Prods<21> {
+    static constexpr int P = 2, n = 1;
+    static constexpr int ai[1] = {1}, bj[1] = {0};
+};
+template <> struct Prods<13> {
+    static constexpr int P = 3, n = 2;
+    static constexpr int ai[2] = {0, 0}, bj[2] = {2, 1};
+};
+template <> struct Prods<31> {
+    static constexpr int P = 3, n = 2;
+    static constexpr int ai[2] = {2, 1}, bj[2] = {0, 0};
+};
+template <> struct Prods<23> {
+    static constexpr int P = 3, n = 4;
+    static constexpr int ai[4] = {1, 0, 1, 0}, bj[4] = {1, 2, 0, 1};
+};
+template <> struct Prods<32> {
+    static constexpr int P = 3, n = 4;
+    static constexpr int ai[4] = {2, 1, 1, 0}, bj[4] = {0, 1, 0, 1};
+};
 
 struct GemmParams {
     int64_t M, N, K;
@@ -65,6 +93,7 @@ struct GemmParams {
     int splits;           // 1 = direct epilogue
     float *partial;       // [splits][2][M][N] when splits > 1
     int vecA, vecB;       // 16-byte loads allowed
+    int fp64_sum = 0;     // X = hi + lo and the alpha/beta epilogue in FP64, one rounding
 };
 
 constexpr int BK = 32;
@@ -136,7 +165,9 @@ __device__ __forceinline__ int swz_off(int n, int k) {
 // of v_mfma_f32_16x16x32_bf16: lane holds column lane%16, rows 4*(lane/16) +
 // 0..3 of each 16 x 16 tile.  X = hi + lo (the largest bin added last), then
 // C = alpha X (beta == 0: C not read) or fma(alpha, X, beta C), or, for
-// split-K, the hi and lo partial sums.  With beta != 0 the C values of CB
+// split-K, the hi and lo partial sums.  With fp64_sum (the "d" option of
+// Sec. IV-A) X and the alpha/beta combination are formed in FP64 and rounded
+// once.  With beta != 0 the C values of CB
 // 16-row bands are all loaded before their first store, so those loads are
 // in flight together instead of each waiting for the previous store.
 template <int TM, int TN, int CB = TM>
@@ -170,7 +201,9 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32
                 for (int e = 0; e < 4; ++e) {
                     const int64_t row = row_of(i, e), col = col_of(j);
                     if (row >= p.M || col >= p.N) continue;
-                    p.C[row * p.ldc + col] = p.alpha * (hi[i][j][e] + lo[i][j][e]);
+                    p.C[row * p.ldc + col] =
+                        p.fp64_sum ? (float)((double)p.alpha * ((double)hi[i][j][e] + (double)lo[i][j][e]))
+                                   : p.alpha * (hi[i][j][e] + lo[i][j][e]);
                 }
         return;
     }
@@ -198,7 +231,10 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32
                     const int64_t row = row_of(i0 + ii, e), col = col_of(j);
                     if (row >= p.M || col >= p.N) continue;
                     p.C[row * p.ldc + col] =
-                        fmaf(p.alpha, hi[i0 + ii][j][e] + lo[i0 + ii][j][e], p.beta * cv[ii][j][e]);
+                        p.fp64_sum
+                            ? (float)fma((double)p.alpha, (double)hi[i0 + ii][j][e] + (double)lo[i0 + ii][j][e],
+                                         (double)p.beta * (double)cv[ii][j][e])
+                            : fmaf(p.alpha, hi[i0 + ii][j][e] + lo[i0 + ii][j][e], p.beta * cv[ii][j][e]);
                 }
     }
 }

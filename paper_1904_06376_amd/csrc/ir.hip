@@ -25,11 +25,12 @@
 //                    the bit pattern of a non-negative double (order-free);
 //   trsv_kernel      blocked triangular solve without a global barrier: each
 //                    workgroup takes the next block row from a ticket counter,
-//                    waits (bounded) on the completion flags of the blocks it
-//                    depends on, adds their contribution, solves its 128 x 128
-//                    diagonal block in one wave and publishes its flag.  Flags
-//                    hold the number of the launch that set them, so that no
-//                    launch has to clear them for the next;
+//                    adds the contributions of the blocks it depends on as
+//                    their solution values arrive, solves its 128 x 128
+//                    diagonal block in one wave and publishes the values as
+//                    64-bit words tagged with the number of the launch, so
+//                    that a reader needs neither a flag nor a fence and no
+//                    launch has to clear the words for the next;
 //   perm_kernel      the row permutation of ipiv, composed once per solve
 //                    (every position evaluated in parallel);
 //   GMRES            matvec_perm_kernel (P A v, materialising the basis
@@ -74,7 +75,7 @@ struct IrWs {
     int32_t *perm;
     float *w;
     double *r;
-    int32_t *flags;   // [nblk]
+    uint64_t *xch;    // [2n] tagged solution words exchanged between workgroups
     uint32_t *ticket; // [4]
     unsigned long long *scal;  // [S_NSCAL]
     IrCtrl *ctrl;
@@ -89,11 +90,10 @@ size_t ir_ws_layout(IrWs *w, void *base, int64_t n) {
         return o;
     };
     const int64_t nn = n > 0 ? n : 1;
-    const int64_t nb = ceil_div(nn, TB);
     const size_t o_perm = take(sizeof(int32_t) * nn);
     const size_t o_w = take(sizeof(float) * nn);
     const size_t o_r = take(sizeof(double) * nn);
-    const size_t o_f = take(sizeof(int32_t) * nb);
+    const size_t o_f = take(sizeof(uint64_t) * 2 * nn);
     const size_t o_t = take(sizeof(uint32_t) * 4);
     const size_t o_s = take(sizeof(unsigned long long) * S_NSCAL);
     const size_t o_c = take(sizeof(IrCtrl));
@@ -103,7 +103,7 @@ size_t ir_ws_layout(IrWs *w, void *base, int64_t n) {
         w->perm = (int32_t *)(b + o_perm);
         w->w = (float *)(b + o_w);
         w->r = (double *)(b + o_r);
-        w->flags = (int32_t *)(b + o_f);
+        w->xch = (uint64_t *)(b + o_f);
         w->ticket = (uint32_t *)(b + o_t);
         w->scal = (unsigned long long *)(b + o_s);
         w->ctrl = (IrCtrl *)(b + o_c);
@@ -126,11 +126,13 @@ __device__ __forceinline__ void atomic_max_abs(unsigned long long *dst, double v
 
 __device__ __forceinline__ double bits_double(unsigned long long u) { return __longlong_as_double((long long)u); }
 
-// Start of a solve: clear the block flags, tickets, reduction scalars and the
-// control block; the caller's result says "not converged" until a check runs.
+// Start of a solve: clear the exchange words, tickets, reduction scalars and
+// the control block; the caller's result says "not converged" until a check
+// runs.
 __global__ void __launch_bounds__(256)
-ir_begin_kernel(IrCtrl *c, unsigned long long *scal, uint32_t *ticket, int32_t *flags, int64_t nflags) {
-    for (int64_t i = threadIdx.x; i < nflags; i += 256) flags[i] = 0;
+ir_begin_kernel(IrCtrl *c, unsigned long long *scal, uint32_t *ticket, uint64_t *xch, int64_t nx) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nx; i += (int64_t)gridDim.x * 256) xch[i] = 0ull;
+    if (blockIdx.x != 0) return;
     if (threadIdx.x < 4) ticket[threadIdx.x] = 0u;
     if (threadIdx.x < S_NSCAL) scal[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) {
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(256) zero_i32(int32_t *p, int64_t n) {
 // computed in parallel instead of replaying the swaps one after another.
 __global__ void __launch_bounds__(256) perm_kernel(const int32_t *ipiv, int64_t n, int32_t *perm,
                                                    int use_lds) {
-    extern __shared__ int32_t sp[];
+    extern __shared__ __align__(16) int32_t sp[];
     const int32_t *iv = ipiv;
     if (use_lds) {
         for (int64_t i = threadIdx.x; i < n; i += 256) sp[i] = ipiv[i];
@@ -165,9 +167,29 @@ __global__ void __launch_bounds__(256) perm_kernel(const int32_t *ipiv, int64_t 
     const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (pos >= n) return;
     int32_t p = (int32_t)pos;
-    for (int32_t i = (int32_t)n - 1; i >= 0; --i) {
-        const int32_t q = iv[i];
-        p = (p == i) ? q : ((p == q) ? i : p);
+    int32_t i = (int32_t)n - 1;
+    if (use_lds) {
+        // 16-byte LDS reads of four interchanges at a time, several in
+        // flight (every lane reads the same address: a broadcast)
+        for (; i >= 0 && (i & 3) != 3; --i) {
+            const int32_t q = iv[i];
+            p = (p == i) ? q : ((p == q) ? i : p);
+        }
+        const int4 *iv4 = reinterpret_cast<const int4 *>(sp);
+#pragma unroll 8
+        for (int32_t ch = (i + 1) / 4 - 1; ch >= 0; --ch) {
+            const int4 q = iv4[ch];
+            const int32_t b = 4 * ch;
+            p = (p == b + 3) ? q.w : ((p == q.w) ? b + 3 : p);
+            p = (p == b + 2) ? q.z : ((p == q.z) ? b + 2 : p);
+            p = (p == b + 1) ? q.y : ((p == q.y) ? b + 1 : p);
+            p = (p == b) ? q.x : ((p == q.x) ? b : p);
+        }
+    } else {
+        for (; i >= 0; --i) {
+            const int32_t q = iv[i];
+            p = (p == i) ? q : ((p == q) ? i : p);
+        }
     }
     perm[pos] = p;
 }
@@ -341,34 +363,69 @@ __device__ __forceinline__ double bcast_lane(double v, int l) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Solution values travel between workgroups as 64-bit words that carry the
+// number of the launch that wrote them (the epoch) in their upper half: one
+// word per FP32 value, two (high and low half) per FP64 value.  A word is
+// written and read whole, so a reader that sees its launch's epoch in every
+// word of a value has the value, without a flag, a fence or a second read.
+template <typename T> struct Xch;
+template <> struct Xch<float> {
+    static constexpr int W = 1;
+    __device__ static void put(uint64_t *x, int64_t i, float v, uint32_t tag) {
+        __hip_atomic_store(x + i, ((uint64_t)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static float value(const uint64_t *w) { return __uint_as_float((uint32_t)w[0]); }
+};
+template <> struct Xch<double> {
+    static constexpr int W = 2;
+    __device__ static void put(uint64_t *x, int64_t i, double v, uint32_t tag) {
+        const uint64_t u = (uint64_t)__double_as_longlong(v);
+        __hip_atomic_store(x + 2 * i, ((uint64_t)tag << 32) | (u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(x + 2 * i + 1, ((uint64_t)tag << 32) | (u & 0xffffffffull), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static double value(const uint64_t *w) {
+        return __longlong_as_double((long long)(((w[0] & 0xffffffffull) << 32) | (w[1] & 0xffffffffull)));
+    }
+};
+
 // Blocked triangular solve with the FP32 LU factors, in place on y; T is the
 // arithmetic and vector type (float for LU-IR, double for the GMRES
 // preconditioner).  lower = 1: unit lower L (forward); lower = 0: upper U
 // (backward, divides).  One workgroup per block row of TB = 128 rows, taken in
 // dependency order from a ticket counter.  Off-diagonal part: wave w owns rows
-// 16w .. 16w+15 of the block row; for every dependency block its 64 lanes
-// read 2 consecutive columns each (one coalesced 512-byte load per row) and
-// accumulate per row in column order, the 16 row sums being reduced across
-// the wave at the end.  The factor values of the next dependency are loaded
-// before waiting for it.  Diagonal block: one wave, lane l holding rows l and
-// l + 64, substitution in column order with the diagonal block in LDS.
+// 16w .. 16w+15 of the block row as 8 row pairs; for every dependency block
+// each half-wave reads one row of a pair with 16-byte loads (4 consecutive
+// columns per lane, 512 bytes per half-wave) and accumulates per row in
+// column order, the row sums being reduced across the half-wave at the end.
+// The factor values and exchange words of the next two dependencies are in
+// flight while the current one is used, which keeps enough bytes in flight
+// per workgroup for the dependency sweep to run ahead of the chain of block
+// solves.  A wave whose words of a block do not carry this launch's epoch
+// yet polls them again (bounded).  Diagonal block: one wave, lane l holding
+// rows l and l + 64, substitution in column order with the diagonal block in
+// LDS; the results go to y and, tagged, to the exchange words.
 //
-// `epoch` numbers the launches of one solve (1, 2, ...): a block's flag is set
-// to the epoch of the launch that solved it, launch e takes its tickets from
-// ticket[e % 3] and clears ticket[(e + 1) % 3] for the launch after it (the
-// launch before it, which used that counter, has completed in stream order).
+// `epoch` numbers the launches of one solve (1, 2, ...); launch e takes its
+// tickets from ticket[e % 3] and clears ticket[(e + 1) % 3] for the launch
+// after it (the launch before it, which used that counter, has completed in
+// stream order).  vec = 1: LU and ld allow 16-byte loads.
 template <typename T>
 __global__ void __launch_bounds__(512)
-trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32_t *ticket,
-            int32_t epoch, int32_t *err, const IrCtrl *c, int inner, int lower) {
+trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, uint64_t *xch, uint32_t *ticket,
+            int32_t epoch, int32_t *err, const IrCtrl *c, int inner, int lower, int vec) {
     extern __shared__ float Ld[];   // [TB][TB + 1] diagonal block
     __shared__ int s_blk;
-    __shared__ int64_t s_known;
     __shared__ T rhs[TB];
     constexpr int LDD = TB + 1;
+    constexpr int W = Xch<T>::W;
+    constexpr int NX = 4 * W;       // exchange words of a lane's 4 columns
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int half = lane >> 5, hl = lane & 31;
     if (blockIdx.x == 0 && t == 0) ticket[(epoch + 1) % 3] = 0u;
     if (stopped(c, inner)) return;
+    const uint32_t tag = (uint32_t)epoch;
     const int64_t nblk = ceil_div(n, TB);
     if (t == 0) s_blk = (int)atomicAdd(ticket + epoch % 3, 1u);
     __syncthreads();
@@ -381,74 +438,105 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
         Ld[i * LDD + cc] = (i < rows && cc < rows) ? LU[(r0 + i) * ld + r0 + cc] : 0.0f;
     }
     const int64_t nb_dep = lower ? blk : nblk - 1 - blk;
-    // rows 16 wave .. 16 wave + 15 of this block row (clamped: rows past the
-    // end of the matrix re-read the last row and are never stored)
-    const float *lrow[16];
+    // row 16 wave + 2 p + half of this block row (clamped: rows past the end
+    // of the matrix re-read the last row and are never stored)
+    const float *lrow[8];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int rr = 16 * wave + q;
-        lrow[q] = LU + (r0 + (rr < rows ? rr : rows - 1)) * ld;
+    for (int p = 0; p < 8; ++p) {
+        const int rr = 16 * wave + 2 * p + half;
+        lrow[p] = LU + (r0 + (rr < rows ? rr : rows - 1)) * ld;
     }
-    auto col0 = [&](int64_t d) { return (lower ? d : nblk - 1 - d) * TB + 2 * lane; };
-    float lc[16][2], ln[16][2];
-    auto load = [&](float (&dst)[16][2], int64_t col) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            dst[q][0] = (col < n) ? lrow[q][col] : 0.0f;
-            dst[q][1] = (col + 1 < n) ? lrow[q][col + 1] : 0.0f;
-        }
+    auto col0 = [&](int64_t d) { return (lower ? d : nblk - 1 - d) * TB + 4 * hl; };
+    struct Stage {
+        float4 l[8];
+        uint64_t x[NX];
     };
-    T acc[16];
+    auto load = [&](Stage &st, int64_t col) {
+        if (vec && col + 3 < n) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0;
-    if (nb_dep > 0) load(lc, col0(0));
-    int64_t known = 0;  // dependencies known complete
-    for (int64_t d = 0; d < nb_dep; ++d) {
-        const int64_t jb = lower ? d : nblk - 1 - d;
-        if (d + 1 < nb_dep) load(ln, col0(d + 1));
-        if (d >= known) {
-            // A block completes only after every block before it in this
-            // order, so one acquire of the furthest flag known set covers all
-            // earlier blocks; polls are relaxed.
-            if (t == 0) {
-                unsigned spins = 0;
-                while (__hip_atomic_load(flags + jb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                    if (++spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                int64_t e = d + 1;
-                while (e < nb_dep &&
-                       __hip_atomic_load(flags + (lower ? e : nblk - 1 - e), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) == epoch)
-                    ++e;
-                (void)__hip_atomic_load(flags + (lower ? e - 1 : nblk - e), __ATOMIC_ACQUIRE,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-                s_known = e;
+            for (int p = 0; p < 8; ++p) st.l[p] = *reinterpret_cast<const float4 *>(lrow[p] + col);
+        } else {
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                st.l[p].x = (col < n) ? lrow[p][col] : 0.0f;
+                st.l[p].y = (col + 1 < n) ? lrow[p][col + 1] : 0.0f;
+                st.l[p].z = (col + 2 < n) ? lrow[p][col + 2] : 0.0f;
+                st.l[p].w = (col + 3 < n) ? lrow[p][col + 3] : 0.0f;
             }
-            __syncthreads();
-            known = s_known;
-        }
-        const int64_t col = jb * TB + 2 * lane;
-        const T y0 = (col < n) ? y[col] : (T)0, y1 = (col + 1 < n) ? y[col + 1] : (T)0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            acc[q] = fma((T)lc[q][0], y0, acc[q]);
-            acc[q] = fma((T)lc[q][1], y1, acc[q]);
         }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) { lc[q][0] = ln[q][0]; lc[q][1] = ln[q][1]; }
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int h = 0; h < W; ++h)
+                st.x[q * W + h] = (col + q < n)
+                                      ? __hip_atomic_load(xch + (col + q) * W + h, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : ((uint64_t)tag << 32);
+    };
+    auto reload_x = [&](Stage &st, int64_t col) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int h = 0; h < W; ++h)
+                st.x[q * W + h] = (col + q < n)
+                                      ? __hip_atomic_load(xch + (col + q) * W + h, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : ((uint64_t)tag << 32);
+    };
+    auto present = [&](const Stage &st) {
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) ok = ok && (uint32_t)(st.x[i] >> 32) == tag;
+        return ok;
+    };
+    // this block's right-hand side, read before the sweep (it is not on the
+    // chain of block solves)
+    T yown = 0;
+    if (hl < 8) {
+        const int rr = 16 * wave + 2 * hl + half;
+        if (rr < rows) yown = y[r0 + rr];
+    }
+    T acc[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acc[p] = 0;
+    Stage s0, s1, s2;
+    if (nb_dep > 0) load(s0, col0(0));
+    if (nb_dep > 1) load(s1, col0(1));
+    for (int64_t d = 0; d < nb_dep; ++d) {
+        if (d + 2 < nb_dep) load(s2, col0(d + 2));
+        unsigned spins = 0;
+        while (!__all(present(s0))) {
+            // another workgroup's expired wait is checked every 256 polls
+            if ((++spins & 255u) == 0 &&
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                break;
+            if (spins > SPIN_LIMIT) { atomicExch(err, 1); break; }
+            __builtin_amdgcn_s_sleep(1);
+            reload_x(s0, col0(d));
+        }
+        const T y0 = Xch<T>::value(s0.x), y1 = Xch<T>::value(s0.x + W);
+        const T y2 = Xch<T>::value(s0.x + 2 * W), y3 = Xch<T>::value(s0.x + 3 * W);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            acc[p] = fma((T)s0.l[p].x, y0, acc[p]);
+            acc[p] = fma((T)s0.l[p].y, y1, acc[p]);
+            acc[p] = fma((T)s0.l[p].z, y2, acc[p]);
+            acc[p] = fma((T)s0.l[p].w, y3, acc[p]);
+        }
+        s0 = s1;
+        s1 = s2;
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
-    if (lane < 16) {
-        // lane q publishes row 16 wave + q (static register index via a select chain)
+    for (int p = 0; p < 8; ++p)
+        for (int off = 16; off > 0; off >>= 1) acc[p] += __shfl_xor(acc[p], off);
+    if (hl < 8) {
+        // lane hl of each half publishes row 16 wave + 2 hl + half (static
+        // register index via a select chain)
         T v = acc[0];
 #pragma unroll
-        for (int q = 1; q < 16; ++q) if (lane == q) v = acc[q];
-        const int rr = 16 * wave + lane;
-        if (rr < rows) rhs[rr] = y[r0 + rr] - v;
+        for (int p = 1; p < 8; ++p) if (hl == p) v = acc[p];
+        const int rr = 16 * wave + 2 * hl + half;
+        if (rr < rows) rhs[rr] = yown - v;
     }
     __syncthreads();
     if (t < 64) {
@@ -513,11 +601,14 @@ trsv_kernel(const float *LU, int64_t ld, int64_t n, T *y, int32_t *flags, uint32
                 for (int k = 0; k < 8; ++k) { a0[k] = b0[k]; a1[k] = b1[k]; }
             }
         }
-        if (lane < rows) y[r0 + lane] = v0;
-        if (lane + 64 < rows) y[r0 + 64 + lane] = v1;
-        __builtin_amdgcn_wave_barrier();
-        // the release covers wave 0's stores of y
-        if (t == 0) __hip_atomic_store(flags + blk, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane < rows) {
+            Xch<T>::put(xch, r0 + lane, v0, tag);
+            y[r0 + lane] = v0;
+        }
+        if (lane + 64 < rows) {
+            Xch<T>::put(xch, r0 + 64 + lane, v1, tag);
+            y[r0 + 64 + lane] = v1;
+        }
     }
 }
 
@@ -720,6 +811,7 @@ struct Solver {
 
     template <typename T>
     int trsv_pair(T *y, const IrCtrl *c, int inner) {
+        const int vec = ((uintptr_t)LU % 16 == 0) && (ldlu % 4 == 0);
         static bool attr = false;
         if (!attr) {
             BFX_HIP(hipFuncSetAttribute((const void *)trsv_kernel<T>,
@@ -730,7 +822,7 @@ struct Solver {
         for (int lower = 1; lower >= 0; --lower) {
             ++epoch;
             hipLaunchKernelGGL(trsv_kernel<T>, dim3((unsigned)nb), dim3(512), TRSV_LDS, s, LU, ldlu, n, y,
-                               w.flags, w.ticket, epoch, &w.ctrl->err, c, inner, lower);
+                               w.xch, w.ticket, epoch, &w.ctrl->err, c, inner, lower, vec);
             BFX_LAUNCH_CHECK("trsv_kernel");
         }
         return BFX_OK;
@@ -757,8 +849,8 @@ struct Solver {
     // x0 = (double) LUsolve32((float) b).
     int begin(const float *A, int64_t lda, const int32_t *ipiv, const double *b, double *x) {
         const unsigned g = grid_for(n);
-        hipLaunchKernelGGL(ir_begin_kernel, dim3(1), dim3(256), 0, s, w.ctrl, w.scal, w.ticket, w.flags,
-                           ceil_div(n, TB));
+        hipLaunchKernelGGL(ir_begin_kernel, dim3(grid_for(2 * n)), dim3(256), 0, s, w.ctrl, w.scal, w.ticket,
+                           w.xch, 2 * n);
         hipLaunchKernelGGL(mat_norm_kernel, dim3((unsigned)n), dim3(256), 0, s, A, lda, n, w.scal);
         hipLaunchKernelGGL(vec_absmax_kernel, dim3(g), dim3(256), 0, s, b, n, w.scal + S_NORMB,
                            (const IrCtrl *)nullptr);
@@ -802,8 +894,8 @@ extern "C" int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu, const 
     hipStream_t s = (hipStream_t)stream;
     bfx::Solver sv{n, LU, ldlu, {}, s};
     bfx::ir_ws_layout(&sv.w, ws, n);
-    hipLaunchKernelGGL(bfx::ir_begin_kernel, dim3(1), dim3(256), 0, s, sv.w.ctrl, sv.w.scal, sv.w.ticket,
-                       sv.w.flags, bfx::ceil_div(n, bfx::TB));
+    hipLaunchKernelGGL(bfx::ir_begin_kernel, dim3(bfx::grid_for(2 * n)), dim3(256), 0, s, sv.w.ctrl, sv.w.scal,
+                       sv.w.ticket, sv.w.xch, 2 * n);
     int rc = sv.compose_perm(ipiv);
     if (rc) return rc;
     hipLaunchKernelGGL(bfx::gather_f32, dim3(bfx::grid_for(n)), dim3(256), 0, s, rhs, sv.w.perm, sv.w.w, n);

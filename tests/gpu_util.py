@@ -22,6 +22,9 @@ def gemm_bound(variant, K):
     """Componentwise error bound relative to |A||B| (spec bounds; for K < 8
     the dropped-term allowance (513/512) 2^-23 is added)."""
     k = 2 * K + (8 if K < 8 else 0)
+    if variant >= 10:
+        # per-operand split counts 10 pa + pb: the weaker operand's count decides
+        variant = 1 if min(divmod(variant, 10)) == 1 else 3
     if variant >= 6:
         return k * U
     if variant == 3:

@@ -464,3 +464,92 @@ def test_gemm_x7_x8_errors_between_x3_and_x9(bfx):
     lo = min(err[v] for v in (6, 7, 8, 9))
     assert hi <= 1.25 * lo, err
     assert err[3] > 8 * hi, err
+
+
+PER_OPERAND = (12, 13, 21, 23, 31, 32)
+
+
+@pytest.mark.parametrize("variant", PER_OPERAND)
+@pytest.mark.parametrize("shape", [(200, 130, 77), (129, 257, 33), (256, 256, 256), (65, 64, 44),
+                                   (3, 5, 4096)])
+def test_gemm_per_operand_vs_oracle(bfx, orc, variant, shape):
+    """Per-operand split counts (Sec. II-G): every entry within the bound of the
+    weaker operand's count and within twice it of the oracle."""
+    M, N, K = shape
+    A = workloads.gauss_exp((M, K), 900 + M, sigma=2)
+    B = workloads.gauss_exp((K, N), 901 + N, sigma=2)
+    C = host(bfx.gemm(variant, dev(A), dev(B)))
+    _check_bound(variant, A, B, C, orc.gemm(variant, A, B))
+
+
+def _terms(orc, X, nterms):
+    planes = [orc.bf16_bits_to_f32(h).reshape(X.shape).astype(np.float64) for h in orc.split(X.ravel())]
+    return sum(planes[:nterms]).astype(np.float32)
+
+
+@pytest.mark.parametrize("variant", PER_OPERAND)
+def test_gemm_per_operand_equals_full_when_dropped_terms_vanish(bfx, orc, variant):
+    """With A holding no terms beyond its pa-th and B none beyond its pb-th, the
+    dropped products are exact zeros: the GPU result has the bits of the full
+    variant (x6, or x3 when both counts are at most 2) on the same engine."""
+    pa, pb = divmod(variant, 10)
+    full = 3 if max(pa, pb) <= 2 else 6
+    A = _terms(orc, workloads.normal((200, 77), 910), pa)
+    B = _terms(orc, workloads.normal((77, 130), 911), pb)
+    tA, tB = dev(A), dev(B)
+    np.testing.assert_array_equal(host(bfx.gemm(variant, tA, tB)).view(np.uint32),
+                                  host(bfx.gemm(full, tA, tB)).view(np.uint32))
+
+
+@pytest.mark.parametrize("variant", [23, 32, 13])
+def test_gemm_per_operand_presplit(bfx, orc, variant):
+    """2048 x 2048 x 512 with the workspace: the pre-split products kernel
+    (bfx_split_blocks planes) against the general engine (small workspace) and
+    the oracle on sampled entries."""
+    n, K = 2048, 512
+    A = workloads.normal((n, K), 920)
+    B = workloads.normal((K, n), 921)
+    tA, tB = dev(A), dev(B)
+    C1 = host(bfx.gemm(variant, tA, tB))                                  # planes path
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    C2 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    from paper_1904_06376_amd._lib import check, lib
+    check(lib.bfx_gemm(variant, n, n, K, 1.0, tA.data_ptr(), K, tB.data_ptr(), n, 0.0,
+                       C2.data_ptr(), n, ws.data_ptr(), 16, torch.cuda.current_stream().cuda_stream),
+          "bfx_gemm")
+    C2 = host(C2)
+    g = np.random.default_rng(3)
+    rows, cols = g.integers(0, n, 200), g.integers(0, n, 200)
+    z = np.einsum("ij,ji->i", A[rows].astype(np.float64), B[:, cols].astype(np.float64))
+    zh = np.einsum("ij,ji->i", np.abs(A[rows]).astype(np.float64), np.abs(B[:, cols]).astype(np.float64))
+    bnd = gemm_bound(variant, K) * zh
+    eo = orc.gemm_entries(variant, A, B, rows, cols)
+    for C in (C1, C2):
+        got = C[rows, cols].astype(np.float64)
+        assert np.all(np.abs(got - z) <= bnd)
+        assert np.all(np.abs(got - eo) <= 2 * bnd)
+    assert np.all(np.abs(C1.astype(np.float64) - C2) <= 2 * gemm_bound(variant, K) * absref(A, B))
+
+
+@pytest.mark.parametrize("shape", [(200, 130, 77), (256, 256, 256), (64, 64, 1 << 16)])
+def test_gemm_fp64_sum(bfx, orc, shape):
+    """The "d" option (Sec. IV-A): with alpha = 1, beta = 0 the FP64 sum of the
+    two FP32 accumulators rounds to the bits of the FP32 sum; with alpha, beta
+    the FP64 epilogue stays within the bound of the exact result and within
+    twice it of the oracle's "d" (split-K shape included)."""
+    M, N, K = shape
+    A = workloads.uniform((M, K), 930 + K)
+    B = workloads.uniform((K, N), 931 + K)
+    C0 = workloads.uniform((M, N), 932)
+    tA, tB = dev(A), dev(B)
+    np.testing.assert_array_equal(host(bfx.gemm(6, tA, tB, fp64_sum=True)).view(np.uint32),
+                                  host(bfx.gemm(6, tA, tB)).view(np.uint32))
+    alpha, beta = 2.5, -0.75
+    for v in (3, 6, 9):
+        C = host(bfx.gemm(v, tA, tB, dev(C0), alpha=alpha, beta=beta, fp64_sum=True))
+        Co = orc.gemm(v, A, B, C0, alpha=alpha, beta=beta, fp64_sum=True)
+        z = alpha * ref64(A, B) + beta * C0.astype(np.float64)
+        bnd = gemm_bound(v, K) * abs(alpha) * absref(A, B) + 2 * 2.0 ** -24 * (
+            np.abs(alpha * ref64(A, B)) + np.abs(beta * C0.astype(np.float64))) + 1e-38
+        assert np.all(np.abs(C - z) <= bnd), v
+        assert np.all(np.abs(C.astype(np.float64) - Co) <= 2 * bnd), v
