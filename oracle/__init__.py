@@ -71,6 +71,10 @@ def lib():
         L.orc_residual.restype = None
         L.orc_inf_norm_mat.argtypes = [_i64, _f32p, _i64]
         L.orc_inf_norm_mat.restype = ctypes.c_double
+        L.orc_lu_fmt.argtypes = [_int, _i64, _f32p, _i64, _i32p]
+        L.orc_lu_fmt.restype = _int
+        L.orc_round_fmt.argtypes = [ctypes.c_double, _int]
+        L.orc_round_fmt.restype = ctypes.c_double
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = _int
         _lib = L
@@ -191,6 +195,28 @@ def lu(A, update_variant: int = 6, nb: int = 64):
     if info < 0:
         raise ValueError(f"orc_lu argument error {info}")
     return A, ipiv, info
+
+
+FMT_BF16, FMT_FP16 = 1, 2
+
+
+def lu_fmt(A, fmt: int):
+    """Single-format LU with partial pivoting (the BF16 / FP16 rows of the
+    Sec. IV-B tables): A rounded to the format, every multiplier and update
+    rounded to it once.  Returns (LU, ipiv, info); the factors are FP32 arrays
+    whose values lie in the format."""
+    A = _c32(A).copy()
+    n = A.shape[0]
+    ipiv = np.zeros(n, np.int32)
+    info = lib().orc_lu_fmt(fmt, n, A, max(n, 1), ipiv)
+    if info < 0:
+        raise ValueError(f"orc_lu_fmt argument error {info}")
+    return A, ipiv, info
+
+
+def round_fmt(x: float, fmt: int) -> float:
+    """x rounded once to the format (1: BF16, 2: FP16), nearest even."""
+    return lib().orc_round_fmt(float(x), fmt)
 
 
 def lu_solve(LU, ipiv, b):

@@ -32,6 +32,13 @@
  *           worked example of Sec. II-G singles out.
  *   R-epi   C = alpha*X when beta == 0 (C not read), else
  *           C = fmaf(alpha, X, beta*C)  (BLAS convention).
+ *   R-po    per-operand split counts (Sec. II-G): pa terms of A, pb of B,
+ *           the products a_i b_j with i + j <= 2, bins as x6 (x3 when
+ *           both counts are at most 2).
+ *   R-fmt   the single-format (BF16, FP16) LU of the Sec. IV-B tables
+ *           rounds the matrix and every multiplier and update to the
+ *           format once (nearest even, gradual underflow, overflow to
+ *           Inf); the paper does not say which operations it rounds.
  */
 #include <math.h>
 #include <stdint.h>
@@ -480,6 +487,67 @@ int orc_lu(int update_variant, int64_t n, float *A, int64_t lda,
                      : orc_gemm(update_variant, rest, rest, jb, -1.0f, A21,
                                 lda, A12, lda, 1.0f, A22, lda);
         if (rc) return rc;
+    }
+    return info;
+}
+
+/* ------------------------------------------------------------------ */
+/* Single-format LU (the BF16 and FP16 rows of the Sec. IV-B tables):   */
+/* the matrix rounded to the format, then right-looking elimination     */
+/* with partial pivoting in which every result is rounded to the format */
+/* once: multipliers l = R(a / pivot) and updates a = R(a - l u), the   */
+/* latter as a fused multiply-add (l u + a is exact in FP64 for these   */
+/* formats, so one rounding of the FP64 value is one rounding of the    */
+/* exact value).  fmt 1: BF16 (8 significant bits, FP32 exponent       */
+/* range), fmt 2: FP16 (11 bits, exponents -14..15); nearest-even,     */
+/* gradual underflow, overflow to Inf.                                  */
+/* ------------------------------------------------------------------ */
+static double round_fmt(double x, int fmt)
+{
+    const int p = fmt == 1 ? 8 : 11;
+    const int emin = fmt == 1 ? -126 : -14, emax = fmt == 1 ? 127 : 15;
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    (void)frexp(x, &e);          /* |x| in [2^(e-1), 2^e) */
+    e -= 1;
+    if (e < emin) e = emin;      /* subnormal: fixed quantum 2^(emin-p+1) */
+    const double q = ldexp(1.0, e - p + 1);
+    const double r = rint(x / q) * q;   /* x / q exact (power of two), rint: nearest even */
+    if (fabs(r) >= ldexp(1.0, emax + 1)) return copysign(INFINITY, x);
+    return r;
+}
+
+double orc_round_fmt(double x, int fmt) { return round_fmt(x, fmt); }
+
+int orc_lu_fmt(int fmt, int64_t n, float *A, int64_t lda, int32_t *ipiv)
+{
+    if (fmt != 1 && fmt != 2) return -1;
+    if (n < 0) return -2;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    int info = 0;
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t q = 0; q < n; ++q)
+            A[r * lda + q] = (float)round_fmt(A[r * lda + q], fmt);
+    for (int64_t c = 0; c < n; ++c) {
+        int64_t p = c;
+        float best = fabsf(A[c * lda + c]);
+        for (int64_t r = c + 1; r < n; ++r) {
+            float v = fabsf(A[r * lda + c]);
+            if (v > best) { best = v; p = r; }
+        }
+        ipiv[c] = (int32_t)p;
+        swap_rows(A, lda, c, p, 0, n);
+        double piv = A[c * lda + c];
+        if (piv == 0.0) {
+            if (info == 0) info = (int)(c + 1);
+            continue;
+        }
+        for (int64_t r = c + 1; r < n; ++r) {
+            double l = round_fmt((double)A[r * lda + c] / piv, fmt);
+            A[r * lda + c] = (float)l;
+            for (int64_t q = c + 1; q < n; ++q)
+                A[r * lda + q] = (float)round_fmt(fma(-l, (double)A[c * lda + q], (double)A[r * lda + q]), fmt);
+        }
     }
     return info;
 }

@@ -3,6 +3,8 @@ updates, Sec. I, IV-A) and residual-form iterative refinement (Sec. III, IV-B).
 Checked against LAPACK (scipy getrf/solve), backward-error bounds, pivot
 structure on diagonally dominant input, the singular-pivot convention, and the
 paper's IR table (FP32-level LU at n=50 converges in a few iterations)."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -215,3 +217,128 @@ def test_gmres_full_krylov_space_is_exact(orc):
     g = orc.gmres_ir(A, LU, ipiv, b, restart=n, inner_tol=0.0)
     assert g["status"] == 0 and g["eta"] <= 1e-14 and g["iters"] <= 2
     assert g["inner"] <= 2 * n
+
+
+# ---------------------------------------------------------------------------
+# Single-format LU (the BF16 and FP16 rows of the Sec. IV-B tables)
+# ---------------------------------------------------------------------------
+FMT_BITS = {1: (8, -126, 127), 2: (11, -14, 15)}
+
+
+def test_round_fmt_matches_library_casts_and_rationals(orc):
+    """The format rounding equals torch's FP32 -> BF16 cast and numpy's FP32 ->
+    FP16 cast (nearest even, gradual underflow, overflow to Inf) on FP32 inputs
+    across the exponent range, ties included, and an exact-rational rounding on
+    FP64 inputs."""
+    import torch
+    from tests.exact import _round_to_grid
+    g = np.random.default_rng(77)
+    e = g.integers(-150, 128, 4000)
+    x = (g.uniform(1, 2, 4000) * np.exp2(e.astype(np.float64)) * np.where(g.random(4000) < 0.5, -1, 1))
+    x32 = x.astype(np.float32)
+    ties = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 65520.0, 65519.0, 1.5 * 2 ** -24, 2.5 * 2 ** -133,
+                     3.3895e38, 3.4e38], np.float32)
+    x32 = np.concatenate([x32, ties, -ties])
+    bf = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float32).numpy()
+    hf = x32.astype(np.float16).astype(np.float64)
+    for v, b, h in zip(x32, bf, hf):
+        assert orc.round_fmt(float(v), 1) == float(b), (v, b)
+        assert orc.round_fmt(float(v), 2) == h or (np.isnan(h) and False), (v, h)
+    for v in x[:1000]:
+        for fmt, (p, emin, emax) in FMT_BITS.items():
+            assert orc.round_fmt(float(v), fmt) == _round_to_grid(Fraction(float(v)), p, emin, emax)
+
+
+def _lu_fmt_emulated(A, fmt):
+    """Exact-rational statement of the single-format elimination: every value a
+    rational, rounded to the format by integer arithmetic (tests/exact.py)."""
+    from tests.exact import _round_to_grid
+    p, emin, emax = FMT_BITS[fmt]
+
+    def R(q):
+        return Fraction(_round_to_grid(q, p, emin, emax))
+
+    n = A.shape[0]
+    M = [[R(Fraction(float(A[i, j]))) for j in range(n)] for i in range(n)]
+    piv = []
+    for c in range(n):
+        best, pr = abs(M[c][c]), c
+        for r in range(c + 1, n):
+            if abs(M[r][c]) > best:
+                best, pr = abs(M[r][c]), r
+        piv.append(pr)
+        M[c], M[pr] = M[pr], M[c]
+        if M[c][c] == 0:
+            continue
+        for r in range(c + 1, n):
+            l = R(M[r][c] / M[c][c])
+            M[r][c] = l
+            for q in range(c + 1, n):
+                M[r][q] = R(M[r][q] - l * M[c][q])
+    return np.array([[float(v) for v in row] for row in M], np.float64), np.array(piv, np.int32)
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_lu_fmt_equals_exact_rational_emulation(orc, fmt):
+    """Bit for bit on small matrices of several exponent ranges: every multiplier
+    and update rounded once to the format (a missing or extra rounding, or an
+    FP32 intermediate, changes some entries)."""
+    for seed in range(6):
+        n = 3 + seed
+        A = workloads.gauss_exp((n, n), 1500 + seed, sigma=2) if seed % 2 else \
+            workloads.uniform((n, n), 1500 + seed)
+        LU, ipiv, info = orc.lu_fmt(A, fmt)
+        LUe, pe = _lu_fmt_emulated(A, fmt)
+        np.testing.assert_array_equal(ipiv, pe)
+        np.testing.assert_array_equal(LU.astype(np.float64), LUe)
+
+
+@pytest.mark.parametrize("fmt,n", [(1, 50), (2, 50), (1, 100), (2, 100)])
+def test_lu_fmt_backward_error(orc, fmt, n):
+    """Gaussian elimination with unit roundoff u of the format: the factors
+    reproduce the rounded matrix to gamma_n |L||U| componentwise, and the
+    error is of the format's size, not of FP32's."""
+    u = 2.0 ** -FMT_BITS[fmt][0]
+    A = workloads.normal((n, n), 1600 + n + fmt)
+    LU, ipiv, info = orc.lu_fmt(A, fmt)
+    assert info == 0
+    Af = np.vectorize(lambda v: orc.round_fmt(float(v), fmt))(A.astype(np.float64))
+    p = np.arange(n)
+    for i, q in enumerate(ipiv):
+        p[[i, q]] = p[[q, i]]
+    L = np.tril(LU.astype(np.float64), -1) + np.eye(n)
+    U = np.triu(LU.astype(np.float64))
+    R = np.abs(Af[p] - L @ U)
+    gam = n * u / (1 - n * u)
+    assert np.all(R <= gam * (np.abs(L) @ np.abs(U)) + 1e-300)
+    assert R.max() / np.abs(Af).max() > 2.0 ** -24
+
+
+def test_ir_and_gmres_tables_single_format_ordering(orc):
+    """IR table (n = 50) and GMRES table (diagonally dominant) of Sec. IV-B,
+    qualitatively: LU-IR from the FP32-accurate split LU converges in fewer
+    steps than from an FP16 LU, and that in fewer than from a BF16 LU; with
+    GMRES-IR all three converge, BF16 needing the most GMRES steps."""
+    its = {1: [], 2: [], 0: []}
+    for s in range(10):
+        A, b, _ = workloads.conditioned_system(50, 100.0, 1700 + s)
+        for fmt in (0, 1, 2):
+            LU, ipiv, _ = orc.lu(A, 6, 64) if fmt == 0 else orc.lu_fmt(A, fmt)
+            r = orc.ir(A, LU, ipiv, b, max_iter=100)
+            assert r["status"] == 0, (fmt, r)
+            its[fmt].append(r["iters"])
+    assert np.mean(its[0]) < np.mean(its[2]) < np.mean(its[1])
+    inner = {1: [], 2: [], 0: []}
+    for s in range(10):
+        g = np.random.default_rng(1800 + s)
+        n = 50
+        A = g.uniform(-1, 1, (n, n))
+        d = np.maximum(np.abs(A).sum(0), np.abs(A).sum(1)) + 1.0
+        A = (A + np.diag(d * np.sign(g.uniform(-1, 1, n)))).astype(np.float32)
+        b = A.astype(np.float64) @ g.normal(size=n)
+        for fmt in (0, 1, 2):
+            LU, ipiv, _ = orc.lu(A, 6, 64) if fmt == 0 else orc.lu_fmt(A, fmt)
+            r = orc.gmres_ir(A, LU, ipiv, b, restart=n)
+            assert r["status"] == 0, (fmt, r)
+            inner[fmt].append(r["inner"])
+    assert np.mean(inner[0]) < np.mean(inner[2]) < np.mean(inner[1])
