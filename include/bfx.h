@@ -244,7 +244,9 @@ int bfx_plan_destroy(bfx_plan *plan);
 /* LU with partial pivoting (SGETRF semantics, Sec. I and IV-A): in place,   */
 /* P A = L U with L unit lower (below the diagonal) and U upper.  The panel, */
 /* the row interchanges and the triangular solve are FP32; every trailing    */
-/* update A22 -= L21 U12 is the split GEMM with `variant` products.          */
+/* update A22 -= L21 U12 is the split GEMM with `variant` products (1, 3, 6, */
+/* 9), or, with variant 0, the plain FP32 vector GEMM (bfx_sgemm_fp32): the   */
+/* SGEMM-based SGETRF that Sec. IV-A's LU experiment compares against.       */
 /* ipiv: n int32 (device), ipiv[i] = 0-based row interchanged with row i.    */
 /* info: one int32 (device): 0, or c+1 for the first column c whose pivot is */
 /* exactly zero (the factorisation is completed regardless).                 */
@@ -371,6 +373,13 @@ typedef struct bfx_batched_solve_opts {
     int32_t restart;         /* GMRES steps per cycle (default 0 = n, a full
                                 Krylov space) */
     double inner_tol;        /* relative GMRES tolerance (default 1e-8) */
+    int32_t lu_format;       /* 0: split-BF16 blocked LU with `variant` (default);
+                                1, 2: single-format BF16 / FP16 LU (the Sec. IV-B
+                                tables): the matrix and every multiplier and
+                                update rounded once to the format */
+    int32_t mode;            /* 0: LU-IR, GMRES-IR when it fails (default);
+                                1: GMRES-IR from the start (needs
+                                gmres_max_iter > 0) */
 } bfx_batched_solve_opts;
 
 typedef struct bfx_solve_plan bfx_solve_plan;
@@ -402,6 +411,12 @@ int bfx_solve_plan_launch_per_problem(bfx_solve_plan *plan, void *stream);
  * order; either may be NULL). */
 int bfx_solve_plan_results(const bfx_solve_plan *plan, bfx_gmres_result *results,
                            int32_t *info);
+
+/* Synchronises the device and copies problem `index`'s factors (n x n FP32,
+ * row-major, L below the diagonal, U on and above) and pivots to HOST arrays
+ * (either may be NULL).  Errors: -1 plan NULL, -2 index out of range. */
+int bfx_solve_plan_factors(const bfx_solve_plan *plan, int64_t index, float *lu,
+                           int32_t *ipiv);
 
 int bfx_solve_plan_destroy(bfx_solve_plan *plan);
 

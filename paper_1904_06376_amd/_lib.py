@@ -52,7 +52,8 @@ class GmresOpts(ctypes.Structure):
 
 class BatchedSolveOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iter", ctypes.c_int32), ("gmres_max_iter", ctypes.c_int32),
-                ("restart", ctypes.c_int32), ("inner_tol", c_f64)]
+                ("restart", ctypes.c_int32), ("inner_tol", c_f64), ("lu_format", ctypes.c_int32),
+                ("mode", ctypes.c_int32)]
 
 
 class GmresResult(ctypes.Structure):
@@ -105,6 +106,7 @@ SIGNATURES = {
     "bfx_solve_plan_launch": ([c_vp, c_vp], c_int),
     "bfx_solve_plan_launch_per_problem": ([c_vp, c_vp], c_int),
     "bfx_solve_plan_results": ([c_vp, ctypes.POINTER(GmresResult), ctypes.POINTER(ctypes.c_int32)], c_int),
+    "bfx_solve_plan_factors": ([c_vp, c_i64, c_vp, c_vp], c_int),
     "bfx_solve_plan_destroy": ([c_vp], c_int),
 }
 

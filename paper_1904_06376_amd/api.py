@@ -303,12 +303,14 @@ def gmres_ir_solve(A: torch.Tensor, LU: torch.Tensor, ipiv: torch.Tensor, b: tor
 class BatchedSolvePlan:
     """Many LU + refinement solves in one persistent, graph-captured launch;
     problems that LU-IR leaves unconverged continue with GMRES-IR when
-    gmres_max_iter > 0 (restart 0 = a full Krylov space).
+    gmres_max_iter > 0 (restart 0 = a full Krylov space).  lu_format 1 / 2:
+    single-format BF16 / FP16 LU; mode 1: GMRES-IR from the start.
 
     problems: list of (A float32 n x n, b float64 n, x float64 n) GPU tensors."""
 
     def __init__(self, variant: int, problems, tol: float = 1e-14, max_iter: int = 30,
-                 gmres_max_iter: int = 10, restart: int = 0, inner_tol: float = 1e-8):
+                 gmres_max_iter: int = 10, restart: int = 0, inner_tol: float = 1e-8,
+                 lu_format: int = 0, mode: int = 0):
         self._keep = problems
         descs = (SolveDesc * len(problems))()
         for i, (A, b, x) in enumerate(problems):
@@ -316,7 +318,7 @@ class BatchedSolvePlan:
             _dev(b, torch.float64, "b")
             _dev(x, torch.float64, "x")
             descs[i] = SolveDesc(A.shape[0], A.data_ptr(), _rows(A, "A"), b.data_ptr(), x.data_ptr())
-        opts = BatchedSolveOpts(tol, max_iter, gmres_max_iter, restart, inner_tol)
+        opts = BatchedSolveOpts(tol, max_iter, gmres_max_iter, restart, inner_tol, lu_format, mode)
         h = ctypes.c_void_p()
         check(lib.bfx_lu_ir_batched_plan_create(variant, len(problems), descs, ctypes.byref(opts),
                                                  ctypes.byref(h)), "solve_plan_create")
@@ -335,6 +337,16 @@ class BatchedSolvePlan:
         check(lib.bfx_solve_plan_results(self._h, res, info), "bfx_solve_plan_results")
         return [dict(iters=r.iters, inner=r.inner, status=r.status, eta=r.eta, info=int(i))
                 for r, i in zip(list(res)[: self.count], list(info)[: self.count])]
+
+    def factors(self, index: int):
+        """(LU, ipiv) of problem `index` as host arrays (after a launch)."""
+        import numpy as np
+        n = self._keep[index][0].shape[0]
+        lu = np.zeros((n, n), np.float32)
+        piv = np.zeros(n, np.int32)
+        check(lib.bfx_solve_plan_factors(self._h, index, lu.ctypes.data, piv.ctypes.data),
+              "bfx_solve_plan_factors")
+        return lu, piv
 
     def close(self):
         if getattr(self, "_h", None):

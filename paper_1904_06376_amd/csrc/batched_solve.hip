@@ -52,6 +52,8 @@ struct SolveItem {
 
 // GMRES fallback settings shared by the launch.
 struct GmresCfg {
+    int lu_format;     // 0: split-BF16 blocked LU; 1, 2: single-format BF16, FP16 LU
+    int mode;          // 0: LU-IR (GMRES-IR if it fails); 1: GMRES-IR from the start
     int max_iter;      // refinement steps with GMRES (0: no fallback)
     int restart;       // basis size per cycle (0: n, a full Krylov space)
     double inner_tol;  // relative GMRES tolerance
@@ -340,6 +342,70 @@ __device__ int gmres_phase(const SolveItem &it, const GmresCfg &cfg, double norm
     return status;
 }
 
+// Round an exact FP64 value once to the single format of the LU (1: BF16,
+// 2: FP16): nearest even, gradual underflow, overflow to Inf.
+__device__ __forceinline__ double round_fmt(double x, int fmt) {
+    const int p = fmt == 1 ? 8 : 11;
+    const int emin = fmt == 1 ? -126 : -14, emax = fmt == 1 ? 127 : 15;
+    if (x == 0.0 || !(fabs(x) < INFINITY)) return x;
+    int e;
+    (void)frexp(x, &e);   // |x| in [2^(e-1), 2^e)
+    e -= 1;
+    if (e < emin) e = emin;
+    const double q = ldexp(1.0, e - p + 1);
+    const double r = rint(x / q) * q;
+    if (fabs(r) >= ldexp(1.0, emax + 1)) return copysign((double)INFINITY, x);
+    return r;
+}
+
+// Single-format LU (the BF16 and FP16 rows of the Sec. IV-B tables), in
+// place on the factor storage that holds a copy of A: every entry rounded to
+// the format, then elimination with partial pivoting in which every
+// multiplier and every update is rounded to the format once (the update as a
+// fused multiply-add: l u + a is exact in FP64 for these formats).
+__device__ void lu_fmt_wg(const SolveItem &it, int fmt, float *s_v, int *s_i) {
+    const int t = threadIdx.x;
+    const int n = (int)it.n;
+    float *LU = it.LU;
+    for (int64_t e = t; e < (int64_t)n * n; e += 256) LU[e] = (float)round_fmt((double)LU[e], fmt);
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        float bv = -1.0f;
+        int bi = INT_MAX;
+        for (int r = c + t; r < n; r += 256) {
+            float v = fabsf(LU[(int64_t)r * n + c]);
+            if (!(v == v)) v = INFINITY;
+            argmax_better(bv, bi, v, r);
+        }
+        block_argmax(bv, bi, s_v, s_i);
+        const int p = bi;
+        if (t == 0) {
+            it.ipiv[c] = p;
+            if (LU[(int64_t)p * n + c] == 0.0f && *it.info == 0) *it.info = c + 1;
+        }
+        if (p != c)
+            for (int q = t; q < n; q += 256) {
+                const float x = LU[(int64_t)c * n + q];
+                LU[(int64_t)c * n + q] = LU[(int64_t)p * n + q];
+                LU[(int64_t)p * n + q] = x;
+            }
+        __syncthreads();
+        const double piv = LU[(int64_t)c * n + c];
+        if (piv == 0.0) continue;   // uniform: the column below is zero
+        for (int r = c + 1 + t; r < n; r += 256)
+            LU[(int64_t)r * n + c] = (float)round_fmt((double)LU[(int64_t)r * n + c] / piv, fmt);
+        __syncthreads();
+        const int m = n - c - 1;
+        for (int e = t; e < m * m; e += 256) {
+            const int r = c + 1 + e / m, q = c + 1 + e % m;
+            const double l = LU[(int64_t)r * n + c];
+            LU[(int64_t)r * n + q] =
+                (float)round_fmt(fma(-l, (double)LU[(int64_t)c * n + q], (double)LU[(int64_t)r * n + q]), fmt);
+        }
+        __syncthreads();
+    }
+}
+
 template <int V>
 __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const GmresCfg &cfg, uint16_t *smem) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -357,8 +423,9 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
     if (t == 0) *it.info = 0;
     __syncthreads();
 
-    // ---- blocked LU
-    for (int j = 0; j < n; j += SNB) {
+    // ---- LU: single-format, or blocked with split-GEMM trailing updates
+    if (cfg.lu_format) lu_fmt_wg(it, cfg.lu_format, s_v, s_i);
+    for (int j = 0; j < (cfg.lu_format ? 0 : n); j += SNB) {
         const int jb = (n - j < SNB) ? n - j : SNB;
         const int m = n - j;
         float *P = reinterpret_cast<float *>(smem);
@@ -499,7 +566,7 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
 
     int iters = 0, rises = 0, status = 1, inner = 0;
     double eta = 0.0, prev_eta = INFINITY;
-    for (;;) {
+    for (; cfg.mode == 0;) {
         const double rn = residual_wg(it, n, r, s_d);
         const double xn = absmax_x_wg(it, n, s_d);
         const double den = normA * xn + normb;
@@ -516,7 +583,7 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
         __syncthreads();
         ++iters;
     }
-    if ((status == 1 || status == 2) && cfg.max_iter > 0)
+    if (cfg.mode == 1 || ((status == 1 || status == 2) && cfg.max_iter > 0))
         status = gmres_phase(it, cfg, normA, normb, tol, smem, iters, inner, eta);
     if (t == 0) {
         it.res->iters = iters;
@@ -564,7 +631,7 @@ persistent_solve_kernel(const SolveItem *__restrict__ items, int64_t count, uint
 struct bfx_solve_plan {
     int variant = 6;
     int64_t count = 0;
-    bfx_batched_solve_opts opts = {1e-14, 30, 10, 0, 1e-8};
+    bfx_batched_solve_opts opts = {1e-14, 30, 10, 0, 1e-8, 0, 0};
     std::vector<bfx_solve_desc> h_desc;
     std::vector<int64_t> lu_off, piv_off;   // host copies of per-problem offsets
     bfx::SolveItem *d_items = nullptr;
@@ -615,7 +682,9 @@ extern "C" int bfx_lu_ir_batched_plan_create(int variant, int64_t count, const b
     if (count < 0) return -2;
     if (count > 0 && !descs) return -3;
     if (opts && (!(opts->tol >= 0.0) || opts->max_iter < 0 || opts->gmres_max_iter < 0 ||
-                 opts->restart < 0 || !(opts->inner_tol >= 0.0)))
+                 opts->restart < 0 || !(opts->inner_tol >= 0.0) || opts->lu_format < 0 ||
+                 opts->lu_format > 2 || opts->mode < 0 || opts->mode > 1 ||
+                 (opts->mode == 1 && opts->gmres_max_iter == 0)))
         return -4;
     if (!out) return -5;
     *out = nullptr;
@@ -721,6 +790,8 @@ extern "C" int bfx_solve_plan_launch(bfx_solve_plan *p, void *stream) {
         double tol = p->opts.tol;
         int max_iter = p->opts.max_iter;
         GmresCfg cfg;
+        cfg.lu_format = p->opts.lu_format;
+        cfg.mode = p->opts.mode;
         cfg.max_iter = p->d_scratch ? p->opts.gmres_max_iter : 0;
         cfg.restart = (int)p->m_cap;
         cfg.inner_tol = p->opts.inner_tol;
@@ -746,6 +817,10 @@ extern "C" int bfx_solve_plan_launch(bfx_solve_plan *p, void *stream) {
 extern "C" int bfx_solve_plan_launch_per_problem(bfx_solve_plan *p, void *stream) {
     using namespace bfx;
     if (!p) return -1;
+    if (p->opts.lu_format != 0 || p->opts.mode != 0) {
+        set_error("bfx_solve_plan_launch_per_problem: only plans with the split-BF16 LU and LU-IR");
+        return -1;
+    }
     hipStream_t s = (hipStream_t)stream;
     for (int64_t i = 0; i < p->count; ++i) {
         const bfx_solve_desc &d = p->h_desc[i];
@@ -773,6 +848,17 @@ extern "C" int bfx_solve_plan_results(const bfx_solve_plan *p, bfx_gmres_result 
         BFX_HIP(hipMemcpy(results, p->d_res, sizeof(bfx_gmres_result) * p->count, hipMemcpyDeviceToHost));
     if (info && p->count)
         BFX_HIP(hipMemcpy(info, p->d_info, sizeof(int32_t) * p->count, hipMemcpyDeviceToHost));
+    return BFX_OK;
+}
+
+extern "C" int bfx_solve_plan_factors(const bfx_solve_plan *p, int64_t index, float *lu, int32_t *ipiv) {
+    using namespace bfx;
+    if (!p) return -1;
+    if (index < 0 || index >= p->count) return -2;
+    BFX_HIP(hipDeviceSynchronize());
+    const int64_t n = p->h_desc[index].n;
+    if (lu) BFX_HIP(hipMemcpy(lu, p->d_lu + p->lu_off[index], sizeof(float) * n * n, hipMemcpyDeviceToHost));
+    if (ipiv) BFX_HIP(hipMemcpy(ipiv, p->d_ipiv + p->piv_off[index], sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     return BFX_OK;
 }
 

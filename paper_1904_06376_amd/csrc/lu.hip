@@ -419,8 +419,13 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         float *A21 = A + (j + jb) * lda + j;
         float *A12 = A + j * lda + (j + jb);
         float *A22 = A + (j + jb) * lda + (j + jb);
-        const int rc = gemm_launch(variant, rest, rest, jb, -1.0f, A21, lda, A12, lda, 1.0f,
-                                   A22, lda, nullptr, 0, s);
+        // variant 0: the plain FP32 vector GEMM (an SGETRF built on SGEMM, the
+        // comparator of Sec. IV-A's LU experiment)
+        const int rc = variant == 0
+                           ? bfx_sgemm_fp32(rest, rest, jb, -1.0f, A21, lda, A12, lda, 1.0f, A22, lda,
+                                            nullptr, 0, (void *)s)
+                           : gemm_launch(variant, rest, rest, jb, -1.0f, A21, lda, A12, lda, 1.0f,
+                                         A22, lda, nullptr, 0, s);
         if (rc != BFX_OK) return rc;
     }
     return BFX_OK;
@@ -435,7 +440,7 @@ extern "C" size_t bfx_lu_ws_size(int64_t n) {
 
 extern "C" int bfx_lu_factor(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv,
                              int32_t *info, void *ws, size_t ws_bytes, void *stream) {
-    if (variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
+    if (variant != 0 && variant != 1 && variant != 3 && variant != 6 && variant != 9) return -1;
     if (n < 0) return -2;
     if (n > 0 && !A) return -3;
     if (lda < (n > 1 ? n : 1)) return -4;

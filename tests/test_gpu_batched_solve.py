@@ -118,3 +118,82 @@ def test_batched_solves_gmres_fallback_high_kappa(bfx, orc, kappa):
             assert ro["status"] == 0, (n, ro)
     assert used >= (1 if kappa < 1e10 else len(sizes) // 2), res
     plan.close()
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_batched_single_format_lu_bitwise_vs_oracle(bfx, orc, fmt):
+    """Single-format LU (Sec. IV-B tables): the same roundings as the oracle in
+    the same order, so factors and pivots are bit-identical."""
+    sizes = [1, 5, 50, 100, 257]
+    mats = [workloads.normal((n, n), 1900 + n) for n in sizes]
+    probs = [(dev(A), dev(A.astype(np.float64).sum(1)), torch.empty(len(A), dtype=torch.float64, device="cuda"))
+             for A in mats]
+    plan = bfx.BatchedSolvePlan(6, probs, lu_format=fmt, max_iter=0, gmres_max_iter=0)
+    plan.launch()
+    plan.results()
+    for i, A in enumerate(mats):
+        lu, piv = plan.factors(i)
+        LUo, ipo, _ = orc.lu_fmt(A, fmt)
+        np.testing.assert_array_equal(piv, ipo)
+        np.testing.assert_array_equal(lu.view(np.uint32), LUo.view(np.uint32))
+    plan.close()
+
+
+def _table_counts(res):
+    conv = [r for r in res if r["status"] == 0]
+    return len(conv), (float(np.mean([r["iters"] for r in conv])) if conv else None)
+
+
+@pytest.mark.parametrize("kappa", [1e1, 1e3, 1e4])
+def test_ir_table_single_format_gpu(bfx, orc, kappa):
+    """IR table (Sec. IV-B), n = 50: LU-IR from the split-BF16 LU (the FP32 row)
+    always converges; from BF16 / FP16 LUs it converges as often as the oracle's
+    refinement on the oracle's factors (within 2 of 20) in about as many steps."""
+    systems = [workloads.conditioned_system(50, kappa, 2000 + s) for s in range(20)]
+    for fmt in (0, 1, 2):
+        probs = [(dev(A), dev(b), torch.empty(50, dtype=torch.float64, device="cuda")) for (A, b, _) in systems]
+        plan = bfx.BatchedSolvePlan(6, probs, lu_format=fmt, max_iter=100, gmres_max_iter=0)
+        plan.launch()
+        res = plan.results()
+        plan.close()
+        ro = []
+        for (A, b, _) in systems:
+            LU, ipiv, _ = orc.lu(A, 6, 32) if fmt == 0 else orc.lu_fmt(A, fmt)
+            r = orc.ir(A, LU, ipiv, b, max_iter=100)
+            ro.append(r)
+        cg, ig = _table_counts(res)
+        co, io = _table_counts(ro)
+        if fmt == 0:
+            assert cg == 20
+        assert abs(cg - co) <= 2, (fmt, cg, co)
+        if cg >= 5 and co >= 5:
+            assert abs(ig - io) <= 0.25 * io + 1, (fmt, ig, io)
+
+
+@pytest.mark.parametrize("n", [10, 50, 100])
+def test_gmres_table_single_format_gpu(bfx, orc, n):
+    """GMRES table (Sec. IV-B): diagonally dominant matrices, GMRES-IR with the
+    split-BF16, BF16 and FP16 LUs as preconditioners; every solve converges, in
+    about as many GMRES steps as the oracle (BF16 the most)."""
+    systems = []
+    for s in range(20):
+        g = np.random.default_rng(2100 + 17 * n + s)
+        A = g.uniform(-1, 1, (n, n))
+        d = np.maximum(np.abs(A).sum(0), np.abs(A).sum(1)) + 1.0
+        A = (A + np.diag(d * np.sign(g.uniform(-1, 1, n)))).astype(np.float32)
+        systems.append((A, A.astype(np.float64) @ g.normal(size=n)))
+    mean_inner = {}
+    for fmt in (0, 1, 2):
+        probs = [(dev(A), dev(b), torch.empty(n, dtype=torch.float64, device="cuda")) for (A, b) in systems]
+        plan = bfx.BatchedSolvePlan(6, probs, lu_format=fmt, mode=1)
+        plan.launch()
+        res = plan.results()
+        plan.close()
+        assert all(r["status"] == 0 for r in res), (fmt, res)
+        ro = []
+        for (A, b) in systems:
+            LU, ipiv, _ = orc.lu(A, 6, 32) if fmt == 0 else orc.lu_fmt(A, fmt)
+            ro.append(orc.gmres_ir(A, LU, ipiv, b, restart=n)["inner"])
+        mean_inner[fmt] = float(np.mean([r["inner"] for r in res]))
+        assert abs(mean_inner[fmt] - np.mean(ro)) <= 1.5, (fmt, mean_inner[fmt], np.mean(ro))
+    assert mean_inner[0] <= mean_inner[2] <= mean_inner[1]

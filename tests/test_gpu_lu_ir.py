@@ -287,3 +287,41 @@ def test_lu_ir_n8192_sixteen_panel_workgroups(bfx):
     eta = float(((b - A64 @ x).abs().max() /
                  (A64.abs().sum(1).max() * x.abs().max() + b.abs().max())).item())
     assert eta <= 1.01e-14, eta
+
+
+@pytest.mark.parametrize("n", [129, 513])
+def test_lu_fp32_gemm_updates_vs_oracle(bfx, orc, n):
+    """variant 0: the same blocked LU with plain FP32 vector-GEMM trailing
+    updates (an SGEMM-based SGETRF, Sec. IV-A's comparator): valid pivots,
+    the backward-error bound, pivots as the oracle's variant 0."""
+    A = workloads.uniform((n, n), 2200 + n)
+    LU, ipiv, info = gpu_lu(bfx, A, 0)
+    assert info == 0
+    ok, ratio = backward_ok(A, LU, ipiv)
+    assert ok, ratio
+    _, ipo, _ = orc.lu(A, 0, 128)
+    assert float(np.mean(ipiv == ipo)) > 0.95
+
+
+def test_fig5_split_lu_more_accurate_than_fp32_gemm_lu_gpu(bfx):
+    """Fig. 5 (Sec. IV-A) on the GPU: against the FP64 LU with the same pivots,
+    the x6 LU's element errors are smaller than those of the FP32-GEMM LU, on
+    [-1, 1] and [-1e10, 1e10], in every run."""
+    n = 512
+
+    def lu64_same_pivots(A, piv):
+        # FP64 elimination of A with the given interchanges (no pivot search)
+        M = A.astype(np.float64)[perm_from_ipiv(piv, n)]
+        for c in range(n - 1):
+            M[c + 1:, c] /= M[c, c]
+            M[c + 1:, c + 1:] -= np.outer(M[c + 1:, c], M[c, c + 1:])
+        return M
+
+    for scale in (1.0, 1e10):
+        for s in range(3):
+            A = (workloads.uniform((n, n), 2300 + s) * np.float32(scale)).astype(np.float32)
+            l6, p6, _ = gpu_lu(bfx, A, 6)
+            l0, p0, _ = gpu_lu(bfx, A, 0)
+            e6 = np.mean(np.abs(l6 - lu64_same_pivots(A, p6)))
+            e0 = np.mean(np.abs(l0 - lu64_same_pivots(A, p0)))
+            assert e6 < e0, (scale, s, e6, e0)

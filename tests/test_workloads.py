@@ -38,3 +38,13 @@ def test_conditioned_system_kappa():
     sv = np.linalg.svd(A.astype(np.float64), compute_uv=False)
     assert abs(sv[0] / sv[-1] / 1e4 - 1) < 1e-3
     np.testing.assert_allclose(b, A.astype(np.float64) @ xt)
+
+
+def test_max_exp_range_and_finite_products():
+    a = workloads.max_exp((256, 256), 3, K=256)
+    e = np.floor(np.log2(np.abs(a.astype(np.float64))))
+    assert e.min() == -58 and e.max() == 58
+    assert abs((a < 0).mean() - 0.5) < 0.01
+    np.testing.assert_array_equal(a, workloads.max_exp((256, 256), 3, K=256))
+    p = np.abs(a.astype(np.float64)) @ np.abs(a.astype(np.float64))
+    assert np.all(p < np.finfo(np.float32).max)

@@ -11,6 +11,8 @@ Recipes (each is stated again in the design doc):
   normal       iid N(0, 1)
   wide         +-2^u, u ~ U[-20, 20] continuous, random sign
   gauss_exp    +-m * 2^e, m ~ U[1, 2), e = round(N(0, 8)) clipped to [-100, 100]
+  max_exp      +-m * 2^e, m ~ U[1, 2), e uniform over the integers of [-E, E],
+               E = floor((126 - log2 K) / 2) - 1 (finite K-term sums)
   cancellation B[:, j] = -A[j, :]^T + 1e-4 * N(0, 1)  (B's j-th column is the
                negated j-th row of A plus noise)
   batched      shapes M, N, K iid uniform over {32, 48, ..., 512}; entries N(0,1)
@@ -24,7 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "rng", "uniform", "normal", "wide", "gauss_exp", "cancellation",
+    "rng", "uniform", "normal", "wide", "gauss_exp", "max_exp", "cancellation",
     "batched_shapes", "batched_problems", "haar", "conditioned_system",
     "batch_sizes",
 ]
@@ -55,6 +57,21 @@ def gauss_exp(shape, seed: int, sigma: float = 8.0, emax: int = 100) -> np.ndarr
     e = np.clip(np.rint(g.normal(0.0, sigma, size=shape)), -emax, emax)
     s = np.where(g.random(size=shape) < 0.5, -1.0, 1.0)
     return (s * m * np.exp2(e)).astype(np.float32)
+
+
+def max_exp(shape, seed: int, K: int = 256) -> np.ndarray:
+    """The "maximal exponent" inputs of Sec. IV-A (Fig. 3): random sign,
+    mantissa uniform in [1, 2), exponent uniform over the integers of
+    [-E, E] with E = floor((126 - log2 K) / 2) - 1, the widest symmetric range
+    whose products and K-term sums stay finite in FP32 (E = 58 for K = 256).
+    Products then reach down to 2^-116, below the 2^-110 limit of an exact
+    split (Sec. II-F)."""
+    E = int((126 - np.log2(max(K, 1))) // 2) - 1
+    g = rng(seed)
+    m = g.uniform(1.0, 2.0, size=shape)
+    e = g.integers(-E, E + 1, size=shape)
+    s = np.where(g.random(size=shape) < 0.5, -1.0, 1.0)
+    return (s * m * np.exp2(e.astype(np.float64))).astype(np.float32)
 
 
 def cancellation(M: int, K: int, seed: int, noise: float = 1e-4):
