@@ -204,21 +204,10 @@ def main():
                   for x in bfx.split(torch.from_numpy(Ssplit).to(dev), 3)]
         total = sum(pl.view(np.float32).astype(np.float64) for pl in planes)
         small["split_131072_sum_exact"] = bool(np.array_equal(total, Ssplit.astype(np.float64)))
-        rel = {k: [] for k in ("x3", "x6", "x9", "fp32_vector")}
+        # (the mean relative Frobenius errors over 1000 seeds are in paper_figures)
         tS1 = torch.empty((256, 256), dtype=torch.float32, device=dev)
-        for seed in range(100):
-            A1 = workloads.uniform((256, 256), 2 * seed)
-            B1 = workloads.uniform((256, 256), 2 * seed + 1)
-            z = A1.astype(np.float64) @ B1.astype(np.float64)
-            tA1, tB1 = torch.from_numpy(A1).to(dev), torch.from_numpy(B1).to(dev)
-            for v in (3, 6, 9, 0):
-                if v:
-                    bfx.gemm(v, tA1, tB1, tS1)
-                else:
-                    bfx.sgemm_fp32(tA1, tB1, tS1)
-                c1 = tS1.cpu().numpy().astype(np.float64)
-                rel["fp32_vector" if v == 0 else f"x{v}"].append(np.linalg.norm(c1 - z) / np.linalg.norm(z))
-        small["mean_rel_frobenius_100_seeds"] = {k: float(np.mean(vv)) for k, vv in rel.items()}
+        tA1 = torch.from_numpy(workloads.uniform((256, 256), 0)).to(dev)
+        tB1 = torch.from_numpy(workloads.uniform((256, 256), 1)).to(dev)
         us = {}
         for v in (3, 6, 9):
             ms, _ = time_launches(torch, lambda: bfx.gemm(v, tA1, tB1, tS1), 20, stream)
@@ -347,6 +336,16 @@ def main():
         except Exception as e:
             extras["batched_solves_512"] = {"error": repr(e)}
         log(f"[bench] batched solves {extras['batched_solves_512']}")
+        try:
+            extras["paper_figures"] = bench_paper_figures(torch, bfx, workloads, dev)
+        except Exception as e:
+            extras["paper_figures"] = {"error": repr(e)}
+        log(f"[bench] paper figures {extras['paper_figures']}")
+        try:
+            extras["paper_tables"] = bench_paper_tables(torch, bfx, workloads, dev)
+        except Exception as e:
+            extras["paper_tables"] = {"error": repr(e)}
+        log(f"[bench] paper tables {extras['paper_tables']}")
 
     # ---------------- CPU baseline: the oracle on a row sample ----------------
     import oracle as orc
@@ -482,7 +481,7 @@ def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512):
         plan = bfx.BatchedSolvePlan(6, probs)
         plan.launch()
         res = plan.results()
-        ms, _ = time_launches(torch, plan.launch, 3, stream)
+        ms, _ = time_launches(torch, plan.launch, 1 if kappa >= 1e12 else 3, stream)
         conv = sum(1 for r in res if r["status"] == 0)
         etas = [eta_check(torch, A, b, x) for (A, b, x) in probs]
         row = {"ms": round(ms, 3), "solves_per_s": round(count / (ms * 1e-3), 1),
@@ -512,6 +511,118 @@ def bench_batched_solves(torch, bfx, workloads, dev, stream, count=512):
         log(f"[bench] batched solves kappa={kappa:g}: {row}")
         del probs, systems
     return out
+
+
+def bench_paper_figures(torch, bfx, workloads, dev, n=256, seeds=1000, lu_n=256, lu_runs=100):
+    """The GEMM and LU accuracy experiments of Sec. IV-A on the GPU.
+    Figs. 2-4: mean relative Frobenius error ||C - AB|| / ||AB|| against the
+    FP64 product over `seeds` pairs of n x n operands (Fig. 2 uniform [-1,1],
+    Fig. 3 maximal exponent range, Fig. 4 Gaussian exponents), for x3, x6, x6
+    with the FP64 final sum ("d"), x9, the FP32 vector-ALU GEMM and torch's
+    FP32 matmul.  Fig. 5: mean element error of the LU factors against the
+    FP64 elimination with the same pivots, FP32-GEMM LU over x6 LU (> 1: x6
+    more accurate), on [-1, 1] and [-1e10, 1e10]."""
+    out = {}
+    keys = ("x3", "x6", "x6d", "x9", "fp32_vector", "torch_fp32")
+    tC = torch.empty((n, n), dtype=torch.float32, device=dev)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    gens = (("fig2_uniform", lambda shape, sd: workloads.uniform(shape, sd)),
+            ("fig3_max_exponent", lambda shape, sd: workloads.max_exp(shape, sd, K=n)),
+            ("fig4_gauss_exponent", lambda shape, sd: workloads.gauss_exp(shape, sd)))
+    for name, gen in gens:
+        t0 = time.perf_counter()
+        errs = torch.zeros((len(keys), seeds), dtype=torch.float64, device=dev)
+        for sd in range(seeds):
+            tA = torch.from_numpy(gen((n, n), 50000 + 2 * sd)).to(dev)
+            tB = torch.from_numpy(gen((n, n), 50001 + 2 * sd)).to(dev)
+            Z = tA.double() @ tB.double()
+            zn = torch.linalg.norm(Z)
+            for k, key in enumerate(keys):
+                if key == "fp32_vector":
+                    bfx.sgemm_fp32(tA, tB, tC)
+                elif key == "torch_fp32":
+                    torch.matmul(tA, tB, out=tC)
+                else:
+                    bfx.gemm(int(key[1]), tA, tB, tC, fp64_sum=key.endswith("d"))
+                errs[k, sd] = torch.linalg.norm(tC.double() - Z) / zn
+        m = errs.mean(dim=1).cpu().numpy()
+        out[name] = {key: float(v) for key, v in zip(keys, m)}
+        out[name]["seeds"] = seeds
+        log(f"[bench] {name}: {out[name]} ({time.perf_counter() - t0:.1f}s)")
+
+    def lu64_same_pivots(A, piv):
+        p = np.arange(lu_n)
+        for i, q in enumerate(piv):
+            p[[i, q]] = p[[q, i]]
+        M = A.double()[torch.from_numpy(p).to(dev)]
+        for c in range(lu_n - 1):
+            M[c + 1:, c] /= M[c, c]
+            M[c + 1:, c + 1:] -= torch.outer(M[c + 1:, c], M[c, c + 1:])
+        return M
+
+    fig5 = {}
+    for scale in (1.0, 1e10):
+        ratios = []
+        for r in range(lu_runs):
+            A = torch.from_numpy(workloads.uniform((lu_n, lu_n), 60000 + r) * np.float32(scale)).to(dev)
+            errs = []
+            for v in (6, 0):
+                LU = A.clone()
+                _, ipiv, _ = bfx.lu_factor(LU, v)
+                ref = lu64_same_pivots(A, ipiv.cpu().numpy())
+                errs.append(float((LU.double() - ref).abs().mean().item()))
+            ratios.append(errs[1] / errs[0])
+        fig5[f"range_{scale:g}"] = {"mean_improvement": float(np.mean(ratios)),
+                                    "min_improvement": float(np.min(ratios)), "runs": lu_runs, "n": lu_n}
+    out["fig5_lu_fp32gemm_over_x6"] = fig5
+    return out
+
+
+def bench_paper_tables(torch, bfx, workloads, dev, count=100):
+    """The Sec. IV-B tables on the GPU, `count` systems per row, with the
+    split-BF16 LU (the FP32-accurate row) and single-format BF16 and FP16 LUs.
+    IR table: n = 50, kappa 10 .. 1e4, LU-IR (max 100 steps).  GMRES table:
+    diagonally dominant n = 10, 50, 100, GMRES-IR.  % converged to eta <=
+    1e-14 and mean refinement steps (and GMRES steps) of the converged."""
+    fmts = {"fp32_split": 0, "bf16": 1, "fp16": 2}
+    ir = {}
+    for kappa in (1e1, 1e2, 1e3, 1e4):
+        systems = [workloads.conditioned_system(50, kappa, 70000 + s) for s in range(count)]
+        row = {}
+        for fname, f in fmts.items():
+            probs = [(torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev),
+                      torch.empty(50, dtype=torch.float64, device=dev)) for (A, b, _) in systems]
+            plan = bfx.BatchedSolvePlan(6, probs, lu_format=f, max_iter=100, gmres_max_iter=0)
+            plan.launch()
+            res = plan.results()
+            plan.close()
+            conv = [r for r in res if r["status"] == 0]
+            row[fname] = {"converged_pct": 100.0 * len(conv) / count,
+                          "mean_iters": round(float(np.mean([r["iters"] for r in conv])), 2) if conv else None}
+        ir[f"kappa{kappa:g}"] = row
+    gm = {}
+    for n in (10, 50, 100):
+        systems = []
+        for s in range(count):
+            g = np.random.default_rng(80000 + 17 * n + s)
+            A = g.uniform(-1, 1, (n, n))
+            d = np.maximum(np.abs(A).sum(0), np.abs(A).sum(1)) + 1.0
+            A = (A + np.diag(d * np.sign(g.uniform(-1, 1, n)))).astype(np.float32)
+            systems.append((A, A.astype(np.float64) @ g.normal(size=n)))
+        row = {}
+        for fname, f in fmts.items():
+            probs = [(torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev),
+                      torch.empty(n, dtype=torch.float64, device=dev)) for (A, b) in systems]
+            plan = bfx.BatchedSolvePlan(6, probs, lu_format=f, mode=1)
+            plan.launch()
+            res = plan.results()
+            plan.close()
+            conv = [r for r in res if r["status"] == 0]
+            row[fname] = {"converged_pct": 100.0 * len(conv) / count,
+                          "mean_iters": round(float(np.mean([r["iters"] for r in conv])), 2) if conv else None,
+                          "mean_gmres_steps": round(float(np.mean([r["inner"] for r in conv])), 2) if conv else None}
+        gm[f"n{n}"] = row
+    return {"ir_table_n50": ir, "gmres_table_diag_dominant": gm}
 
 
 if __name__ == "__main__":
