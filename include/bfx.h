@@ -355,8 +355,8 @@ int bfx_lu_solve_f32(int64_t n, const float *LU, int64_t ldlu,
 /* split-BF16 blocked LU (Sec. I, IV-A) + FP64-residual refinement (Sec. III) */
 /* for each problem, one workgroup per problem, longest problems first.  A    */
 /* problem that LU-IR leaves unconverged (max_iter reached or stagnation)     */
-/* continues from its current x with GMRES-IR (Sec. III, Sec. IV-B) when      */
-/* gmres_max_iter > 0, in the same workgroup.                                 */
+/* is solved again from x0 = LUsolve(b) with GMRES-IR (Sec. III, Sec. IV-B)   */
+/* when gmres_max_iter > 0, in the same workgroup.                            */
 /* ------------------------------------------------------------------------ */
 typedef struct bfx_solve_desc {
     int64_t n;                     /* 1 <= n <= 1024 */

@@ -15,7 +15,8 @@
 //          wave per row) and FP32 triangular solves in 64-row blocks (the
 //          diagonal block in LDS, solved by one wave);
 //   GMRES  when LU-IR stops without converging (max_iter reached or
-//          stagnation) and GMRES is enabled: refinement from the current x
+//          stagnation) and GMRES is enabled: refinement from x0 again (a
+//          stalled or diverging LU-IR can leave x where GMRES-IR stalls too)
 //          with FP64 GMRES on M^-1 A d = M^-1 r, M the FP32 factors applied
 //          in FP64 arithmetic, classical Gram-Schmidt twice, Givens
 //          rotations; the basis and the rotated Hessenberg matrix live in the
@@ -144,11 +145,30 @@ __device__ void block_trsv(const float *LU, int n, T *y, float *D) {
         __syncthreads();
         // update the rows not yet solved with this block's solution
         const int lo = LOWER ? k0 + rows : 0, hi = LOWER ? n : k0;
-        for (int i = lo + t; i < hi; i += 256) {
-            const float *row = LU + (int64_t)i * n + k0;
-            T acc = (T)0;
-            for (int c = 0; c < rows; ++c) acc = fma((T)row[c], y[k0 + c], acc);
-            y[i] -= acc;
+        if (rows == STB && (n % 4) == 0 && ((uintptr_t)LU % 16) == 0) {
+            // whole 64-column block: sixteen 16-byte loads per row, all in flight
+            for (int i = lo + t; i < hi; i += 256) {
+                const float4 *row = reinterpret_cast<const float4 *>(LU + (int64_t)i * n + k0);
+                float4 a[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) a[q] = row[q];
+                T acc = (T)0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    acc = fma((T)a[q].x, y[k0 + 4 * q], acc);
+                    acc = fma((T)a[q].y, y[k0 + 4 * q + 1], acc);
+                    acc = fma((T)a[q].z, y[k0 + 4 * q + 2], acc);
+                    acc = fma((T)a[q].w, y[k0 + 4 * q + 3], acc);
+                }
+                y[i] -= acc;
+            }
+        } else {
+            for (int i = lo + t; i < hi; i += 256) {
+                const float *row = LU + (int64_t)i * n + k0;
+                T acc = (T)0;
+                for (int c = 0; c < rows; ++c) acc = fma((T)row[c], y[k0 + c], acc);
+                y[i] -= acc;
+            }
         }
         __syncthreads();
     }
@@ -163,16 +183,134 @@ __device__ __forceinline__ double block_sum_d(double v, double *sd) {
     return s;
 }
 
-// r = b - A x (FP64, one wave per row) into LDS; returns |r|_inf.
-__device__ double residual_wg(const SolveItem &it, int n, double *r, double *sd) {
+// Row dot products of one workgroup, out[row] = sum_c A[src(row)][c] u[c]
+// (u in LDS, n <= 1024): each wave takes two rows at a time, each lane
+// four columns per 256-column chunk, so that every lane has eight 16-byte
+// loads in flight before the first FMA (rows one at a time with one load
+// per FMA wait for memory at every step).  src(row) = perm[row] when perm
+// is given.  Accumulation per lane in column order, then a wave reduction.
+__device__ void rowdots_wg(const float *A, int64_t lda, int n, const int32_t *perm, const double *u,
+                           double *out, int vec) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int row0 = 2 * wave; row0 < n; row0 += 8) {
+        float4 a[2][4];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int row = row0 + rr < n ? row0 + rr : n - 1;
+            const float *ar = A + (int64_t)(perm ? perm[row] : row) * lda;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = 4 * lane + 256 * q;
+                if (vec && c + 3 < n) {
+                    a[rr][q] = *reinterpret_cast<const float4 *>(ar + c);
+                } else {
+                    a[rr][q].x = (c < n) ? ar[c] : 0.0f;
+                    a[rr][q].y = (c + 1 < n) ? ar[c + 1] : 0.0f;
+                    a[rr][q].z = (c + 2 < n) ? ar[c + 2] : 0.0f;
+                    a[rr][q].w = (c + 3 < n) ? ar[c + 3] : 0.0f;
+                }
+            }
+        }
+        double sacc[2] = {0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * lane + 256 * q;
+            const double u0 = (c < n) ? u[c] : 0.0, u1 = (c + 1 < n) ? u[c + 1] : 0.0;
+            const double u2 = (c + 2 < n) ? u[c + 2] : 0.0, u3 = (c + 3 < n) ? u[c + 3] : 0.0;
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                sacc[rr] = fma((double)a[rr][q].x, u0, sacc[rr]);
+                sacc[rr] = fma((double)a[rr][q].y, u1, sacc[rr]);
+                sacc[rr] = fma((double)a[rr][q].z, u2, sacc[rr]);
+                sacc[rr] = fma((double)a[rr][q].w, u3, sacc[rr]);
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            double v = sacc[rr];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0 && row0 + rr < n) out[row0 + rr] = v;
+        }
+    }
+}
+
+// h[j] = <V_j, w> for j = 0 .. k (V_j: n doubles in global memory, w in
+// LDS): each wave takes two basis vectors at a time with all of a lane's
+// loads (16 per vector for n = 1024) issued before its FMAs.
+__device__ void basis_dots_wg(const double *V, int n, int k, const double *w, double *h) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j0 = 2 * wave; j0 <= k; j0 += 8) {
+        double x[2][16];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const double *vj = V + (int64_t)(j0 + jj <= k ? j0 + jj : k) * n;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = lane + 64 * q;
+                x[jj][q] = (i < n) ? vj[i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = lane + 64 * q;
+                if (i < n) sacc = fma(x[jj][q], w[i], sacc);
+            }
+            for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+            if (lane == 0 && j0 + jj <= k) h[j0 + jj] = sacc;
+        }
+    }
+}
+
+// out[i] = base[i] + sign * sum_{j < cnt} h[j] V_j[i] for i < n: each thread
+// takes its (up to four) rows together and four basis vectors per step, so
+// that sixteen loads are in flight.
+__device__ void basis_combine_wg(const double *V, int n, int cnt, const double *h, const double *base,
+                                 double *out, double sign) {
+    const int t = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    for (; j + 3 < cnt; j += 4) {
+        double x[4][4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = t + 256 * q;
+                x[jj][q] = (i < n) ? V[(int64_t)(j + jj) * n + i] : 0.0;
+            }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fma(h[j + jj], x[jj][q], acc[q]);
+    }
+    for (; j < cnt; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = t + 256 * q;
+            if (i < n) acc[q] = fma(h[j], V[(int64_t)j * n + i], acc[q]);
+        }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = t + 256 * q;
+        if (i < n) out[i] = fma(sign, acc[q], base[i]);
+    }
+}
+
+// r = b - A x (FP64) into LDS, x staged in LDS at xs; returns |r|_inf.
+__device__ double residual_wg(const SolveItem &it, int n, double *r, double *xs, double *sd) {
+    const int t = threadIdx.x;
+    for (int i = t; i < n; i += 256) xs[i] = it.x[i];
+    __syncthreads();
+    const int vec = ((uintptr_t)it.A % 16 == 0) && (it.lda % 4 == 0);
+    rowdots_wg(it.A, it.lda, n, nullptr, xs, r, vec);
+    __syncthreads();
     double rl = 0.0;
-    for (int row = wave; row < n; row += 4) {
-        double s = 0.0;
-        for (int c = lane; c < n; c += 64) s = fma((double)it.A[(int64_t)row * it.lda + c], it.x[c], s);
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        const double ri = it.b[row] - s;
-        if (lane == 0) r[row] = ri;
+    for (int i = t; i < n; i += 256) {
+        const double ri = it.b[i] - r[i];
+        r[i] = ri;
         const double a = fabs(ri);
         if (a > rl || a != a) rl = a;
     }
@@ -224,10 +362,11 @@ __device__ int gmres_phase(const SolveItem &it, const GmresCfg &cfg, double norm
     double *V = cfg.scratch + (int64_t)blockIdx.x * cfg.per_wg;          // (m_cap + 1) x n
     double *R = V + (cfg.m_cap + 1) * (int64_t)n;                         // m_cap x m_cap, column-major
     const int64_t ldr = cfg.m_cap;
+    const int avec = ((uintptr_t)it.A % 16 == 0) && (it.lda % 4 == 0);
     int steps = 0, rises = 0, status = 1;
     double prev_eta = INFINITY;
     for (;;) {
-        const double rn = residual_wg(it, n, r, s_d);
+        const double rn = residual_wg(it, n, r, v, s_d);
         const double xn = absmax_x_wg(it, n, s_d);
         const double den = normA * xn + normb;
         eta = den > 0.0 ? rn / den : rn;
@@ -255,32 +394,16 @@ __device__ int gmres_phase(const SolveItem &it, const GmresCfg &cfg, double norm
             __syncthreads();
             for (k = 0; k < m;) {
                 // w = P A v
-                for (int row = wave; row < n; row += 4) {
-                    const float *a = it.A + (int64_t)perm[row] * it.lda;
-                    double s = 0.0;
-                    for (int c = lane; c < n; c += 64) s = fma((double)a[c], v[c], s);
-                    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                    if (lane == 0) w[row] = s;
-                }
+                rowdots_wg(it.A, it.lda, n, perm, v, w, avec);
                 __syncthreads();
                 block_trsv<double, true>(LU, n, w, D);
                 block_trsv<double, false>(LU, n, w, D);
                 // classical Gram-Schmidt, twice
                 for (int pass = 0; pass < 2; ++pass) {
                     double *h = pass ? hB : hA;
-                    for (int j = wave; j <= k; j += 4) {
-                        const double *vj = V + (int64_t)j * n;
-                        double s = 0.0;
-                        for (int i = lane; i < n; i += 64) s = fma(vj[i], w[i], s);
-                        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                        if (lane == 0) h[j] = s;
-                    }
+                    basis_dots_wg(V, n, k, w, h);
                     __syncthreads();
-                    for (int i = t; i < n; i += 256) {
-                        double acc = 0.0;
-                        for (int j = 0; j <= k; ++j) acc = fma(h[j], V[(int64_t)j * n + i], acc);
-                        w[i] -= acc;
-                    }
+                    basis_combine_wg(V, n, k + 1, h, w, w, -1.0);
                     __syncthreads();
                 }
                 double qq = 0.0;
@@ -329,11 +452,7 @@ __device__ int gmres_phase(const SolveItem &it, const GmresCfg &cfg, double norm
                 for (int i = t; i < j; i += 256) g[i] = fma(-colj[i], yj, g[i]);
                 __syncthreads();
             }
-            for (int i = t; i < n; i += 256) {
-                double acc = 0.0;
-                for (int j = 0; j < k; ++j) acc = fma(y[j], V[(int64_t)j * n + i], acc);
-                it.x[i] += acc;
-            }
+            basis_combine_wg(V, n, k, y, it.x, it.x, 1.0);
             __syncthreads();
         }
         ++steps;
@@ -567,7 +686,7 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
     int iters = 0, rises = 0, status = 1, inner = 0;
     double eta = 0.0, prev_eta = INFINITY;
     for (; cfg.mode == 0;) {
-        const double rn = residual_wg(it, n, r, s_d);
+        const double rn = residual_wg(it, n, r, reinterpret_cast<double *>(sb + L_V), s_d);
         const double xn = absmax_x_wg(it, n, s_d);
         const double den = normA * xn + normb;
         eta = den > 0.0 ? rn / den : rn;
@@ -583,8 +702,19 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
         __syncthreads();
         ++iters;
     }
-    if (cfg.mode == 1 || ((status == 1 || status == 2) && cfg.max_iter > 0))
+    if (cfg.mode == 1 || ((status == 1 || status == 2) && cfg.max_iter > 0)) {
+        if (cfg.mode == 0) {
+            // LU-IR that stalls or diverges can leave x far worse than x0, and
+            // GMRES-IR started there may stall as well: start it from x0.
+            for (int i = t; i < n; i += 256) y[i] = (float)it.b[perm[i]];
+            __syncthreads();
+            block_trsv<float, true>(LU, n, y, D);
+            block_trsv<float, false>(LU, n, y, D);
+            for (int i = t; i < n; i += 256) it.x[i] = (double)y[i];
+            __syncthreads();
+        }
         status = gmres_phase(it, cfg, normA, normb, tol, smem, iters, inner, eta);
+    }
     if (t == 0) {
         it.res->iters = iters;
         it.res->inner = inner;
