@@ -6,6 +6,13 @@
     python paper_1904_06376_amd/run_workload.py batched-gemm --count 4096 --reps 3
     python paper_1904_06376_amd/run_workload.py batched-solve --count 512 --reps 2
     python paper_1904_06376_amd/run_workload.py lu-update --n 16384 --reps 5
+    python paper_1904_06376_amd/run_workload.py save-system --n 16384 --kappa 1e8 --out /tmp/s16k
+    python paper_1904_06376_amd/run_workload.py refine --src /tmp/s16k --solver gmres --restart 200 --max-iter 1
+
+save-system generates a conditioned system, factors it and writes A, the
+factors, the pivots and b to <out>_A.npy, <out>_LU.npy, <out>_ipiv.npy and
+<out>_b.npy; refine loads them and runs only the refinement (LU-IR or
+GMRES-IR), so that a profiler sees the refinement kernels alone.
 
 Inputs are the seeded synthetic workloads of the benchmark; nothing is timed
 here except a one-line summary printed at the end.
@@ -23,7 +30,12 @@ if ROOT not in sys.path:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", choices=["gemm", "splitk", "lu", "batched-gemm", "batched-solve",
-                                            "lu-update"])
+                                            "lu-update", "save-system", "refine"])
+    ap.add_argument("--out", default="/tmp/bfx_system")
+    ap.add_argument("--src", default="/tmp/bfx_system")
+    ap.add_argument("--solver", choices=["ir", "gmres"], default="gmres")
+    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--max-iter", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--variant", type=int, default=6)
     ap.add_argument("--reps", type=int, default=3)
@@ -63,6 +75,28 @@ def main():
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             print(f"lu {1e3 * (t2 - t1):.1f} ms, ir {1e3 * (t3 - t2):.1f} ms, {res}", flush=True)
+    elif a.workload == "save-system":
+        import numpy as np
+        A, b = workloads.conditioned_system_torch(a.n, a.kappa, 7, dev)
+        LU = A.clone()
+        _, ipiv, info = bfx.lu_factor(LU, a.variant)
+        torch.cuda.synchronize()
+        for name, t in (("A", A), ("LU", LU), ("ipiv", ipiv), ("b", b)):
+            np.save(f"{a.out}_{name}.npy", t.cpu().numpy())
+        print(f"saved n={a.n} kappa={a.kappa:g} info={int(info.item())} to {a.out}_*.npy", flush=True)
+    elif a.workload == "refine":
+        import numpy as np
+        A, LU, ipiv, b = (torch.from_numpy(np.load(f"{a.src}_{name}.npy")).to(dev)
+                          for name in ("A", "LU", "ipiv", "b"))
+        for _ in range(a.reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if a.solver == "ir":
+                x, res = bfx.ir_solve(A, LU, ipiv, b, max_iter=a.max_iter)
+            else:
+                x, res = bfx.gmres_ir_solve(A, LU, ipiv, b, restart=a.restart, max_iter=a.max_iter)
+            torch.cuda.synchronize()
+            print(f"{a.solver} {1e3 * (time.perf_counter() - t1):.1f} ms, {res}", flush=True)
     elif a.workload == "lu-update":
         # the first trailing update of an n x n LU: A22 -= L21 x U12, K = 128,
         # all three operands strided views of one n x n matrix
