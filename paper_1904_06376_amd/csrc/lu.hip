@@ -30,11 +30,17 @@ constexpr int PROWS = 512;   // panel rows per workgroup (= threads, one row eac
 constexpr int MAX_G = 256;   // co-resident workgroups the panel may use
 constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
 
+// Column exchange words: {tag << 32 | 32-bit payload}, tag = global column
+// index + 1, two slots alternating with the column's parity.  A slot holds a
+// row's register image as it was before the previous column's elimination
+// (words 0..PNB-1), that elimination's multiplier (word PNB) and, for
+// candidates, the panel row index (word PNB + 1; -1: no candidate).
+constexpr int CW = PNB + 4;      // words per slot
+constexpr int XCH = PROWS / 16;  // candidates read per round (16 threads each)
+constexpr int CRS = PNB + 4;     // LDS row stride of read candidates
 struct LuWs {
-    uint64_t *hdr;      // [2][MAX_G] {tag << 32 | bits(|candidate|)}
-    int32_t *slot_idx;  // [2][MAX_G] candidate row (panel-relative)
-    float *slot_row;    // [2][MAX_G][PNB] candidate row values
-    float *diag_row;    // [2][PNB] row c before the interchange
+    uint64_t *cand;     // [2][MAX_G][CW] the workgroups' candidate rows
+    uint64_t *diag;     // [2][CW] row c
 };
 
 size_t lu_ws_layout(LuWs *w, void *base) {
@@ -44,16 +50,12 @@ size_t lu_ws_layout(LuWs *w, void *base) {
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const size_t o_hdr = take(sizeof(uint64_t) * 2 * MAX_G);
-    const size_t o_idx = take(sizeof(int32_t) * 2 * MAX_G);
-    const size_t o_row = take(sizeof(float) * 2 * MAX_G * PNB);
-    const size_t o_diag = take(sizeof(float) * 2 * PNB);
+    const size_t o_cand = take(sizeof(uint64_t) * 2 * MAX_G * CW);
+    const size_t o_diag = take(sizeof(uint64_t) * 2 * CW);
     if (w && base) {
         char *b = (char *)base;
-        w->hdr = (uint64_t *)(b + o_hdr);
-        w->slot_idx = (int32_t *)(b + o_idx);
-        w->slot_row = (float *)(b + o_row);
-        w->diag_row = (float *)(b + o_diag);
+        w->cand = (uint64_t *)(b + o_cand);
+        w->diag = (uint64_t *)(b + o_diag);
     }
     return off;
 }
@@ -69,8 +71,54 @@ struct PanelArgs {
 }  // namespace
 
 
-__device__ __forceinline__ void better(float &v, int &i, float v2, int i2) {
-    if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+// Pivot keys: 0 for a row that takes no part (above the diagonal, or no row
+// at all), else bits(|v|) + 1 with NaN taken as infinity (a NaN pivot wins and
+// poisons the result).  Keys of non-negative floats order as the values; equal
+// keys are broken by the lowest row, as ISAMAX does.
+__device__ __forceinline__ uint32_t pivot_key(float v) {
+    float av = fabsf(v);
+    if (!(av == av)) av = INFINITY;
+    return __float_as_uint(av) + 1u;
+}
+
+// Wave-wide maximum of a 32-bit key, returned uniform: DPP steps inside each
+// row of 16 lanes (quad swaps, half-row and row mirrors), then the rows are
+// chained by the row broadcasts so that lane 63 holds the maximum.  All 64
+// lanes must be active.
+__device__ __forceinline__ uint32_t wave_max_key(uint32_t x) {
+    uint32_t y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x140, 0xF, 0xF, false);  // row_mirror
+    x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x = x > y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    x = x > y ? x : y;
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// lowest lane whose predicate holds (64 if none)
+__device__ __forceinline__ int first_lane(bool pred) {
+    const uint64_t b = __ballot(pred);
+    return b ? __builtin_ctzll(b) : 64;
+}
+
+// Bounded wait until every word of a tagged exchange read carries the tag:
+// returns false (and records info = -1) when the wait expires or another
+// workgroup's wait already did.
+__device__ __forceinline__ bool wait_expired(unsigned &spins, int32_t *info) {
+    if (++spins > SPIN_LIMIT ||
+        ((spins & 255u) == 0 && __hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1)) {
+        __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    __builtin_amdgcn_s_sleep(2);
+    return false;
 }
 
 // Each thread holds one panel row in registers, r[0..PNB-1], in a layout
@@ -82,189 +130,261 @@ __device__ __forceinline__ void better(float &v, int &i, float v2, int i2) {
 // puts the new multiplier in r[PNB-1]; all register indices are static.  Rows
 // that reach the diagonal freeze.  Two rows that swap at column c were both
 // shifted c times, so their register images are exchanged as they are.
+//
+// The elimination of column c-1 is deferred past the pivot search of column
+// c: once pivot c-1 is known, every row computes its multiplier and only its
+// next column entry (one FMA), which gives the pivot keys of column c.  The
+// workgroup's candidate is published as it was before that elimination,
+// with its multiplier, and every reader applies the elimination itself while
+// storing it (the same FMA, so the same bits); the owner's full-row update
+// runs while the exchange is in flight.  Row c is published the same way by
+// the wave holding it, as soon as its multiplier is known.
+//
+// Per column, two workgroup barriers.  Before the first, every wave has the
+// pivot keys of its rows (DPP maximum, lowest lane on ties) in LDS; after it
+// every wave forms the workgroup's candidate from the eight wave maxima and
+// the wave holding it publishes it as words tagged with the column (a reader
+// that sees the column's tag in a word has that word's value, so no fence
+// orders the stores).  Every thread then reads its share of all candidates
+// (16 threads per candidate, one 128-byte segment per load instruction and
+// candidate) and threads < PNB read row c, each polling its own words.
+// After the second barrier every wave picks the same pivot.
 __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
-    __shared__ __align__(16) float U[PNB], D[PNB], rowbuf[PNB], diagbuf[PNB];
-    __shared__ float red_v[PROWS / 64];
-    __shared__ int red_i[PROWS / 64];
-    __shared__ int s_piv, s_win;
-    __shared__ float s_val;
+    // staged rows for publishing (image, multiplier): the candidate, row c
+    __shared__ __align__(16) float rowbuf[PNB + 4], diagbuf[PNB + 4];
+    // candidate rows read from the exchange (after the elimination), element
+    // q of candidate k at crow[.][k][3 + q], so that elements 1, 5, 9, ...
+    // start 16-byte groups; two buffers alternate with the column, since
+    // the readers of column c apply the elimination by pivot row c-1.  ubuf
+    // holds the best row of earlier rounds when there are several.
+    __shared__ __align__(16) float crow[2][XCH][CRS];
+    __shared__ __align__(16) float ubuf[2][CRS];
+    __shared__ __align__(16) float D[PNB];   // row c before the interchange
+    __shared__ int cidx[XCH];
+    __shared__ uint32_t red_key[PROWS / 64];
+    __shared__ int red_lane[PROWS / 64];
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int w = a.w;
-    const int64_t row0 = (int64_t)g * PROWS;      // first panel row of this workgroup
-    const int64_t pr = row0 + t;                   // panel row owned by this thread
+    const int row0 = g * PROWS;                    // first panel row of this workgroup
+    const int pr = row0 + t;                       // panel row owned by this thread
+    const int wrow0 = row0 + 64 * wave;            // first row of this wave
     const bool own = pr < a.m;
     float *Ag = a.A + a.j * a.lda + a.j;           // panel origin
     float r[PNB];
 #pragma unroll
-    for (int k = 0; k < PNB; ++k) r[k] = (own && k < w) ? Ag[pr * a.lda + k] : 0.0f;
+    for (int k = 0; k < PNB; ++k) r[k] = (own && k < w) ? Ag[(int64_t)pr * a.lda + k] : 0.0f;
+    float l = 0.0f;   // this row's multiplier of the deferred elimination
 
+    // the elimination of one column on this thread's row: multiplier l,
+    // pivot row U1[k] = U[k + 1], live = width of that column's live part
+    auto eliminate = [&](const float *U1, int live) __attribute__((always_inline)) {
+#pragma unroll
+        for (int b = 0; b < PNB / 8; ++b) {
+            if (8 * b + 8 <= live - 1) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 8 * b + i;
+                    if (k < PNB - 1) r[k] = fmaf(-l, U1[k], r[k + 1]);
+                }
+            } else if (8 * b >= live - 1) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 8 * b + i;
+                    if (k < PNB - 1) r[k] = r[k + 1];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = 8 * b + i;
+                    if (k < PNB - 1) r[k] = (k < live - 1) ? fmaf(-l, U1[k], r[k + 1]) : r[k + 1];
+                }
+            }
+        }
+        r[PNB - 1] = l;
+    };
+    // pivot keys of column c from the entries v, this wave's maximum to LDS
+    auto wave_keys = [&](int c, float v) __attribute__((always_inline)) {
+        const uint32_t key = (own && pr >= c) ? pivot_key(v) : 0u;
+        const uint32_t m = wave_max_key(key);
+        const int lw = first_lane(key == m);
+        if (lane == 0) { red_key[wave] = m; red_lane[wave] = lw; }
+    };
+    // a wave publishes a row staged in buf (image and multiplier) to dst
+    auto publish = [&](const float *buf, uint64_t *dst, uint32_t tag) __attribute__((always_inline)) {
+        const uint64_t tg = (uint64_t)tag << 32;
+        __hip_atomic_store(dst + lane, tg | __float_as_uint(buf[lane]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + lane + 64, tg | __float_as_uint(buf[lane + 64]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0)
+            __hip_atomic_store(dst + PNB, tg | __float_as_uint(buf[PNB]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // the wave holding row c stages and publishes it (image before the
+    // deferred elimination, multiplier l)
+    auto publish_diag = [&](int c) __attribute__((always_inline)) {
+        if (c >= wrow0 && c < wrow0 + 64) {   // uniform over the wave
+            if (pr == c) {
+#pragma unroll
+                for (int k = 0; k < PNB; ++k) diagbuf[k] = r[k];
+                diagbuf[PNB] = l;
+            }
+            publish(diagbuf, a.ws.diag + (c & 1) * CW, (uint32_t)(a.j + c + 1));
+        }
+    };
+
+    publish_diag(0);
+    wave_keys(0, r[0]);
+    const float *Up = nullptr;   // pivot row of the previous column (LDS), U[k] at Up[3 + k]
     for (int c = 0; c < w; ++c) {
         const int par = c & 1;
-        const uint32_t tag = (uint32_t)(a.j + c + 1);   // never 0 (headers start zeroed)
-        const bool active = own && pr >= c;             // rows at or below the diagonal
-        // ---- local arg-max of |column c| over rows >= c
-        float v = active ? fabsf(r[0]) : -1.0f;
-        int idx = own ? (int)pr : INT_MAX;
-        if (!(v == v)) v = INFINITY;  // NaN pivots win (and poison the result)
-        for (int off = 32; off > 0; off >>= 1) {
-            const float v2 = __shfl_xor(v, off);
-            const int i2 = __shfl_xor(idx, off);
-            better(v, idx, v2, i2);
-        }
-        if (lane == 0) { red_v[wave] = v; red_i[wave] = idx; }
+        const uint32_t tag = (uint32_t)(a.j + c + 1);   // never 0 (exchange words start zeroed)
+        const int live_p = w - c + 1;   // live width of the deferred elimination (column c-1)
         __syncthreads();
-        if (t == 0) {
-            float bv = red_v[0];
-            int bi = red_i[0];
-            for (int k = 1; k < PROWS / 64; ++k) better(bv, bi, red_v[k], red_i[k]);
-            s_val = bv;
-            s_piv = (bv >= 0.0f) ? bi : -1;
-        }
-        __syncthreads();
-        // ---- the candidate row and row c (register images) to LDS
-        if (own && pr == s_piv) {
-#pragma unroll
-            for (int k = 0; k < PNB; ++k) rowbuf[k] = r[k];
-        }
-        if (own && pr == c) {
-#pragma unroll
-            for (int k = 0; k < PNB; ++k) diagbuf[k] = r[k];
-        }
-        __syncthreads();
-        // ---- wave 0 publishes them, then the header with release order
-        // (covering the wave's own stores)
-        if (wave == 0) {
-            const bool has_c = c >= row0 && c < row0 + PROWS;
-            for (int q = lane; q < PNB; q += 64) {
-                if (s_piv >= 0) a.ws.slot_row[(par * MAX_G + g) * PNB + q] = rowbuf[q];
-                if (has_c) a.ws.diag_row[par * PNB + q] = diagbuf[q];
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-                a.ws.slot_idx[par * MAX_G + g] = s_piv;
-                const uint64_t h = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(s_val);
-                __hip_atomic_store(&a.ws.hdr[par * MAX_G + g], h, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        // ---- every wave polls 64 of the G headers (bounded wait), then the
-        // largest candidate wins, the lowest workgroup on ties
+        // ---- the workgroup's candidate: the best of the wave maxima (waves
+        // own increasing rows, so the lowest wave wins ties)
         {
-            const int k = wave * 64 + lane;
-            float bv = -2.0f;
-            int bg = INT_MAX;
-            if (k < a.G) {
-                uint64_t h = 0;
-                unsigned spins = 0;
-                for (;;) {
-                    h = __hip_atomic_load(&a.ws.hdr[par * MAX_G + k], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                    if ((uint32_t)(h >> 32) == tag) {
-                        // acquire: the candidate rows published before it are visible
-                        (void)__hip_atomic_load(&a.ws.hdr[par * MAX_G + k], __ATOMIC_ACQUIRE,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    if (__hip_atomic_load(a.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) break;
-                    if (++spins > SPIN_LIMIT) {
-                        __hip_atomic_store(a.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+            const uint32_t wk = lane < PROWS / 64 ? red_key[lane] : 0u;
+            const uint32_t M = wave_max_key(wk);
+            const int W = first_lane(lane < PROWS / 64 && wk == M);
+            const int L = red_lane[W < PROWS / 64 ? W : 0];
+            if (wave == (M ? W : 0)) {
+                if (M && lane == L) {
+#pragma unroll
+                    for (int k = 0; k < PNB; ++k) rowbuf[k] = r[k];
+                    rowbuf[PNB] = l;
                 }
-                bv = __uint_as_float((uint32_t)h);
-                bg = k;
+                uint64_t *slot = a.ws.cand + (size_t)(par * MAX_G + g) * CW;
+                publish(rowbuf, slot, tag);
+                if (lane == 0)
+                    __hip_atomic_store(slot + PNB + 1, ((uint64_t)tag << 32) | (uint32_t)(M ? wrow0 - 64 * wave + 64 * W + L : -1),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const float v2 = __shfl_xor(bv, off);
-                const int g2 = __shfl_xor(bg, off);
-                better(bv, bg, v2, g2);
+        }
+        // ---- the deferred elimination of column c-1 on this thread's row
+        if (c > 0 && own && pr >= c) eliminate(Up + 4, live_p);
+        // ---- read every candidate and row c, eliminating column c-1 on the
+        // way (word q + 1 of the slot gives element q; the last element is
+        // the multiplier itself); then pick the pivot
+        uint32_t best = 0;
+        int bidx = -1;
+        const float *Uc = crow[par][0];
+        const int o = c > 0 ? 1 : 0;
+        for (int k0 = 0; k0 < a.G; k0 += XCH) {
+            const int kl = t >> 4, sub = t & 15;
+            if (k0 + kl < a.G) {
+                const uint64_t *src = a.ws.cand + (size_t)(par * MAX_G + k0 + kl) * CW;
+                uint64_t wv[8], wl = 0, wi = 0;
+                for (unsigned spins = 0;;) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        wv[q] = __hip_atomic_load(src + sub + o + 16 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wl = __hip_atomic_load(src + PNB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bool ok = (uint32_t)(wl >> 32) == tag;
+                    if (sub == 0) {
+                        wi = __hip_atomic_load(src + PNB + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = ok && (uint32_t)(wi >> 32) == tag;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) ok = ok && (uint32_t)(wv[q] >> 32) == tag;
+                    if (ok || wait_expired(spins, a.info)) break;
+                }
+                const float lk = __uint_as_float((uint32_t)wl);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int e = sub + 16 * q;
+                    float x = __uint_as_float((uint32_t)wv[q]);
+                    if (c > 0 && e < live_p - 1) x = fmaf(-lk, Up[4 + e], x);
+                    crow[par][kl][3 + e] = x;
+                }
+                if (sub == 0) cidx[kl] = (int)(uint32_t)wi;
             }
-            if (lane == 0) { red_v[wave] = bv; red_i[wave] = bg; }
+            if (k0 == 0 && t < PNB) {
+                const uint64_t *src = a.ws.diag + par * CW;
+                uint64_t dv = 0, dl = 0;
+                for (unsigned spins = 0;;) {
+                    dv = __hip_atomic_load(src + t + o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    dl = __hip_atomic_load(src + PNB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (((uint32_t)(dv >> 32) == tag && (uint32_t)(dl >> 32) == tag) || wait_expired(spins, a.info))
+                        break;
+                }
+                float x = __uint_as_float((uint32_t)dv);
+                if (c > 0 && t < live_p - 1) x = fmaf(-__uint_as_float((uint32_t)dl), Up[4 + t], x);
+                D[t] = x;
+            }
+            __syncthreads();
+            // every wave: the best candidate of this round (lowest k on ties:
+            // workgroups own increasing rows), kept if it beats earlier rounds
+            uint32_t key = 0;
+            if (lane < XCH && k0 + lane < a.G && cidx[lane] >= 0) key = pivot_key(crow[par][lane][3]);
+            const uint32_t m = wave_max_key(key);
+            const int kw = first_lane(key == m);
+            if (a.G <= XCH) {
+                best = m;
+                bidx = m ? cidx[kw] : -1;
+                Uc = crow[par][kw];
+            } else {
+                if (k0 == 0 || m > best) {
+                    best = m;
+                    bidx = m ? cidx[kw] : -1;
+                    if (t < PNB) ubuf[par][3 + t] = crow[par][kw][3 + t];
+                }
+                Uc = ubuf[par];
+                __syncthreads();   // ubuf complete; crow free for the next round
+            }
         }
-        __syncthreads();
-        if (t == 0) {
-            float bv = red_v[0];
-            int bg = red_i[0];
-            for (int k = 1; k < PROWS / 64; ++k) better(bv, bg, red_v[k], red_i[k]);
-            // a wait that expired leaves bg possibly without a published row:
-            // fall back to this workgroup's own slot (the result is invalid
-            // anyway and reported through info = -1)
-            s_win = (bg < a.G) ? bg : g;
-        }
-        __syncthreads();
-        const int pg = s_win;
-        if (t < PNB) {
-            U[t] = a.ws.slot_row[(par * MAX_G + pg) * PNB + t];
-            D[t] = a.ws.diag_row[par * PNB + t];
-        }
-        if (t == 0) s_piv = a.ws.slot_idx[par * MAX_G + pg];
-        __syncthreads();
         // a valid pivot row is >= c; anything else only follows an expired wait
-        const int p = (s_piv >= c && s_piv < a.m) ? s_piv : c;
-        const float piv = U[0];
+        const int p = (bidx >= c && bidx < a.m) ? bidx : c;
+        const float piv = Uc[3];
         if (g == 0 && t == 0) {
             a.ipiv[a.j + c] = (int32_t)(a.j + p);
             if (piv == 0.0f && *a.info == 0) *a.info = (int32_t)(a.j + c + 1);  // -1 (expired wait) is kept
         }
-        // ---- swap rows c and p, divide, shift-update the rows below
-        if (active) {
+        // ---- interchange rows c and p; the multipliers of the rows below
+        // and their entries in column c+1 (the rest of the elimination is
+        // deferred)
+        float v1 = 0.0f;
+        if (own && pr >= c) {
             if (pr == p && p != c) {
 #pragma unroll
                 for (int k = 0; k < PNB; ++k) r[k] = D[k];
             }
             if (pr == c) {
 #pragma unroll
-                for (int k = 0; k < PNB; ++k) r[k] = U[k];
+                for (int k = 0; k < PNB; ++k) r[k] = Uc[3 + k];
             } else {
-                float l = r[0];
+                l = r[0];
                 if (piv != 0.0f) l = l / piv;
-                const int live = w - c;   // r[0 .. live-1] are columns c .. w-1
-                // blocks of 8 registers: all updated, all shifted, or mixed
-#pragma unroll
-                for (int b = 0; b < PNB / 8; ++b) {
-                    if (8 * b + 8 <= live - 1) {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int k = 8 * b + i;
-                            if (k < PNB - 1) r[k] = fmaf(-l, U[k + 1], r[k + 1]);
-                        }
-                    } else if (8 * b >= live - 1) {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int k = 8 * b + i;
-                            if (k < PNB - 1) r[k] = r[k + 1];
-                        }
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int k = 8 * b + i;
-                            if (k < PNB - 1) r[k] = (k < live - 1) ? fmaf(-l, U[k + 1], r[k + 1]) : r[k + 1];
-                        }
-                    }
-                }
-                r[PNB - 1] = l;
+                v1 = (w - c > 1) ? fmaf(-l, Uc[4], r[1]) : r[1];
             }
         }
+        Up = Uc;
+        if (c + 1 < w) {
+            publish_diag(c + 1);
+            wave_keys(c + 1, v1);
+        }
     }
+    // the last column's elimination
+    if (own && pr >= w) eliminate(Up + 4, 1);
 
     // ---- write back: register k of a row shifted s times holds column s + k
     // (k < w - s) or multiplier k - (PNB - s) (k >= PNB - s)
     if (own) {
-        const int sh = (pr < w) ? (int)pr : w;
+        const int sh = (pr < w) ? pr : w;
+        float *Ar = Ag + (int64_t)pr * a.lda;
 #pragma unroll
         for (int k = 0; k < PNB; ++k) {
             int col = -1;
             if (k < w - sh) col = sh + k;
             else if (k >= PNB - sh) col = k - (PNB - sh);
-            if (col >= 0) Ag[pr * a.lda + col] = r[k];
+            if (col >= 0) Ar[col] = r[k];
         }
     }
 }
 
 __global__ void __launch_bounds__(256) zero_u64(uint64_t *p, int n) {
-    for (int i = threadIdx.x; i < n; i += 256) p[i] = 0ull;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0ull;
 }
 
 // Row interchanges of rows j..j+w-1 (ipiv, applied in order, LAPACK laswp
@@ -394,7 +514,8 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
         attr = true;
     }
     BFX_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, s, w.hdr, 2 * MAX_G);
+    hipLaunchKernelGGL(zero_u64, dim3(64), dim3(256), 0, s, w.cand, 2 * MAX_G * CW);
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, s, w.diag, 2 * CW);
     BFX_LAUNCH_CHECK("zero_u64");
     for (int64_t j = 0; j < n; j += PNB) {
         const int jb = (int)((n - j < PNB) ? n - j : PNB);
