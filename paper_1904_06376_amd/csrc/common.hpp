@@ -140,11 +140,13 @@ int hip_fail(hipError_t e, const char *what);
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Internal GEMM launcher shared by the public entry points, the LU trailing
-// update and the batched per-problem baseline.
+// update and the batched per-problem baseline.  grid_cus > 0: the stream's
+// kernels run on that many compute units (a CU-masked stream), which sizes
+// the persistent launch; 0: the whole device.
 int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                 const float *A, int64_t lda, const float *B, int64_t ldb,
                 float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
-                hipStream_t stream, int flags = 0);
+                hipStream_t stream, int flags = 0, int grid_cus = 0);
 // 1, 3, 6, 7, 8, 9 and the per-operand split counts 12, 13, 21, 23, 31, 32.
 bool variant_valid(int variant);
 size_t gemm_ws_bytes(int variant, int64_t M, int64_t N, int64_t K);

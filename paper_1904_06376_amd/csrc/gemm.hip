@@ -518,7 +518,7 @@ static int launch_persist(const GemmParams &p, hipStream_t s) {
     }
     const int tiles_m = (int)(p.M / BM), tiles_n = (int)(p.N / BM);
     const int total = tiles_m * tiles_n;
-    const int slots = device_cus() * (BM == 64 ? 2 : 1);
+    const int slots = (p.grid_cus > 0 ? p.grid_cus : device_cus()) * (BM == 64 ? 2 : 1);
     const int grid = total < slots ? total : slots;
     hipLaunchKernelGGL((gemm_persist_kernel<V, BM>), dim3((unsigned)grid), dim3(512), lds, s, p, total, tiles_m,
                        tiles_n);
@@ -569,7 +569,7 @@ static int dispatch_general(GemmParams &p, int BM, hipStream_t s) {
 int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
                 const float *A, int64_t lda, const float *B, int64_t ldb,
                 float beta, float *C, int64_t ldc, void *ws, size_t ws_bytes,
-                hipStream_t stream, int flags) {
+                hipStream_t stream, int flags, int grid_cus) {
     if (M == 0 || N == 0) return BFX_OK;
     int BM, BN;
     tile_for(M, N, BM, BN);
@@ -584,6 +584,7 @@ int gemm_launch(int variant, int64_t M, int64_t N, int64_t K, float alpha,
     p.vecA = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
     p.vecB = ((uintptr_t)B % 16 == 0) && (ldb % 4 == 0);
     p.fp64_sum = (flags & BFX_GEMM_FP64_SUM) ? 1 : 0;
+    p.grid_cus = grid_cus;
     const int groups = split_groups(p.splits);
     if (p.splits > 1 && (size_t)(p.splits + groups) * 2 * M * N * sizeof(float) > ws_bytes)
         return -14;

@@ -94,6 +94,7 @@ struct GemmParams {
     float *partial;       // [splits][2][M][N] when splits > 1
     int vecA, vecB;       // 16-byte loads allowed
     int fp64_sum = 0;     // X = hi + lo and the alpha/beta epilogue in FP64, one rounding
+    int grid_cus = 0;     // compute units the launch may use (0: all); host side only
 };
 
 constexpr int BK = 32;

@@ -19,6 +19,9 @@
 //      index order; column-oriented steps over register-resident rows).
 //   4. A22 -= L21 x U12 with the split-BF16 GEMM (alpha = -1, beta = 1).
 #include <climits>
+#include <mutex>
+
+#include <hip/hip_ext.h>
 
 #include "common.hpp"
 
@@ -460,12 +463,12 @@ constexpr int TRSM_COLS = 64;
 constexpr int TRSM_LD = PNB + 4;
 constexpr size_t TRSM_LDS = (size_t)PNB * TRSM_LD * sizeof(float);
 __global__ void __launch_bounds__(256, 2)
-trsm_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w) {
+trsm_kernel(float *A, int64_t lda, int64_t c0, int64_t c1, int64_t j, int w) {
     extern __shared__ __align__(16) float Lt[];   // Lt[p * TRSM_LD + i] = L11[i][p]
     __shared__ float xb[TRSM_COLS];
     const int t = threadIdx.x, c = t & 63, h = t >> 6;
-    const int64_t col = j + w + (int64_t)blockIdx.x * TRSM_COLS + c;
-    const bool ok = col < n;
+    const int64_t col = c0 + (int64_t)blockIdx.x * TRSM_COLS + c;   // columns [c0, c1)
+    const bool ok = col < c1;
     for (int e = t; e < PNB * PNB; e += 256) {
         const int i = e / PNB, p = e % PNB;
         Lt[p * TRSM_LD + i] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
@@ -503,53 +506,201 @@ trsm_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w) {
     }
 }
 
-static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv,
-                          int32_t *info, void *ws, hipStream_t s) {
-    LuWs w;
-    lu_ws_layout(&w, ws);
+static int set_trsm_attr() {
     static bool attr = false;
     if (!attr) {
         BFX_HIP(hipFuncSetAttribute((const void *)trsm_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)TRSM_LDS));
         attr = true;
     }
+    return BFX_OK;
+}
+
+// U12 = L11^{-1} A12 and A22 -= L21 U12 for the columns [c0, c1) of the
+// trailing matrix of the panel at j (rows j + jb .. n-1).
+static int lu_update_cols(int variant, int64_t n, float *A, int64_t lda, int64_t j, int jb, int64_t c0,
+                          int64_t c1, hipStream_t s, int cus) {
+    if (c1 <= c0) return BFX_OK;
+    hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(c1 - c0, TRSM_COLS)), dim3(256), TRSM_LDS, s,
+                       A, lda, c0, c1, j, jb);
+    BFX_LAUNCH_CHECK("trsm_kernel");
+    const int64_t rows = n - j - jb;
+    if (rows <= 0) return BFX_OK;
+    const float *A21 = A + (j + jb) * lda + j;
+    const float *A12 = A + j * lda + c0;
+    float *A22 = A + (j + jb) * lda + c0;
+    // variant 0: the plain FP32 vector GEMM (an SGETRF built on SGEMM, the
+    // comparator of Sec. IV-A's LU experiment)
+    return variant == 0 ? bfx_sgemm_fp32(rows, c1 - c0, jb, -1.0f, A21, lda, A12, lda, 1.0f, A22, lda, nullptr, 0,
+                                         (void *)s)
+                        : gemm_launch(variant, rows, c1 - c0, jb, -1.0f, A21, lda, A12, lda, 1.0f, A22, lda,
+                                      nullptr, 0, s, 0, cus);
+}
+
+static PanelArgs panel_args(float *A, int64_t lda, int64_t n, int64_t j, int32_t *ipiv, int32_t *info,
+                            const LuWs &w) {
+    PanelArgs pa;
+    pa.A = A; pa.lda = lda; pa.n = n; pa.j = j; pa.m = n - j;
+    pa.w = (int)((n - j < PNB) ? n - j : PNB);
+    pa.G = (int)ceil_div(n - j, PROWS);
+    pa.ipiv = ipiv; pa.info = info; pa.ws = w;
+    return pa;
+}
+
+static int launch_laswp(float *A, int64_t lda, int64_t n, int64_t j, int jb, const int32_t *ipiv, hipStream_t s) {
+    const int64_t others = n - jb;
+    if (others <= 0) return BFX_OK;
+    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_THREADS), 0, s, A, lda,
+                       n, j, jb, ipiv);
+    BFX_LAUNCH_CHECK("laswp_kernel");
+    return BFX_OK;
+}
+
+// One stream: panel (cooperative launch over the whole device), row
+// interchanges, U12, trailing update, in order.
+static int lu_serial(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv, int32_t *info,
+                     const LuWs &w, hipStream_t s) {
+    for (int64_t j = 0; j < n; j += PNB) {
+        PanelArgs pa = panel_args(A, lda, n, j, ipiv, info, w);
+        void *args[] = {&pa};
+        BFX_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(pa.G), dim3(PROWS), args, 0, s));
+        int rc = launch_laswp(A, lda, n, j, pa.w, ipiv, s);
+        if (rc != BFX_OK) return rc;
+        rc = lu_update_cols(variant, n, A, lda, j, pa.w, j + pa.w, n, s, 0);
+        if (rc != BFX_OK) return rc;
+    }
+    return BFX_OK;
+}
+
+// Depth-1 look-ahead over two CU-masked streams: the panel stream runs on
+// PANEL_CUS compute units (the first PANEL_CUS bits of the mask, which the
+// driver spreads evenly over the XCDs), the update stream on all the others.
+// After panel k, the update stream applies its interchanges, then updates the
+// next block column first; the panel stream factors that column (panel k+1)
+// while the update stream updates the rest of the trailing matrix.  The
+// arithmetic and its order are those of the serial schedule (each trailing
+// element sees the same updates in the same order), so the factors are the
+// same bits.  The panel launch is a plain one: its G <= PANEL_CUS workgroups
+// each fill a compute unit and nothing else runs on those units, so all of
+// them are resident together.  A panel too tall for PANEL_CUS units runs on
+// the update stream, in order.  Streams and events are created once per
+// device and kept for the life of the process; one mutex per device orders
+// concurrent callers' launch sequences.
+constexpr int PANEL_CUS = 32;
+struct LuStreams {
+    bool tried = false, ok = false;
+    hipStream_t sp = nullptr, sg = nullptr;
+    hipEvent_t e0 = nullptr, en = nullptr, ep = nullptr, ef = nullptr;
+    int update_cus = 0;
+    std::mutex mu;
+};
+static LuStreams g_lu_streams[64];
+static std::mutex g_lu_streams_mu;
+
+static LuStreams *lu_streams() {
+    static const bool off = [] {
+        const char *e = getenv("BFX_LU_LOOKAHEAD");
+        return e && e[0] == '0';
+    }();
+    if (off) return nullptr;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    LuStreams &L = g_lu_streams[dev];
+    std::lock_guard<std::mutex> lock(g_lu_streams_mu);
+    if (!L.tried) {
+        L.tried = true;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 2 * PANEL_CUS || cus > 1024)
+            return nullptr;
+        uint32_t mp[32] = {0}, mg[32] = {0};
+        const int words = (cus + 31) / 32;
+        for (int c = 0; c < cus; ++c) {
+            if (c < PANEL_CUS) mp[c / 32] |= 1u << (c % 32);
+            else mg[c / 32] |= 1u << (c % 32);
+        }
+        bool ok = hipExtStreamCreateWithCUMask(&L.sp, words, mp) == hipSuccess &&
+                  hipExtStreamCreateWithCUMask(&L.sg, words, mg) == hipSuccess;
+        for (hipEvent_t *e : {&L.e0, &L.en, &L.ep, &L.ef})
+            ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+        (void)hipGetLastError();
+        L.update_cus = cus - PANEL_CUS;
+        L.ok = ok;
+    }
+    return L.ok ? &L : nullptr;
+}
+
+static int lu_lookahead(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv, int32_t *info,
+                        const LuWs &w, hipStream_t s, LuStreams &L) {
+    std::lock_guard<std::mutex> lock(L.mu);
+    hipStream_t sp = L.sp, sg = L.sg;
+    const int ucus = L.update_cus;
+    // both streams start after the work already queued on s
+    BFX_HIP(hipEventRecord(L.e0, s));
+    BFX_HIP(hipStreamWaitEvent(sp, L.e0, 0));
+    BFX_HIP(hipStreamWaitEvent(sg, L.e0, 0));
+    // panel at j: on the panel stream when it fits there (its event ep is
+    // recorded; the caller queues the update stream's wait for it), else on
+    // the update stream
+    auto panel_small = [&](int64_t j) { return ceil_div(n - j, PROWS) <= PANEL_CUS; };
+    auto launch_panel = [&](int64_t j) -> int {
+        PanelArgs pa = panel_args(A, lda, n, j, ipiv, info, w);
+        hipStream_t ps = sp;
+        if (pa.G > PANEL_CUS) {
+            if (pa.G > ucus) return -2;
+            ps = sg;
+        }
+        hipLaunchKernelGGL(panel_kernel, dim3(pa.G), dim3(PROWS), 0, ps, pa);
+        BFX_LAUNCH_CHECK("panel_kernel");
+        if (ps == sp) BFX_HIP(hipEventRecord(L.ep, sp));
+        return BFX_OK;
+    };
+    int rc = launch_panel(0);
+    if (rc == BFX_OK && panel_small(0)) BFX_HIP(hipStreamWaitEvent(sg, L.ep, 0));
+    for (int64_t j = 0; j < n && rc == BFX_OK; j += PNB) {
+        const int jb = (int)((n - j < PNB) ? n - j : PNB);
+        rc = launch_laswp(A, lda, n, j, jb, ipiv, sg);
+        if (rc != BFX_OK) break;
+        const int64_t c0 = j + jb;
+        if (c0 >= n) break;
+        const int64_t c1 = (n - c0 < PNB) ? n : c0 + PNB;
+        // the next block column first
+        rc = lu_update_cols(variant, n, A, lda, j, jb, c0, c1, sg, ucus);
+        if (rc != BFX_OK) break;
+        if (panel_small(c0)) {
+            // its panel on the panel stream, beside the rest of the update
+            BFX_HIP(hipEventRecord(L.en, sg));
+            BFX_HIP(hipStreamWaitEvent(sp, L.en, 0));
+            rc = launch_panel(c0);
+            if (rc != BFX_OK) break;
+            rc = lu_update_cols(variant, n, A, lda, j, jb, c1, n, sg, ucus);
+            if (rc != BFX_OK) break;
+            BFX_HIP(hipStreamWaitEvent(sg, L.ep, 0));
+        } else {
+            rc = lu_update_cols(variant, n, A, lda, j, jb, c1, n, sg, ucus);
+            if (rc != BFX_OK) break;
+            rc = launch_panel(c0);
+        }
+    }
+    if (rc != BFX_OK) return rc;
+    BFX_HIP(hipEventRecord(L.ef, sp));
+    BFX_HIP(hipStreamWaitEvent(s, L.ef, 0));
+    BFX_HIP(hipEventRecord(L.ef, sg));
+    BFX_HIP(hipStreamWaitEvent(s, L.ef, 0));
+    return BFX_OK;
+}
+
+static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t *ipiv,
+                          int32_t *info, void *ws, hipStream_t s) {
+    LuWs w;
+    lu_ws_layout(&w, ws);
+    int rc = set_trsm_attr();
+    if (rc != BFX_OK) return rc;
     BFX_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(zero_u64, dim3(64), dim3(256), 0, s, w.cand, 2 * MAX_G * CW);
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, s, w.diag, 2 * CW);
     BFX_LAUNCH_CHECK("zero_u64");
-    for (int64_t j = 0; j < n; j += PNB) {
-        const int jb = (int)((n - j < PNB) ? n - j : PNB);
-        PanelArgs pa;
-        pa.A = A; pa.lda = lda; pa.n = n; pa.j = j; pa.m = n - j; pa.w = jb;
-        pa.G = (int)ceil_div(n - j, PROWS);
-        pa.ipiv = ipiv; pa.info = info; pa.ws = w;
-        void *args[] = {&pa};
-        BFX_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(pa.G), dim3(PROWS),
-                                           args, 0, s));
-        const int64_t others = n - jb;
-        if (others > 0) {
-            hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_THREADS),
-                               0, s, A, lda, n, j, jb, ipiv);
-            BFX_LAUNCH_CHECK("laswp_kernel");
-        }
-        const int64_t rest = n - j - jb;
-        if (rest <= 0) continue;
-        hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(rest, TRSM_COLS)), dim3(256), TRSM_LDS, s,
-                           A, lda, n, j, jb);
-        BFX_LAUNCH_CHECK("trsm_kernel");
-        float *A21 = A + (j + jb) * lda + j;
-        float *A12 = A + j * lda + (j + jb);
-        float *A22 = A + (j + jb) * lda + (j + jb);
-        // variant 0: the plain FP32 vector GEMM (an SGETRF built on SGEMM, the
-        // comparator of Sec. IV-A's LU experiment)
-        const int rc = variant == 0
-                           ? bfx_sgemm_fp32(rest, rest, jb, -1.0f, A21, lda, A12, lda, 1.0f, A22, lda,
-                                            nullptr, 0, (void *)s)
-                           : gemm_launch(variant, rest, rest, jb, -1.0f, A21, lda, A12, lda, 1.0f,
-                                         A22, lda, nullptr, 0, s);
-        if (rc != BFX_OK) return rc;
-    }
-    return BFX_OK;
+    if (LuStreams *L = lu_streams()) return lu_lookahead(variant, n, A, lda, ipiv, info, w, s, *L);
+    return lu_serial(variant, n, A, lda, ipiv, info, w, s);
 }
 
 }  // namespace bfx
