@@ -34,16 +34,16 @@ constexpr int MAX_G = 256;   // co-resident workgroups the panel may use
 constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
 
 // Column exchange words: {tag << 32 | 32-bit payload}, tag = global column
-// index + 1, two slots alternating with the column's parity.  A slot holds a
-// row's register image as it was before the previous column's elimination
-// (words 0..PNB-1), that elimination's multiplier (word PNB) and, for
-// candidates, the panel row index (word PNB + 1; -1: no candidate).
+// index + 1, two slots per workgroup alternating with the column's parity.
+// A slot holds the workgroup's candidate row: its register image as it was
+// before the previous column's elimination (words 0..PNB-1), that
+// elimination's multiplier (word PNB) and the row's position in the panel
+// (word PNB + 1; -1: no candidate).
 constexpr int CW = PNB + 4;      // words per slot
 constexpr int XCH = PROWS / 16;  // candidates read per round (16 threads each)
 constexpr int CRS = PNB + 4;     // LDS row stride of read candidates
 struct LuWs {
     uint64_t *cand;     // [2][MAX_G][CW] the workgroups' candidate rows
-    uint64_t *diag;     // [2][CW] row c
 };
 
 size_t lu_ws_layout(LuWs *w, void *base) {
@@ -54,12 +54,7 @@ size_t lu_ws_layout(LuWs *w, void *base) {
         return o;
     };
     const size_t o_cand = take(sizeof(uint64_t) * 2 * MAX_G * CW);
-    const size_t o_diag = take(sizeof(uint64_t) * 2 * CW);
-    if (w && base) {
-        char *b = (char *)base;
-        w->cand = (uint64_t *)(b + o_cand);
-        w->diag = (uint64_t *)(b + o_diag);
-    }
+    if (w && base) w->cand = (uint64_t *)((char *)base + o_cand);
     return off;
 }
 
@@ -105,6 +100,35 @@ __device__ __forceinline__ uint32_t wave_max_key(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
+// Wave-wide minimum of a 32-bit value, returned uniform (the same DPP steps).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+    uint32_t y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);
+    x = x < y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);
+    x = x < y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x141, 0xF, 0xF, false);
+    x = x < y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x140, 0xF, 0xF, false);
+    x = x < y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x142, 0xA, 0xF, false);
+    x = x < y ? x : y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x143, 0xC, 0xF, false);
+    x = x < y ? x : y;
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// The lane holding the largest key, the lowest position among equal keys:
+// returns that lane (uniform) and the maximum key in m.  Lanes whose key
+// is 0 take no part (m = 0 then).
+__device__ __forceinline__ int best_lane(uint32_t key, uint32_t pos, uint32_t &m) {
+    m = wave_max_key(key);
+    const uint64_t ties = __ballot(key == m);
+    if (__popcll(ties) == 1) return __builtin_ctzll(ties);
+    const uint32_t pm = wave_min_u32(key == m ? pos : 0xffffffffu);
+    return __builtin_ctzll(__ballot(key == m && pos == pm));
+}
+
 // lowest lane whose predicate holds (64 if none)
 __device__ __forceinline__ int first_lane(bool pred) {
     const uint64_t b = __ballot(pred);
@@ -131,8 +155,15 @@ __device__ __forceinline__ bool wait_expired(unsigned &spins, int32_t *info) {
 // registers between are padding.  An elimination shifts the row left by one
 // (r[i] = r[i+1] - l U[i+1] on the live part, a plain shift elsewhere) and
 // puts the new multiplier in r[PNB-1]; all register indices are static.  Rows
-// that reach the diagonal freeze.  Two rows that swap at column c were both
-// shifted c times, so their register images are exchanged as they are.
+// that reach the diagonal freeze.
+//
+// Interchanges move labels, not data: each thread carries the position of
+// the row it holds (pos).  When row p is chosen as pivot of column c, the
+// thread holding it takes position c and freezes, and the thread holding
+// position c takes position p; both images were shifted c times, so each
+// thread's registers are exactly the row at its new position.  Rows go to
+// their final positions at the write-back.  Ties between equal pivot
+// magnitudes go to the lowest position, as ISAMAX.
 //
 // The elimination of column c-1 is deferred past the pivot search of column
 // c: once pivot c-1 is known, every row computes its multiplier and only its
@@ -140,21 +171,20 @@ __device__ __forceinline__ bool wait_expired(unsigned &spins, int32_t *info) {
 // workgroup's candidate is published as it was before that elimination,
 // with its multiplier, and every reader applies the elimination itself while
 // storing it (the same FMA, so the same bits); the owner's full-row update
-// runs while the exchange is in flight.  Row c is published the same way by
-// the wave holding it, as soon as its multiplier is known.
+// runs while the exchange is in flight.
 //
-// Per column, two workgroup barriers.  Before the first, every wave has the
-// pivot keys of its rows (DPP maximum, lowest lane on ties) in LDS; after it
-// every wave forms the workgroup's candidate from the eight wave maxima and
-// the wave holding it publishes it as words tagged with the column (a reader
+// Per column, two workgroup barriers.  Before the first, every wave has its
+// best pivot key (DPP maximum) and that row's position in LDS; after it every
+// wave forms the workgroup's candidate from the eight wave maxima and the
+// wave holding it publishes it as words tagged with the column (a reader
 // that sees the column's tag in a word has that word's value, so no fence
 // orders the stores).  Every thread then reads its share of all candidates
 // (16 threads per candidate, one 128-byte segment per load instruction and
-// candidate) and threads < PNB read row c, each polling its own words.
-// After the second barrier every wave picks the same pivot.
+// candidate), polling its own words.  After the second barrier every wave
+// picks the same pivot.
 __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
-    // staged rows for publishing (image, multiplier): the candidate, row c
-    __shared__ __align__(16) float rowbuf[PNB + 4], diagbuf[PNB + 4];
+    // the workgroup's candidate staged for publishing (image, multiplier)
+    __shared__ __align__(16) float rowbuf[PNB + 4];
     // candidate rows read from the exchange (after the elimination), element
     // q of candidate k at crow[.][k][3 + q], so that elements 1, 5, 9, ...
     // start 16-byte groups; two buffers alternate with the column, since
@@ -162,21 +192,19 @@ __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
     // holds the best row of earlier rounds when there are several.
     __shared__ __align__(16) float crow[2][XCH][CRS];
     __shared__ __align__(16) float ubuf[2][CRS];
-    __shared__ __align__(16) float D[PNB];   // row c before the interchange
     __shared__ int cidx[XCH];
-    __shared__ uint32_t red_key[PROWS / 64];
+    __shared__ uint32_t red_key[PROWS / 64], red_pos[PROWS / 64];
     __shared__ int red_lane[PROWS / 64];
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int w = a.w;
     const int row0 = g * PROWS;                    // first panel row of this workgroup
-    const int pr = row0 + t;                       // panel row owned by this thread
-    const int wrow0 = row0 + 64 * wave;            // first row of this wave
-    const bool own = pr < a.m;
+    const bool own = row0 + t < a.m;               // this thread holds a row
+    int pos = row0 + t;                            // position of the row it holds
     float *Ag = a.A + a.j * a.lda + a.j;           // panel origin
     float r[PNB];
 #pragma unroll
-    for (int k = 0; k < PNB; ++k) r[k] = (own && k < w) ? Ag[(int64_t)pr * a.lda + k] : 0.0f;
+    for (int k = 0; k < PNB; ++k) r[k] = (own && k < w) ? Ag[(int64_t)pos * a.lda + k] : 0.0f;
     float l = 0.0f;   // this row's multiplier of the deferred elimination
 
     // the elimination of one column on this thread's row: multiplier l,
@@ -206,38 +234,18 @@ __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
         }
         r[PNB - 1] = l;
     };
-    // pivot keys of column c from the entries v, this wave's maximum to LDS
+    // pivot keys of column c from the entries v; this wave's best to LDS
     auto wave_keys = [&](int c, float v) __attribute__((always_inline)) {
-        const uint32_t key = (own && pr >= c) ? pivot_key(v) : 0u;
-        const uint32_t m = wave_max_key(key);
-        const int lw = first_lane(key == m);
-        if (lane == 0) { red_key[wave] = m; red_lane[wave] = lw; }
-    };
-    // a wave publishes a row staged in buf (image and multiplier) to dst
-    auto publish = [&](const float *buf, uint64_t *dst, uint32_t tag) __attribute__((always_inline)) {
-        const uint64_t tg = (uint64_t)tag << 32;
-        __hip_atomic_store(dst + lane, tg | __float_as_uint(buf[lane]), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(dst + lane + 64, tg | __float_as_uint(buf[lane + 64]), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        if (lane == 0)
-            __hip_atomic_store(dst + PNB, tg | __float_as_uint(buf[PNB]), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    };
-    // the wave holding row c stages and publishes it (image before the
-    // deferred elimination, multiplier l)
-    auto publish_diag = [&](int c) __attribute__((always_inline)) {
-        if (c >= wrow0 && c < wrow0 + 64) {   // uniform over the wave
-            if (pr == c) {
-#pragma unroll
-                for (int k = 0; k < PNB; ++k) diagbuf[k] = r[k];
-                diagbuf[PNB] = l;
-            }
-            publish(diagbuf, a.ws.diag + (c & 1) * CW, (uint32_t)(a.j + c + 1));
+        const uint32_t key = (own && pos >= c) ? pivot_key(v) : 0u;
+        uint32_t m;
+        const int lw = best_lane(key, (uint32_t)pos, m);
+        if (lane == 0) {
+            red_key[wave] = m;
+            red_pos[wave] = (uint32_t)__builtin_amdgcn_readlane(pos, lw);
+            red_lane[wave] = lw;
         }
     };
 
-    publish_diag(0);
     wave_keys(0, r[0]);
     const float *Up = nullptr;   // pivot row of the previous column (LDS), U[k] at Up[3 + k]
     for (int c = 0; c < w; ++c) {
@@ -245,31 +253,41 @@ __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
         const uint32_t tag = (uint32_t)(a.j + c + 1);   // never 0 (exchange words start zeroed)
         const int live_p = w - c + 1;   // live width of the deferred elimination (column c-1)
         __syncthreads();
-        // ---- the workgroup's candidate: the best of the wave maxima (waves
-        // own increasing rows, so the lowest wave wins ties)
+        // ---- the workgroup's candidate: the best of the wave maxima
         {
-            const uint32_t wk = lane < PROWS / 64 ? red_key[lane] : 0u;
-            const uint32_t M = wave_max_key(wk);
-            const int W = first_lane(lane < PROWS / 64 && wk == M);
-            const int L = red_lane[W < PROWS / 64 ? W : 0];
-            if (wave == (M ? W : 0)) {
+            const bool lw8 = lane < PROWS / 64;
+            const uint32_t wk = lw8 ? red_key[lane] : 0u;
+            const uint32_t wp = lw8 ? red_pos[lane] : 0xffffffffu;
+            uint32_t M;
+            const int W = best_lane(wk, wp, M);
+            const int Wc = W < PROWS / 64 ? W : 0;
+            const int L = red_lane[Wc];
+            const int cand = M ? (int)red_pos[Wc] : -1;
+            if (wave == (M ? Wc : 0)) {
                 if (M && lane == L) {
 #pragma unroll
                     for (int k = 0; k < PNB; ++k) rowbuf[k] = r[k];
                     rowbuf[PNB] = l;
                 }
+                const uint64_t tg = (uint64_t)tag << 32;
                 uint64_t *slot = a.ws.cand + (size_t)(par * MAX_G + g) * CW;
-                publish(rowbuf, slot, tag);
-                if (lane == 0)
-                    __hip_atomic_store(slot + PNB + 1, ((uint64_t)tag << 32) | (uint32_t)(M ? wrow0 - 64 * wave + 64 * W + L : -1),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(slot + lane, tg | __float_as_uint(rowbuf[lane]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(slot + lane + 64, tg | __float_as_uint(rowbuf[lane + 64]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) {
+                    __hip_atomic_store(slot + PNB, tg | __float_as_uint(rowbuf[PNB]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(slot + PNB + 1, tg | (uint32_t)cand, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
         // ---- the deferred elimination of column c-1 on this thread's row
-        if (c > 0 && own && pr >= c) eliminate(Up + 4, live_p);
-        // ---- read every candidate and row c, eliminating column c-1 on the
-        // way (word q + 1 of the slot gives element q; the last element is
-        // the multiplier itself); then pick the pivot
+        if (c > 0 && own && pos >= c) eliminate(Up + 4, live_p);
+        // ---- read every candidate, eliminating column c-1 on the way (word
+        // q + 1 of the slot gives element q; the last element is the
+        // multiplier itself); then pick the pivot
         uint32_t best = 0;
         int bidx = -1;
         const float *Uc = crow[par][0];
@@ -303,79 +321,64 @@ __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
                 }
                 if (sub == 0) cidx[kl] = (int)(uint32_t)wi;
             }
-            if (k0 == 0 && t < PNB) {
-                const uint64_t *src = a.ws.diag + par * CW;
-                uint64_t dv = 0, dl = 0;
-                for (unsigned spins = 0;;) {
-                    dv = __hip_atomic_load(src + t + o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    dl = __hip_atomic_load(src + PNB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (((uint32_t)(dv >> 32) == tag && (uint32_t)(dl >> 32) == tag) || wait_expired(spins, a.info))
-                        break;
-                }
-                float x = __uint_as_float((uint32_t)dv);
-                if (c > 0 && t < live_p - 1) x = fmaf(-__uint_as_float((uint32_t)dl), Up[4 + t], x);
-                D[t] = x;
-            }
             __syncthreads();
-            // every wave: the best candidate of this round (lowest k on ties:
-            // workgroups own increasing rows), kept if it beats earlier rounds
-            uint32_t key = 0;
-            if (lane < XCH && k0 + lane < a.G && cidx[lane] >= 0) key = pivot_key(crow[par][lane][3]);
-            const uint32_t m = wave_max_key(key);
-            const int kw = first_lane(key == m);
+            // every wave: the best candidate of this round, kept if it beats
+            // earlier rounds (which hold lower positions on equal keys)
+            uint32_t key = 0, cp = 0xffffffffu;
+            if (lane < XCH && k0 + lane < a.G && cidx[lane] >= 0) {
+                key = pivot_key(crow[par][lane][3]);
+                cp = (uint32_t)cidx[lane];
+            }
+            uint32_t m;
+            const int kw = best_lane(key, cp, m);
+            const int kwc = kw < XCH ? kw : 0;
             if (a.G <= XCH) {
                 best = m;
-                bidx = m ? cidx[kw] : -1;
-                Uc = crow[par][kw];
+                bidx = m ? cidx[kwc] : -1;
+                Uc = crow[par][kwc];
             } else {
-                if (k0 == 0 || m > best) {
+                const bool better = k0 == 0 || m > best || (m == best && m && cidx[kwc] < bidx);
+                if (better) {
                     best = m;
-                    bidx = m ? cidx[kw] : -1;
-                    if (t < PNB) ubuf[par][3 + t] = crow[par][kw][3 + t];
+                    bidx = m ? cidx[kwc] : -1;
+                    if (t < PNB) ubuf[par][3 + t] = crow[par][kwc][3 + t];
                 }
                 Uc = ubuf[par];
                 __syncthreads();   // ubuf complete; crow free for the next round
             }
         }
-        // a valid pivot row is >= c; anything else only follows an expired wait
+        // a valid pivot position is >= c; anything else only follows an expired wait
         const int p = (bidx >= c && bidx < a.m) ? bidx : c;
         const float piv = Uc[3];
         if (g == 0 && t == 0) {
             a.ipiv[a.j + c] = (int32_t)(a.j + p);
             if (piv == 0.0f && *a.info == 0) *a.info = (int32_t)(a.j + c + 1);  // -1 (expired wait) is kept
         }
-        // ---- interchange rows c and p; the multipliers of the rows below
-        // and their entries in column c+1 (the rest of the elimination is
-        // deferred)
+        // ---- interchange positions c and p (labels); the multipliers of
+        // the rows below and their entries in column c+1 (the rest of the
+        // elimination is deferred)
         float v1 = 0.0f;
-        if (own && pr >= c) {
-            if (pr == p && p != c) {
-#pragma unroll
-                for (int k = 0; k < PNB; ++k) r[k] = D[k];
-            }
-            if (pr == c) {
-#pragma unroll
-                for (int k = 0; k < PNB; ++k) r[k] = Uc[3 + k];
-            } else {
+        if (own && pos >= c) {
+            if (pos == p) pos = c;
+            else if (pos == c) pos = p;
+            if (pos > c) {
                 l = r[0];
                 if (piv != 0.0f) l = l / piv;
                 v1 = (w - c > 1) ? fmaf(-l, Uc[4], r[1]) : r[1];
             }
         }
         Up = Uc;
-        if (c + 1 < w) {
-            publish_diag(c + 1);
-            wave_keys(c + 1, v1);
-        }
+        if (c + 1 < w) wave_keys(c + 1, v1);
     }
     // the last column's elimination
-    if (own && pr >= w) eliminate(Up + 4, 1);
+    if (own && pos >= w) eliminate(Up + 4, 1);
 
-    // ---- write back: register k of a row shifted s times holds column s + k
-    // (k < w - s) or multiplier k - (PNB - s) (k >= PNB - s)
+    // ---- write back to the row's final position: register k of a row
+    // shifted s times holds column s + k (k < w - s) or multiplier
+    // k - (PNB - s) (k >= PNB - s)
     if (own) {
-        const int sh = (pr < w) ? pr : w;
-        float *Ar = Ag + (int64_t)pr * a.lda;
+        const int sh = (pos < w) ? pos : w;
+        float *Ar = Ag + (int64_t)pos * a.lda;
 #pragma unroll
         for (int k = 0; k < PNB; ++k) {
             int col = -1;
@@ -453,56 +456,74 @@ laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *
 }
 
 // U12 = L11^{-1} A12 (unit lower L11, jb x jb).  Column-oriented forward
-// substitution: at step p the now final row p of X is broadcast and every row
+// substitution: at step p the now final x_p is broadcast and every row
 // i > p is updated, x_i = fma(-L_ip, x_p, x_i) -- for each element the same
-// FMA chain, in increasing p, as the row-oriented algorithm.  A 256-thread
-// workgroup owns 64 columns; wave h keeps rows 32h .. 32h+31 of its column in
-// registers, L11 is staged transposed in LDS (rows padded to 132 floats).
-// Steps are unrolled in blocks of 32 so that register indices are static.
-constexpr int TRSM_COLS = 64;
-constexpr int TRSM_LD = PNB + 4;
-constexpr size_t TRSM_LDS = (size_t)PNB * TRSM_LD * sizeof(float);
-__global__ void __launch_bounds__(256, 2)
+// FMA chain, in increasing p, as the row-oriented algorithm.  One wave per
+// column, lane l holding rows l and l + 64: x_p is read from its lane
+// (readlane) as soon as the previous step has made it final, so the solve
+// has no barrier.  A 1024-thread workgroup owns 16 columns; L11 is staged
+// transposed in LDS (rows padded to 129 floats: conflict-free both ways),
+// the columns go through LDS so that global loads and stores are row
+// segments.
+constexpr int TRSM_COLS = 16;
+constexpr int TRSM_LD = PNB + 1;
+constexpr size_t TRSM_LDS = (size_t)(PNB + TRSM_COLS) * TRSM_LD * sizeof(float);
+__global__ void __launch_bounds__(1024)
 trsm_kernel(float *A, int64_t lda, int64_t c0, int64_t c1, int64_t j, int w) {
-    extern __shared__ __align__(16) float Lt[];   // Lt[p * TRSM_LD + i] = L11[i][p]
-    __shared__ float xb[TRSM_COLS];
-    const int t = threadIdx.x, c = t & 63, h = t >> 6;
-    const int64_t col = c0 + (int64_t)blockIdx.x * TRSM_COLS + c;   // columns [c0, c1)
-    const bool ok = col < c1;
-    for (int e = t; e < PNB * PNB; e += 256) {
+    extern __shared__ float tsm[];
+    float *Lt = tsm;                    // Lt[p * TRSM_LD + i] = L11[i][p] for p < i < w, else 0
+    float *Xs = tsm + PNB * TRSM_LD;    // Xs[c * TRSM_LD + i] = A12[i][c]
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t cb = c0 + (int64_t)blockIdx.x * TRSM_COLS;   // columns [c0, c1)
+    for (int e = t; e < PNB * PNB; e += 1024) {
         const int i = e / PNB, p = e % PNB;
         Lt[p * TRSM_LD + i] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
     }
-    float x[32];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        const int i = 32 * h + k;
-        x[k] = (ok && i < w) ? A[(j + i) * lda + col] : 0.0f;
+    for (int e = t; e < PNB * TRSM_COLS; e += 1024) {
+        const int i = e / TRSM_COLS, c = e % TRSM_COLS;
+        Xs[c * TRSM_LD + i] = (i < w && cb + c < c1) ? A[(j + i) * lda + cb + c] : 0.0f;
     }
     __syncthreads();
-    for (int hp = 0; hp < 4; ++hp) {
-        if (32 * hp >= w - 1) break;   // uniform
+    float x0 = Xs[wv * TRSM_LD + lane], x1 = Xs[wv * TRSM_LD + lane + 64];
+    // all PNB - 1 steps, branch-free: rows at or beyond w are zero padding
+    // (never stored), so the steps past w - 1 change no stored row
 #pragma unroll
-        for (int kp = 0; kp < 32; ++kp) {
-            const int p = 32 * hp + kp;
-            if (h == hp) xb[c] = x[kp];
-            __syncthreads();
-            const float xp = xb[c];
-            const float *lp = Lt + p * TRSM_LD + 32 * h;   // L11[32h + k][p]
-            if (h > hp) {
+    for (int p0 = 0; p0 < 64; p0 += 8) {            // x_p in lane p's x0
+        float la[8], lb[8];
 #pragma unroll
-                for (int k = 0; k < 32; ++k) x[k] = fmaf(-lp[k], xp, x[k]);
-            } else if (h == hp) {
+        for (int q = 0; q < 8; ++q) {
+            la[q] = Lt[(p0 + q) * TRSM_LD + lane];
+            lb[q] = Lt[(p0 + q) * TRSM_LD + lane + 64];
+        }
 #pragma unroll
-                for (int k = kp + 1; k < 32; ++k) x[k] = fmaf(-lp[k], xp, x[k]);
-            }
-            __syncthreads();
+        for (int q = 0; q < 8; ++q) {
+            const int p = p0 + q;
+            const float xp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x0), p));
+            const float y0 = fmaf(-la[q], xp, x0);
+            x0 = (lane > p) ? y0 : x0;
+            x1 = fmaf(-lb[q], xp, x1);              // rows lane + 64 > p
         }
     }
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        const int i = 32 * h + k;
-        if (ok && i >= 1 && i < w) A[(j + i) * lda + col] = x[k];
+    for (int p0 = 64; p0 < PNB; p0 += 8) {          // x_p in lane p-64's x1
+        float lb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lb[q] = Lt[(p0 + q) * TRSM_LD + lane + 64];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int p = p0 + q;
+            if (p == PNB - 1) break;
+            const float xp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x1), p - 64));
+            const float y1 = fmaf(-lb[q], xp, x1);
+            x1 = (lane + 64 > p) ? y1 : x1;
+        }
+    }
+    Xs[wv * TRSM_LD + lane] = x0;
+    Xs[wv * TRSM_LD + lane + 64] = x1;
+    __syncthreads();
+    for (int e = t; e < PNB * TRSM_COLS; e += 1024) {
+        const int i = e / TRSM_COLS, c = e % TRSM_COLS;
+        if (i >= 1 && i < w && cb + c < c1) A[(j + i) * lda + cb + c] = Xs[c * TRSM_LD + i];
     }
 }
 
@@ -521,7 +542,7 @@ static int set_trsm_attr() {
 static int lu_update_cols(int variant, int64_t n, float *A, int64_t lda, int64_t j, int jb, int64_t c0,
                           int64_t c1, hipStream_t s, int cus) {
     if (c1 <= c0) return BFX_OK;
-    hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(c1 - c0, TRSM_COLS)), dim3(256), TRSM_LDS, s,
+    hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(c1 - c0, TRSM_COLS)), dim3(1024), TRSM_LDS, s,
                        A, lda, c0, c1, j, jb);
     BFX_LAUNCH_CHECK("trsm_kernel");
     const int64_t rows = n - j - jb;
@@ -697,7 +718,6 @@ static int lu_factor_impl(int variant, int64_t n, float *A, int64_t lda, int32_t
     if (rc != BFX_OK) return rc;
     BFX_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(zero_u64, dim3(64), dim3(256), 0, s, w.cand, 2 * MAX_G * CW);
-    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, s, w.diag, 2 * CW);
     BFX_LAUNCH_CHECK("zero_u64");
     if (LuStreams *L = lu_streams()) return lu_lookahead(variant, n, A, lda, ipiv, info, w, s, *L);
     return lu_serial(variant, n, A, lda, ipiv, info, w, s);

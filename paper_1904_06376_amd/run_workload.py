@@ -3,6 +3,7 @@
     python paper_1904_06376_amd/run_workload.py gemm   --n 8192 --variant 6 --reps 5
     python paper_1904_06376_amd/run_workload.py splitk --variant 6 --reps 10
     python paper_1904_06376_amd/run_workload.py lu     --n 16384 --kappa 1e4
+    python paper_1904_06376_amd/run_workload.py lu     --n 16384 --plain --reps 3
     python paper_1904_06376_amd/run_workload.py batched-gemm --count 4096 --reps 3
     python paper_1904_06376_amd/run_workload.py batched-solve --count 512 --reps 2
     python paper_1904_06376_amd/run_workload.py lu-update --n 16384 --reps 5
@@ -41,6 +42,7 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--count", type=int, default=4096)
+    ap.add_argument("--plain", action="store_true", help="lu: factor a seeded normal matrix, no refinement")
     a = ap.parse_args()
 
     import torch
@@ -62,6 +64,16 @@ def main():
         Z = torch.empty((64, 64), dtype=torch.float32, device=dev)
         for _ in range(a.reps):
             bfx.gemm(a.variant, X, Y, Z)
+    elif a.workload == "lu" and a.plain:
+        # factorisation only, of a seeded normal matrix (no QR-built system)
+        A = torch.from_numpy(workloads.normal((a.n, a.n), 7)).to(dev)
+        for _ in range(a.reps):
+            LU = A.clone()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, ipiv, info = bfx.lu_factor(LU, a.variant)
+            torch.cuda.synchronize()
+            print(f"lu {1e3 * (time.perf_counter() - t1):.1f} ms, info {int(info.item())}", flush=True)
     elif a.workload == "lu":
         A, b = workloads.conditioned_system_torch(a.n, a.kappa, 7, dev)
         for _ in range(a.reps):
