@@ -42,8 +42,13 @@ constexpr unsigned SPIN_LIMIT = 1u << 20;  // ~1 s of polling
 constexpr int CW = PNB + 4;      // words per slot
 constexpr int XCH = PROWS / 16;  // candidates read per round (16 threads each)
 constexpr int CRS = PNB + 4;     // LDS row stride of read candidates
+// The panel's row interchanges as a move list for the rows outside it
+// ([2][2 PNB] ints, by panel parity): entry q < w is the original panel
+// position of the row that ends at position q; entry w + r (r < w) is the
+// final position of original row r when that is >= w, else -1.
 struct LuWs {
     uint64_t *cand;     // [2][MAX_G][CW] the workgroups' candidate rows
+    int32_t *plan;      // [2][2 PNB] move lists
 };
 
 size_t lu_ws_layout(LuWs *w, void *base) {
@@ -54,7 +59,11 @@ size_t lu_ws_layout(LuWs *w, void *base) {
         return o;
     };
     const size_t o_cand = take(sizeof(uint64_t) * 2 * MAX_G * CW);
-    if (w && base) w->cand = (uint64_t *)((char *)base + o_cand);
+    const size_t o_plan = take(sizeof(int32_t) * 2 * 2 * PNB);
+    if (w && base) {
+        w->cand = (uint64_t *)((char *)base + o_cand);
+        w->plan = (int32_t *)((char *)base + o_plan);
+    }
     return off;
 }
 
@@ -373,6 +382,13 @@ __global__ void __launch_bounds__(PROWS, 1) panel_kernel(PanelArgs a) {
     // the last column's elimination
     if (own && pos >= w) eliminate(Up + 4, 1);
 
+    // ---- the move list for the columns outside the panel (a thread's
+    // original position is row0 + t, its final one pos)
+    if (own) {
+        int32_t *plan = a.ws.plan + ((a.j / PNB) & 1) * 2 * PNB;
+        if (pos < w) plan[pos] = row0 + t;
+        if (row0 + t < w) plan[w + row0 + t] = pos >= w ? pos : -1;
+    }
     // ---- write back to the row's final position: register k of a row
     // shifted s times holds column s + k (k < w - s) or multiplier
     // k - (PNB - s) (k >= PNB - s)
@@ -394,49 +410,44 @@ __global__ void __launch_bounds__(256) zero_u64(uint64_t *p, int n) {
 }
 
 // Row interchanges of rows j..j+w-1 (ipiv, applied in order, LAPACK laswp
-// semantics) on every column outside the panel.
-constexpr int SWP_COLS = 64;       // columns per workgroup
-constexpr int SWP_THREADS = 256;   // 4 waves: wave v moves affected rows v, v+4, ...
+// semantics) on columns outside the panel, from the panel's move list: the
+// affected positions are the panel rows 0..w-1 and the rows beyond them that
+// received a panel row.  Every thread of the workgroup calls this; on return
+// dpos[0..nd) are the affected positions and spos[e] is the position whose
+// old row moves to dpos[e].
 constexpr int SWP_MAXR = 2 * PNB;  // affected rows: the panel rows and at most w others
-// The w interchanges compose into one permutation of at most 2w rows: the
-// affected positions are the panel rows 0..w-1 and every pivot row beyond
-// them.  Position p receives the old row sigma(p), sigma = tau_0 o tau_1 o
-// ... o tau_{w-1} (tau_i swaps i and ipiv[i]); each thread evaluates sigma
-// for its positions by applying the transpositions in reverse order.  Then
-// every affected row of the workgroup's 64 columns is loaded (coalesced
-// 256-byte row segments, many loads in flight), all loads complete before
-// the barrier, and the rows are stored at their new positions.
-__global__ void __launch_bounds__(SWP_THREADS)
-laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *ipiv) {
-    __shared__ int sp[PNB], dpos[SWP_MAXR], spos[SWP_MAXR];
-    __shared__ int s_nd;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    for (int i = t; i < w; i += SWP_THREADS) {
-        const int64_t q = ipiv[j + i] - j;  // >= i for a valid factorisation
-        sp[i] = (q >= i && q < n - j) ? (int)q : i;
-    }
-    if (t == 0) s_nd = w;
+__device__ int read_moves(const int32_t *plan, int w, int *dpos, int *spos, int *s_nd) {
+    const int t = threadIdx.x;
+    if (t == 0) *s_nd = w;
     __syncthreads();
     if (t < w) {
         dpos[t] = t;
-        const int q = sp[t];
-        bool first = q >= w;
-        for (int k = 0; k < t && first; ++k) first = sp[k] != q;
-        if (first) dpos[atomicAdd(&s_nd, 1)] = q;
-    }
-    __syncthreads();
-    const int nd = s_nd;
-    for (int e = t; e < nd; e += SWP_THREADS) {
-        int pos = dpos[e];
-        for (int i = w - 1; i >= 0; --i) {
-            const int q = sp[i];
-            pos = (pos == i) ? q : ((pos == q) ? i : pos);
+        spos[t] = plan[t];
+        const int q = plan[w + t];
+        if (q >= w) {
+            const int e = atomicAdd(s_nd, 1);
+            dpos[e] = q;
+            spos[e] = t;
         }
-        spos[e] = pos;
     }
     __syncthreads();
+    return *s_nd;
+}
+
+// The panel's interchanges on the columns [0, x1) and [x2, n).  Every
+// affected row of the workgroup's 64 columns is loaded (coalesced 256-byte
+// row segments, many loads in flight), all loads complete before the
+// barrier, and the rows are stored at their new positions.
+constexpr int SWP_COLS = 64;       // columns per workgroup
+constexpr int SWP_THREADS = 256;   // 4 waves: wave v moves affected rows v, v+4, ...
+__global__ void __launch_bounds__(SWP_THREADS)
+laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *plan, int64_t x1, int64_t x2) {
+    __shared__ int dpos[SWP_MAXR], spos[SWP_MAXR];
+    __shared__ int s_nd;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int nd = read_moves(plan, w, dpos, spos, &s_nd);
     int64_t col = (int64_t)blockIdx.x * SWP_COLS + lane;
-    if (col >= j) col += w;
+    if (col >= x1) col += x2 - x1;
     const bool ok = col < n;
     constexpr int PER = SWP_MAXR / 4;   // rows per wave
     float v[PER];
@@ -455,33 +466,67 @@ laswp_kernel(float *A, int64_t lda, int64_t n, int64_t j, int w, const int32_t *
     }
 }
 
-// U12 = L11^{-1} A12 (unit lower L11, jb x jb).  Column-oriented forward
-// substitution: at step p the now final x_p is broadcast and every row
-// i > p is updated, x_i = fma(-L_ip, x_p, x_i) -- for each element the same
-// FMA chain, in increasing p, as the row-oriented algorithm.  One wave per
-// column, lane l holding rows l and l + 64: x_p is read from its lane
-// (readlane) as soon as the previous step has made it final, so the solve
-// has no barrier.  A 1024-thread workgroup owns 16 columns; L11 is staged
-// transposed in LDS (rows padded to 129 floats: conflict-free both ways),
-// the columns go through LDS so that global loads and stores are row
-// segments.
+// U12 = L11^{-1} A12 (unit lower L11, jb x jb), with the panel's row
+// interchanges applied to the same columns first.  The interchanges: every
+// affected row of the workgroup's columns is loaded (16-column row segments),
+// all loads complete before the barrier, then rows beyond the panel are
+// stored at their new positions and the panel rows go to LDS as the
+// right-hand sides.  The solve is the column-oriented forward substitution:
+// at step p the now final x_p is broadcast and every row i > p is updated,
+// x_i = fma(-L_ip, x_p, x_i) -- for each element the same FMA chain, in
+// increasing p, as the row-oriented algorithm.  One wave per column, lane l
+// holding rows l and l + 64: x_p is read from its lane (readlane) as soon as
+// the previous step has made it final, so the solve has no barrier.  A
+// 1024-thread workgroup owns 16 columns; L11 is staged transposed in LDS
+// (rows padded to 129 floats: conflict-free both ways).
 constexpr int TRSM_COLS = 16;
 constexpr int TRSM_LD = PNB + 1;
 constexpr size_t TRSM_LDS = (size_t)(PNB + TRSM_COLS) * TRSM_LD * sizeof(float);
 __global__ void __launch_bounds__(1024)
-trsm_kernel(float *A, int64_t lda, int64_t c0, int64_t c1, int64_t j, int w) {
+trsm_kernel(float *A, int64_t lda, int64_t n, int64_t c0, int64_t c1, int64_t j, int w, const int32_t *plan) {
     extern __shared__ float tsm[];
     float *Lt = tsm;                    // Lt[p * TRSM_LD + i] = L11[i][p] for p < i < w, else 0
     float *Xs = tsm + PNB * TRSM_LD;    // Xs[c * TRSM_LD + i] = A12[i][c]
+    __shared__ int dpos[SWP_MAXR], spos[SWP_MAXR];
+    __shared__ int s_nd;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t cb = c0 + (int64_t)blockIdx.x * TRSM_COLS;   // columns [c0, c1)
+    // plan == nullptr: the interchanges were applied already
+    const int nd = plan ? read_moves(plan, w, dpos, spos, &s_nd) : 0;
+    // the interchanges: thread t moves column t % 16 of affected rows
+    // t / 16, t / 16 + 64, ...
+    const int sc = t & (TRSM_COLS - 1), se = t / TRSM_COLS;
+    const bool cok = cb + sc < c1;
+    constexpr int SPER = SWP_MAXR / (1024 / TRSM_COLS);
+    float v[SPER];
+#pragma unroll
+    for (int k = 0; k < SPER; ++k) {
+        const int e = se + (1024 / TRSM_COLS) * k;
+        v[k] = (cok && e < nd) ? A[(j + spos[e]) * lda + cb + sc] : 0.0f;
+    }
     for (int e = t; e < PNB * PNB; e += 1024) {
         const int i = e / PNB, p = e % PNB;
         Lt[p * TRSM_LD + i] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
     }
-    for (int e = t; e < PNB * TRSM_COLS; e += 1024) {
-        const int i = e / TRSM_COLS, c = e % TRSM_COLS;
-        Xs[c * TRSM_LD + i] = (i < w && cb + c < c1) ? A[(j + i) * lda + cb + c] : 0.0f;
+    if (!plan) {
+        for (int e = t; e < PNB * TRSM_COLS; e += 1024) {
+            const int i = e / TRSM_COLS, c = e % TRSM_COLS;
+            Xs[c * TRSM_LD + i] = (i < w && cb + c < c1) ? A[(j + i) * lda + cb + c] : 0.0f;
+        }
+    } else {
+        for (int e = t; e < PNB * TRSM_COLS; e += 1024) Xs[(e / PNB) * TRSM_LD + e % PNB] = 0.0f;
+    }
+    // every load of the workgroup has returned before any row is overwritten
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SPER; ++k) {
+        const int e = se + (1024 / TRSM_COLS) * k;
+        if (e < nd) {
+            const int q = dpos[e];
+            if (q < w) Xs[sc * TRSM_LD + q] = v[k];
+            else if (cok) A[(j + q) * lda + cb + sc] = v[k];
+        }
     }
     __syncthreads();
     float x0 = Xs[wv * TRSM_LD + lane], x1 = Xs[wv * TRSM_LD + lane + 64];
@@ -523,7 +568,7 @@ trsm_kernel(float *A, int64_t lda, int64_t c0, int64_t c1, int64_t j, int w) {
     __syncthreads();
     for (int e = t; e < PNB * TRSM_COLS; e += 1024) {
         const int i = e / TRSM_COLS, c = e % TRSM_COLS;
-        if (i >= 1 && i < w && cb + c < c1) A[(j + i) * lda + cb + c] = Xs[c * TRSM_LD + i];
+        if (i < w && cb + c < c1) A[(j + i) * lda + cb + c] = Xs[c * TRSM_LD + i];
     }
 }
 
@@ -538,12 +583,13 @@ static int set_trsm_attr() {
 }
 
 // U12 = L11^{-1} A12 and A22 -= L21 U12 for the columns [c0, c1) of the
-// trailing matrix of the panel at j (rows j + jb .. n-1).
-static int lu_update_cols(int variant, int64_t n, float *A, int64_t lda, int64_t j, int jb, int64_t c0,
-                          int64_t c1, hipStream_t s, int cus) {
+// trailing matrix of the panel at j (rows j + jb .. n-1); with the panel's
+// move list, its interchanges on those columns first (else they were applied).
+static int lu_update_cols(int variant, int64_t n, float *A, int64_t lda, const int32_t *plan, int64_t j, int jb,
+                          int64_t c0, int64_t c1, hipStream_t s, int cus) {
     if (c1 <= c0) return BFX_OK;
     hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)ceil_div(c1 - c0, TRSM_COLS)), dim3(1024), TRSM_LDS, s,
-                       A, lda, c0, c1, j, jb);
+                       A, lda, n, c0, c1, j, jb, plan);
     BFX_LAUNCH_CHECK("trsm_kernel");
     const int64_t rows = n - j - jb;
     if (rows <= 0) return BFX_OK;
@@ -568,11 +614,15 @@ static PanelArgs panel_args(float *A, int64_t lda, int64_t n, int64_t j, int32_t
     return pa;
 }
 
-static int launch_laswp(float *A, int64_t lda, int64_t n, int64_t j, int jb, const int32_t *ipiv, hipStream_t s) {
-    const int64_t others = n - jb;
-    if (others <= 0) return BFX_OK;
-    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(others, SWP_COLS)), dim3(SWP_THREADS), 0, s, A, lda,
-                       n, j, jb, ipiv);
+static const int32_t *plan_of(const LuWs &w, int64_t j) { return w.plan + ((j / PNB) & 1) * 2 * PNB; }
+
+// the panel's interchanges on the columns [0, x1) and [x2, n)
+static int launch_laswp(float *A, int64_t lda, int64_t n, int64_t j, int jb, const int32_t *plan, int64_t x1,
+                        int64_t x2, hipStream_t s) {
+    const int64_t cols = x1 + (n - x2);
+    if (cols <= 0) return BFX_OK;
+    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)ceil_div(cols, SWP_COLS)), dim3(SWP_THREADS), 0, s, A, lda,
+                       n, j, jb, plan, x1, x2);
     BFX_LAUNCH_CHECK("laswp_kernel");
     return BFX_OK;
 }
@@ -585,9 +635,9 @@ static int lu_serial(int variant, int64_t n, float *A, int64_t lda, int32_t *ipi
         PanelArgs pa = panel_args(A, lda, n, j, ipiv, info, w);
         void *args[] = {&pa};
         BFX_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel, dim3(pa.G), dim3(PROWS), args, 0, s));
-        int rc = launch_laswp(A, lda, n, j, pa.w, ipiv, s);
+        int rc = launch_laswp(A, lda, n, j, pa.w, plan_of(w, j), j, j + pa.w, s);
         if (rc != BFX_OK) return rc;
-        rc = lu_update_cols(variant, n, A, lda, j, pa.w, j + pa.w, n, s, 0);
+        rc = lu_update_cols(variant, n, A, lda, nullptr, j, pa.w, j + pa.w, n, s, 0);
         if (rc != BFX_OK) return rc;
     }
     return BFX_OK;
@@ -619,11 +669,8 @@ static LuStreams g_lu_streams[64];
 static std::mutex g_lu_streams_mu;
 
 static LuStreams *lu_streams() {
-    static const bool off = [] {
-        const char *e = getenv("BFX_LU_LOOKAHEAD");
-        return e && e[0] == '0';
-    }();
-    if (off) return nullptr;
+    const char *off = getenv("BFX_LU_LOOKAHEAD");   // "0": the serial schedule
+    if (off && off[0] == '0') return nullptr;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     LuStreams &L = g_lu_streams[dev];
@@ -679,28 +726,32 @@ static int lu_lookahead(int variant, int64_t n, float *A, int64_t lda, int32_t *
     if (rc == BFX_OK && panel_small(0)) BFX_HIP(hipStreamWaitEvent(sg, L.ep, 0));
     for (int64_t j = 0; j < n && rc == BFX_OK; j += PNB) {
         const int jb = (int)((n - j < PNB) ? n - j : PNB);
-        rc = launch_laswp(A, lda, n, j, jb, ipiv, sg);
-        if (rc != BFX_OK) break;
         const int64_t c0 = j + jb;
-        if (c0 >= n) break;
+        const int32_t *plan = plan_of(w, j);
+        if (c0 >= n) {
+            rc = launch_laswp(A, lda, n, j, jb, plan, j, n, sg);
+            break;
+        }
         const int64_t c1 = (n - c0 < PNB) ? n : c0 + PNB;
-        // the next block column first
-        rc = lu_update_cols(variant, n, A, lda, j, jb, c0, c1, sg, ucus);
+        // the next block column first (its interchanges in the same kernel)
+        rc = lu_update_cols(variant, n, A, lda, plan, j, jb, c0, c1, sg, ucus);
         if (rc != BFX_OK) break;
-        if (panel_small(c0)) {
+        const bool small = panel_small(c0);
+        if (small) {
             // its panel on the panel stream, beside the rest of the update
             BFX_HIP(hipEventRecord(L.en, sg));
             BFX_HIP(hipStreamWaitEvent(sp, L.en, 0));
             rc = launch_panel(c0);
             if (rc != BFX_OK) break;
-            rc = lu_update_cols(variant, n, A, lda, j, jb, c1, n, sg, ucus);
-            if (rc != BFX_OK) break;
-            BFX_HIP(hipStreamWaitEvent(sg, L.ep, 0));
-        } else {
-            rc = lu_update_cols(variant, n, A, lda, j, jb, c1, n, sg, ucus);
-            if (rc != BFX_OK) break;
-            rc = launch_panel(c0);
         }
+        // the interchanges left of the panel and right of the next block
+        // column, then the rest of the trailing update
+        rc = launch_laswp(A, lda, n, j, jb, plan, j, c1, sg);
+        if (rc != BFX_OK) break;
+        rc = lu_update_cols(variant, n, A, lda, nullptr, j, jb, c1, n, sg, ucus);
+        if (rc != BFX_OK) break;
+        if (small) BFX_HIP(hipStreamWaitEvent(sg, L.ep, 0));
+        else rc = launch_panel(c0);
     }
     if (rc != BFX_OK) return rc;
     BFX_HIP(hipEventRecord(L.ef, sp));
