@@ -38,6 +38,7 @@ constexpr int SLD = SNB + 1;     // LDS stride of a panel row
 constexpr int SMAXN = 1024;      // largest n
 constexpr int STB = 64;          // triangular-solve block
 constexpr unsigned SOLVE_LDS = SMAXN * SLD * 4;   // panel; the other phases fit inside
+constexpr int SWP_OFF = 0;       // int offset of the interchange lists (after the panel's write-back)
 
 struct SolveItem {
     int64_t n;
@@ -526,7 +527,8 @@ __device__ void lu_fmt_wg(const SolveItem &it, int fmt, float *s_v, int *s_i) {
 }
 
 template <int V>
-__device__ void solve_one(const SolveItem &it, double tol, int max_iter, const GmresCfg &cfg, uint16_t *smem) {
+__device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int max_iter, const GmresCfg &cfg,
+                                          uint16_t *smem) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int n = (int)it.n;
     float *LU = it.LU;
@@ -534,10 +536,12 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
     __shared__ int s_i[4];
     __shared__ double s_d[4];
 
-    // ---- copy A into the factor storage
-    for (int64_t e = t; e < (int64_t)n * n; e += 256) {
-        const int64_t r = e / n, c = e % n;
-        LU[e] = it.A[r * it.lda + c];
+    // ---- copy A into the factor storage (a wave per row, lanes along it)
+    for (int r = wave; r < n; r += 4) {
+        const float *src = it.A + (int64_t)r * it.lda;
+        float *dst = LU + (int64_t)r * n;
+#pragma unroll 4
+        for (int c = lane; c < n; c += 64) dst[c] = src[c];
     }
     if (t == 0) *it.info = 0;
     __syncthreads();
@@ -548,9 +552,9 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
         const int jb = (n - j < SNB) ? n - j : SNB;
         const int m = n - j;
         float *P = reinterpret_cast<float *>(smem);
-        for (int e = t; e < m * jb; e += 256) {
-            const int r = e / jb, q = e % jb;
-            P[r * SLD + q] = LU[(int64_t)(j + r) * n + j + q];
+        for (int e = t; e < m * SNB; e += 256) {
+            const int r = e / SNB, q = e % SNB;
+            if (q < jb) P[r * SLD + q] = LU[(int64_t)(j + r) * n + j + q];
         }
         __syncthreads();
         for (int c = 0; c < jb; ++c) {
@@ -583,20 +587,52 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
             }
             __syncthreads();
         }
-        for (int e = t; e < m * jb; e += 256) {
-            const int r = e / jb, q = e % jb;
-            LU[(int64_t)(j + r) * n + j + q] = P[r * SLD + q];
+        for (int e = t; e < m * SNB; e += 256) {
+            const int r = e / SNB, q = e % SNB;
+            if (q < jb) LU[(int64_t)(j + r) * n + j + q] = P[r * SLD + q];
         }
-        __syncthreads();
-        for (int col = t; col < n - jb; col += 256) {
-            const int cc = col < j ? col : col + jb;
-            for (int i = 0; i < jb; ++i) {
-                const int r = j + i, p = it.ipiv[r];
-                if (p != r) {
-                    const float x = LU[(int64_t)r * n + cc];
-                    LU[(int64_t)r * n + cc] = LU[(int64_t)p * n + cc];
-                    LU[(int64_t)p * n + cc] = x;
+        // ---- the panel's interchanges on the other columns: composed into
+        // one permutation of at most 2 jb rows (position d receives the old
+        // row s), then every column's affected entries are all loaded before
+        // any is stored
+        __syncthreads();   // the panel's LDS is free
+        {
+            int *sp = reinterpret_cast<int *>(smem) + SWP_OFF;
+            int *dpos = sp + SNB, *spos = dpos + 2 * SNB;
+            int *s_nd = spos + 2 * SNB;
+            if (t < jb) {
+                const int q = it.ipiv[j + t] - j;   // >= t for a valid factorisation
+                sp[t] = (q >= t && q < m) ? q : t;
+            }
+            if (t == 0) *s_nd = jb;
+            __syncthreads();
+            if (t < jb) {
+                dpos[t] = t;
+                const int q = sp[t];
+                bool first = q >= jb;
+                for (int k = 0; k < t && first; ++k) first = sp[k] != q;
+                if (first) dpos[atomicAdd(s_nd, 1)] = q;
+            }
+            __syncthreads();
+            const int nd = *s_nd;
+            if (t < nd) {
+                int pos = dpos[t];
+                for (int i = jb - 1; i >= 0; --i) {
+                    const int q = sp[i];
+                    pos = (pos == i) ? q : ((pos == q) ? i : pos);
                 }
+                spos[t] = pos;
+            }
+            __syncthreads();
+            float *tmp = reinterpret_cast<float *>(s_nd + 4);   // [2 SNB][256] staged entries
+            for (int col = t; col < n - jb; col += 256) {
+                const int cc = col < j ? col : col + jb;
+                const float *src = LU + (int64_t)j * n + cc;
+#pragma unroll 8
+                for (int e = 0; e < nd; ++e) tmp[e * 256 + t] = src[(int64_t)spos[e] * n];
+                float *dst = LU + (int64_t)j * n + cc;
+#pragma unroll 8
+                for (int e = 0; e < nd; ++e) dst[(int64_t)dpos[e] * n] = tmp[e * 256 + t];
             }
         }
         __syncthreads();
@@ -612,10 +648,8 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
                 const int i = e / SNB, p = e % SNB;
                 L[e] = (i < jb && p < i) ? LU[(int64_t)(j + i) * n + j + p] : 0.0f;
             }
-            for (int e = t; e < jb * rest; e += 256) {
-                const int i = e / rest, c = e % rest;
-                X[i * XLD + c] = LU[(int64_t)(j + i) * n + j + jb + c];
-            }
+            for (int i = 0; i < jb; ++i)
+                for (int c = t; c < rest; c += 256) X[i * XLD + c] = LU[(int64_t)(j + i) * n + j + jb + c];
             __syncthreads();
             for (int c = t; c < rest; c += 256)
                 for (int i = 1; i < jb; ++i) {
@@ -624,10 +658,8 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
                     X[i * XLD + c] = s;
                 }
             __syncthreads();
-            for (int e = t; e < jb * rest; e += 256) {
-                const int i = e / rest, c = e % rest;
-                LU[(int64_t)(j + i) * n + j + jb + c] = X[i * XLD + c];
-            }
+            for (int i = 0; i < jb; ++i)
+                for (int c = t; c < rest; c += 256) LU[(int64_t)(j + i) * n + j + jb + c] = X[i * XLD + c];
             __syncthreads();
         }
         GemmParams gp;
@@ -639,10 +671,19 @@ __device__ void solve_one(const SolveItem &it, double tol, int max_iter, const G
         gp.k_per_split = jb; gp.splits = 1; gp.partial = nullptr;
         gp.vecA = (n % 4 == 0) && (j % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
         gp.vecB = (n % 4 == 0) && ((j + jb) % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
-        const int tiles = (rest + 63) / 64;
-        for (int tm = 0; tm < tiles; ++tm)
-            for (int tn = 0; tn < tiles; ++tn)
-                gemm_tile<V, 64, 64, 2, 2>(gp, (int64_t)tm * 64, (int64_t)tn * 64, 0, jb, 0, smem);
+        // 128 x 128 tiles while the trailing matrix is large (four times the
+        // work per tile pass, the same arithmetic per element), 64 x 64 below
+        if (rest > 256) {
+            const int tiles = (rest + 127) / 128;
+            for (int tm = 0; tm < tiles; ++tm)
+                for (int tn = 0; tn < tiles; ++tn)
+                    gemm_tile<V, 128, 128, 2, 2>(gp, (int64_t)tm * 128, (int64_t)tn * 128, 0, jb, 0, smem);
+        } else {
+            const int tiles = (rest + 63) / 64;
+            for (int tm = 0; tm < tiles; ++tm)
+                for (int tn = 0; tn < tiles; ++tn)
+                    gemm_tile<V, 64, 64, 2, 2>(gp, (int64_t)tm * 64, (int64_t)tn * 64, 0, jb, 0, smem);
+        }
         __syncthreads();
     }
 
