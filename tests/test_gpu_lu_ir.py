@@ -289,11 +289,12 @@ def test_lu_ir_n8192_sixteen_panel_workgroups(bfx):
     assert eta <= 1.01e-14, eta
 
 
-@pytest.mark.parametrize("n,variant", [(1100, 6), (2560, 6), (2048, 0)])
+@pytest.mark.parametrize("n,variant", [(1100, 6), (2560, 6), (2048, 0), (12288, 6)])
 def test_lu_lookahead_same_bits_as_serial(bfx, n, variant, monkeypatch):
     """The look-ahead schedule (next panel on its own compute units beside the
     rest of the trailing update) performs each element's updates in the
-    serial order: factors and pivots are the same bits."""
+    serial order: factors and pivots are the same bits (compared on the GPU;
+    n = 12288 runs 24-workgroup panels)."""
     A = torch.from_numpy(workloads.normal((n, n), 3300 + n)).cuda()
     out = []
     for mode in ("1", "0"):
@@ -302,9 +303,9 @@ def test_lu_lookahead_same_bits_as_serial(bfx, n, variant, monkeypatch):
         _, ipiv, info = bfx.lu_factor(LU, variant)
         torch.cuda.synchronize()
         assert int(info.item()) == 0
-        out.append((LU.cpu().numpy(), ipiv.cpu().numpy()))
-    assert np.array_equal(out[0][1], out[1][1])
-    assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
+        out.append((LU, ipiv))
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][0].view(torch.int32), out[1][0].view(torch.int32))
 
 
 @pytest.mark.parametrize("n", [129, 513])
