@@ -289,12 +289,14 @@ def test_lu_ir_n8192_sixteen_panel_workgroups(bfx):
     assert eta <= 1.01e-14, eta
 
 
-@pytest.mark.parametrize("n,variant", [(1100, 6), (2560, 6), (2048, 0), (12288, 6)])
+@pytest.mark.parametrize("n,variant", [(1100, 6), (2560, 6), (2048, 0), (12288, 6), (16640, 6)])
 def test_lu_lookahead_same_bits_as_serial(bfx, n, variant, monkeypatch):
     """The look-ahead schedule (next panel on its own compute units beside the
     rest of the trailing update) performs each element's updates in the
     serial order: factors and pivots are the same bits (compared on the GPU;
-    n = 12288 runs 24-workgroup panels)."""
+    n = 12288 runs 24-workgroup panels; at n = 16640 the first two panels
+    need 33 workgroups, more than the panel stream's compute units, and run
+    on the update stream)."""
     A = torch.from_numpy(workloads.normal((n, n), 3300 + n)).cuda()
     out = []
     for mode in ("1", "0"):
