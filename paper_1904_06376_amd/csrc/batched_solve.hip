@@ -526,6 +526,146 @@ __device__ void lu_fmt_wg(const SolveItem &it, int fmt, float *s_v, int *s_i) {
     }
 }
 
+// A22 -= L21 U12 for one problem's trailing matrix when the panel is a full
+// 32 columns (K = 32, rest x rest), on the workgroup's four waves without
+// barriers: wave w takes the 32 x 32 output blocks w, w + 4, ... in
+// row-major order.  Each lane loads its MFMA fragments' FP32 values (A row
+// lane % 16 and B column lane % 16, k = 8 (lane / 16) .. + 7) and its C values
+// straight into registers through buffer loads, splits them there and runs
+// the products; the next block's values are loaded while the current block
+// computes.  Elements outside the trailing matrix get an offset beyond the
+// buffer, so they load as zero and their stores are dropped, without
+// branches.  Zero padding, split, product order (lo products in the listed
+// order, then hi) and epilogue are the general tile engine's, so the result
+// is the same bits.
+struct Rank32Frag {
+    float a[2][8], b[2][8], c[2][2][4];
+};
+constexpr uint32_t R32_OOR = 0x80000000u;   // beyond every buffer's range
+
+__device__ __forceinline__ void rank32_load(__amdgpu_buffer_rsrc_t rL, __amdgpu_buffer_rsrc_t rU,
+                                            __amdgpu_buffer_rsrc_t rC, int n, int rest, int nb, int blk,
+                                            int r16, int kg, Rank32Frag &f) {
+    const int m0 = (blk / nb) * 32, n0 = (blk % nb) * 32;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int row = m0 + i * 16 + r16, col = n0 + i * 16 + r16;
+        const uint32_t oa = row < rest ? (uint32_t)(row * n + kg * 8) * 4u : R32_OOR;
+        const uint32_t ob = col < rest ? (uint32_t)(kg * 8 * n + col) * 4u : R32_OOR;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            f.a[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rL, oa + 4u * e, 0, 0));
+            f.b[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rU, ob + 4u * n * e, 0, 0));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + i * 16 + kg * 4 + e, col = n0 + jj * 16 + r16;
+                const uint32_t oc = (row < rest && col < rest) ? (uint32_t)(row * n + col) * 4u : R32_OOR;
+                f.c[i][jj][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rC, oc, 0, 0));
+            }
+}
+
+template <int V>
+__device__ __forceinline__ void rank32_compute(__amdgpu_buffer_rsrc_t rC, int n, int rest, int nb, int blk,
+                                               int r16, int kg, const Rank32Frag &f) {
+    using PR = Prods<V>;
+    constexpr int P = PR::P;
+    const int m0 = (blk / nb) * 32, n0 = (blk % nb) * 32;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    bfx_bf16x8 af[P][2], bf[P][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        uint32_t h0[3][2], h1[3][2], g0[3][2], g1[3][2];
+        split4<P>(&f.a[i][0], h0);
+        split4<P>(&f.a[i][4], h1);
+        split4<P>(&f.b[i][0], g0);
+        split4<P>(&f.b[i][4], g1);
+#pragma unroll
+        for (int pl = 0; pl < P; ++pl) {
+            af[pl][i] = __builtin_bit_cast(bfx_bf16x8, u32x4{h0[pl][0], h0[pl][1], h1[pl][0], h1[pl][1]});
+            bf[pl][i] = __builtin_bit_cast(bfx_bf16x8, u32x4{g0[pl][0], g0[pl][1], g1[pl][0], g1[pl][1]});
+        }
+    }
+    bfx_f32x4 hi[2][2], lo[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            hi[i][jj] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+            lo[i][jj] = bfx_f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+    for (int q = 0; q < PR::n; ++q)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+                lo[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PR::ai[q]][i], bf[PR::bj[q]][jj], lo[i][jj],
+                                                                    0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+            hi[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[0][jj], hi[i][jj], 0, 0, 0);
+    // the epilogue of the general engine with alpha = -1, beta = 1
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + i * 16 + kg * 4 + e, col = n0 + jj * 16 + r16;
+                const uint32_t oc = (row < rest && col < rest) ? (uint32_t)(row * n + col) * 4u : R32_OOR;
+                const float x = fmaf(-1.0f, hi[i][jj][e] + lo[i][jj][e], 1.0f * f.c[i][jj][e]);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), rC, oc, 0, 0);
+            }
+}
+
+// a pointer the whole wave holds, made explicitly uniform (so that buffer
+// resources built from it live in scalar registers)
+__device__ __forceinline__ float *uniform_ptr(float *p) {
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (float *)(((uint64_t)hi << 32) | lo);
+}
+
+template <int V>
+__device__ __forceinline__ void rank32_update(float *LU_, int n_, int j_, int rest_) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    float *LU = uniform_ptr(LU_);
+    const int n = __builtin_amdgcn_readfirstlane(n_), j = __builtin_amdgcn_readfirstlane(j_);
+    const int rest = __builtin_amdgcn_readfirstlane(rest_);
+    float *L21 = LU + (int64_t)(j + 32) * n + j;
+    float *U12 = LU + (int64_t)j * n + j + 32;
+    float *C = LU + (int64_t)(j + 32) * n + j + 32;
+    const __amdgpu_buffer_rsrc_t rL =
+        __builtin_amdgcn_make_buffer_rsrc((void *)L21, (short)0, ((rest - 1) * n + 32) * 4, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rU =
+        __builtin_amdgcn_make_buffer_rsrc((void *)U12, (short)0, (31 * n + rest) * 4, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rC =
+        __builtin_amdgcn_make_buffer_rsrc((void *)C, (short)0, ((rest - 1) * n + rest) * 4, 0x00020000);
+    const int nb = (rest + 31) / 32, total = nb * nb;
+    Rank32Frag f0, f1;
+    int b = wave;
+    if (b < total) rank32_load(rL, rU, rC, n, rest, nb, b, r16, kg, f0);
+    while (b < total) {
+        if (b + 4 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f1);
+        rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f0);
+        b += 4;
+        if (b >= total) break;
+        if (b + 4 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f0);
+        rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f1);
+        b += 4;
+    }
+}
+
 template <int V>
 __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int max_iter, const GmresCfg &cfg,
                                           uint16_t *smem) {
@@ -671,9 +811,10 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
         gp.k_per_split = jb; gp.splits = 1; gp.partial = nullptr;
         gp.vecA = (n % 4 == 0) && (j % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
         gp.vecB = (n % 4 == 0) && ((j + jb) % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
-        // 128 x 128 tiles while the trailing matrix is large (four times the
-        // work per tile pass, the same arithmetic per element), 64 x 64 below
-        if (rest > 256) {
+        if (jb == SNB) {
+            rank32_update<V>(LU, n, j, rest);
+        } else if (rest > 256) {
+            // (a narrower last panel leaves no trailing matrix; kept general)
             const int tiles = (rest + 127) / 128;
             for (int tm = 0; tm < tiles; ++tm)
                 for (int tn = 0; tn < tiles; ++tn)
