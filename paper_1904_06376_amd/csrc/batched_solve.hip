@@ -6,10 +6,11 @@
 //
 // Per problem, inside one 256-thread workgroup:
 //   LU     panels of 32 columns held in LDS (pivot search by wave shuffles and
-//          LDS, swap, divide, rank-1 update), interchanges on the other
-//          columns, TRSM with L11 in LDS, and the trailing update
-//          A22 -= L21 U12 through the split-GEMM tile engine (alpha = -1,
-//          beta = 1, 64 x 64 tiles, one K-step of 32);
+//          LDS, swap, divide, rank-1 update), the panel's interchanges on
+//          the other columns (composed once, applied column by column through
+//          LDS), TRSM with L11 in LDS, and the trailing update
+//          A22 -= L21 U12 as a rank-32 split-BF16 update on the four waves
+//          (alpha = -1, beta = 1; rank32_update);
 //   IR     |A|_inf and |b|_inf, the permutation from ipiv, then
 //          x0 = LUsolve32(b) and refinement steps with an FP64 residual (one
 //          wave per row) and FP32 triangular solves in 64-row blocks (the

@@ -3,21 +3,24 @@
 // columns:
 //   1. panel_kernel  - FP32 factorisation of the (n-j) x jb panel.  The panel
 //      rows are spread over G co-resident workgroups, 512 rows each, one row
-//      per thread held in registers for the whole panel.  Per column: each
-//      workgroup finds its local arg-max (wave shuffles + LDS) and
-//      publishes the candidate row and a
-//      64-bit header {column tag, |candidate|}; every workgroup then polls the
-//      G headers of that column, picks the same pivot (largest magnitude,
-//      lowest row on ties, as ISAMAX: workgroups own increasing row ranges),
-//      reads the winning row, swaps, divides and applies the rank-1 update to
-//      its own rows.  The header exchange is the only grid-wide
-//      synchronisation: one round of polling per column, no barrier counter.
-//   2. laswp_kernel  - the panel's row interchanges applied to the columns
-//      left and right of the panel (composed into one row permutation, each
-//      affected row moved once).
-//   3. trsm_kernel   - U12 = L11^{-1} A12 (unit lower, FP32 FMA chains in
-//      index order; column-oriented steps over register-resident rows).
+//      per thread held in registers for the whole panel.  Per column every
+//      workgroup publishes its best candidate row as words tagged with the
+//      column, every workgroup reads all candidates in one round trip and
+//      picks the same pivot (largest magnitude, lowest position on ties, as
+//      ISAMAX); the previous column's elimination of a row runs while the
+//      exchange is in flight, and interchanges move row labels.  The
+//      candidate exchange is the only grid-wide synchronisation.  At the end
+//      the panel writes its rows at their final positions and its
+//      interchanges as a move list.
+//   2. trsm_kernel   - for a range of trailing columns: the panel's
+//      interchanges on those columns, then U12 = L11^{-1} A12 (unit lower,
+//      FP32 FMA chains in index order, one wave per column).
+//   3. laswp_kernel  - the interchanges on the columns left of the panel (and
+//      on trailing columns whose trsm does not apply them).
 //   4. A22 -= L21 x U12 with the split-BF16 GEMM (alpha = -1, beta = 1).
+// With look-ahead (lu_lookahead) the next block column is updated first and
+// its panel runs on its own compute units while the rest of the trailing
+// matrix is updated; the serial schedule (lu_serial) runs 1-4 in order.
 #include <climits>
 #include <mutex>
 
