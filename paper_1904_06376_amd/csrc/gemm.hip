@@ -532,7 +532,8 @@ static int launch_persist(const GemmParams &p, hipStream_t s) {
 // persistent launch applies.
 static bool persist_ok(const GemmParams &p) {
     return !g_no_persist && p.splits == 1 && p.M % 128 == 0 && p.N % 128 == 0 && p.K % BK == 0 &&
-           p.K <= 4096 && (p.M / 128) * (p.N / 128) < (int64_t(1) << 30);
+           p.K <= 4096 && (p.M / 128) * (p.N / 128) < (int64_t(1) << 30) &&
+           128 * p.ldc * 4 < (int64_t(1) << 31);   // a wave's C block in 32-bit buffer offsets
 }
 
 static bool fast_ok(const GemmParams &p, int BM, int BN) {

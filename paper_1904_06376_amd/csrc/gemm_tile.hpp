@@ -162,6 +162,77 @@ __device__ __forceinline__ int swz_off(int n, int k) {
     return ((n ^ ((n >> 2) & 1)) << 5) + ((((k >> 3) ^ (n >> 1)) & 3) << 3) + (k & 7);
 }
 
+// A wave-uniform 64-bit value moved to scalar registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Epilogue of a block that lies wholly inside C, its TM*16 rows spanning less
+// than 2^31 bytes: straight-line code with no per-element test.  Buffer loads
+// and stores take the lane's part of the address in one VGPR and the
+// element's (uniform) part in an SGPR, so the C values of CB bands are in
+// flight together and the stores issue back to back; nothing waits for a
+// store to complete.  Same arithmetic as the general epilogue.
+template <int TM, int TN, int CB>
+__device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f32x4 (&hi)[TM][TN],
+                                               const bfx_f32x4 (&lo)[TM][TN], int64_t row0, int64_t col0,
+                                               int kg, int r16) {
+    const int ldc = (int)p.ldc;
+    const int64_t r0 = row0, c0 = col0;   // uniform (scalar registers)
+    const int bytes = (int)(((int64_t)(TM * 16 - 1) * p.ldc + TN * 16) * 4);
+    const __amdgpu_buffer_rsrc_t rc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(p.C + r0 * p.ldc + c0), (short)0, bytes, 0x00020000);
+    const int vo = (kg * 4 * ldc + r16) * 4;
+    auto so = [&](int i, int j, int e) { return ((i * 16 + e) * ldc + j * 16) * 4; };
+    const float alpha = p.alpha, beta = p.beta;
+    // one straight-line body per case (uniform branches outside the loops)
+    auto body = [&](auto f64c, auto beta0c) {
+        constexpr bool F64 = decltype(f64c)::value, B0 = decltype(beta0c)::value;
+#pragma unroll
+        for (int i0 = 0; i0 < TM; i0 += CB) {
+            float cv[CB][TN][4];
+            if constexpr (!B0) {
+#pragma unroll
+                for (int ii = 0; ii < CB; ++ii)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            cv[ii][j][e] =
+                                __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rc, vo, so(i0 + ii, j, e), 0));
+            }
+#pragma unroll
+            for (int ii = 0; ii < CB; ++ii)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float h = hi[i0 + ii][j][e], l = lo[i0 + ii][j][e];
+                        float x;
+                        if constexpr (B0)
+                            x = F64 ? (float)((double)alpha * ((double)h + (double)l)) : alpha * (h + l);
+                        else
+                            x = F64 ? (float)fma((double)alpha, (double)h + (double)l, (double)beta * (double)cv[ii][j][e])
+                                    : fmaf(alpha, h + l, beta * cv[ii][j][e]);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rc, vo, so(i0 + ii, j, e), 0);
+                    }
+        }
+    };
+    static_assert(TM % CB == 0, "bands per batch must divide the bands");
+    using T = std::true_type;
+    using F = std::false_type;
+    if (beta == 0.0f) {
+        if (p.fp64_sum) body(T{}, T{});
+        else body(F{}, T{});
+    } else {
+        if (p.fp64_sum) body(T{}, F{});
+        else body(F{}, F{});
+    }
+}
+
 // Epilogue of one MFMA wave's TM x TN block of 16 x 16 tiles.  Output layout
 // of v_mfma_f32_16x16x32_bf16: lane holds column lane%16, rows 4*(lane/16) +
 // 0..3 of each 16 x 16 tile.  X = hi + lo (the largest bin added last), then
@@ -191,6 +262,13 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32
                     base[row * p.N + col] = hi[i][j][e];
                     base[MN + row * p.N + col] = lo[i][j][e];
                 }
+        return;
+    }
+    // (row0, col0) is the same in every lane of the wave
+    const int64_t ur0 = uniform_i64(row0), uc0 = uniform_i64(col0);
+    if (ur0 + TM * 16 <= p.M && uc0 + TN * 16 <= p.N &&
+        ((int64_t)(TM * 16 - 1) * p.ldc + TN * 16) * 4 < (int64_t(1) << 31)) {
+        epilogue_block<TM, TN, CB>(p, hi, lo, ur0, uc0, kg, r16);
         return;
     }
     if (p.beta == 0.0f) {
@@ -616,8 +694,10 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
                     // helpers' loads and split of the next tile's first steps
                     int tm, tn;
                     seq_tile(*seq, tile_k, tm, tn);
-                    tile_epilogue<TM, TN, ECB ? ECB : TM>(p, hi, lo, (int64_t)tm * BM + wm * (BM / 2),
-                                          (int64_t)tn * BN + wn * (BN / 2), kg, r16, 0);
+                    // every tile of a persistent launch is full
+                    epilogue_block<TM, TN, ECB ? ECB : TM>(p, hi, lo,
+                                                          uniform_i64((int64_t)tm * BM + wm * (BM / 2)),
+                                                          uniform_i64((int64_t)tn * BN + wn * (BN / 2)), kg, r16);
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
