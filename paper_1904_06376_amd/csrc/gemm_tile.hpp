@@ -170,22 +170,37 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Epilogue of a block that lies wholly inside C, its TM*16 rows spanning less
-// than 2^31 bytes: straight-line code with no per-element test.  Buffer loads
-// and stores take the lane's part of the address in one VGPR and the
-// element's (uniform) part in an SGPR, so the C values of CB bands are in
-// flight together and the stores issue back to back; nothing waits for a
-// store to complete.  Same arithmetic as the general epilogue.
-template <int TM, int TN, int CB>
+// Epilogue of one wave's block whose TM*16 rows span less than 2^31 bytes of
+// C: straight-line code with no per-element branch.  Buffer loads and stores
+// take the lane's part of the address in one VGPR and the element's (uniform)
+// part in an SGPR, so the C values of CB bands are in flight together and the
+// stores issue back to back; nothing waits for a store to complete.  MASK
+// (blocks crossing the edge of C): the buffer covers C from the block's
+// origin to its last element inside C, and an element outside C takes a
+// lane offset beyond that range, so its load returns 0 and its store is
+// dropped.  Same arithmetic as the general epilogue.
+template <int TM, int TN, int CB, bool MASK = false>
 __device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f32x4 (&hi)[TM][TN],
                                                const bfx_f32x4 (&lo)[TM][TN], int64_t row0, int64_t col0,
                                                int kg, int r16) {
     const int ldc = (int)p.ldc;
     const int64_t r0 = row0, c0 = col0;   // uniform (scalar registers)
-    const int bytes = (int)(((int64_t)(TM * 16 - 1) * p.ldc + TN * 16) * 4);
+    int rows = TM * 16, cols = TN * 16;   // extent of the block inside C
+    if constexpr (MASK) {
+        if (p.M - r0 < rows) rows = (int)(p.M - r0);
+        if (p.N - c0 < cols) cols = (int)(p.N - c0);
+        if (rows <= 0 || cols <= 0) return;
+    }
+    const int bytes = ((rows - 1) * ldc + cols) * 4;
     const __amdgpu_buffer_rsrc_t rc =
         __builtin_amdgcn_make_buffer_rsrc((void *)(p.C + r0 * p.ldc + c0), (short)0, bytes, 0x00020000);
-    const int vo = (kg * 4 * ldc + r16) * 4;
+    const int vo_ = (kg * 4 * ldc + r16) * 4;
+    auto vo = [&](int i, int j, int e) {
+        if constexpr (MASK)
+            return (i * 16 + kg * 4 + e < rows && j * 16 + r16 < cols) ? vo_ : (int)0x80000000;
+        else
+            return vo_;
+    };
     auto so = [&](int i, int j, int e) { return ((i * 16 + e) * ldc + j * 16) * 4; };
     const float alpha = p.alpha, beta = p.beta;
     // one straight-line body per case (uniform branches outside the loops)
@@ -202,7 +217,7 @@ __device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f3
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
                             cv[ii][j][e] =
-                                __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rc, vo, so(i0 + ii, j, e), 0));
+                                __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rc, vo(i0 + ii, j, e), so(i0 + ii, j, e), 0));
             }
 #pragma unroll
             for (int ii = 0; ii < CB; ++ii)
@@ -217,7 +232,7 @@ __device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f3
                         else
                             x = F64 ? (float)fma((double)alpha, (double)h + (double)l, (double)beta * (double)cv[ii][j][e])
                                     : fmaf(alpha, h + l, beta * cv[ii][j][e]);
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rc, vo, so(i0 + ii, j, e), 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rc, vo(i0 + ii, j, e), so(i0 + ii, j, e), 0);
                     }
         }
     };
@@ -266,9 +281,9 @@ __device__ __forceinline__ void tile_epilogue(const GemmParams &p, const bfx_f32
     }
     // (row0, col0) is the same in every lane of the wave
     const int64_t ur0 = uniform_i64(row0), uc0 = uniform_i64(col0);
-    if (ur0 + TM * 16 <= p.M && uc0 + TN * 16 <= p.N &&
-        ((int64_t)(TM * 16 - 1) * p.ldc + TN * 16) * 4 < (int64_t(1) << 31)) {
-        epilogue_block<TM, TN, CB>(p, hi, lo, ur0, uc0, kg, r16);
+    if (((int64_t)(TM * 16 - 1) * p.ldc + TN * 16) * 4 < (int64_t(1) << 31)) {
+        if (ur0 + TM * 16 <= p.M && uc0 + TN * 16 <= p.N) epilogue_block<TM, TN, CB>(p, hi, lo, ur0, uc0, kg, r16);
+        else epilogue_block<TM, TN, CB, true>(p, hi, lo, ur0, uc0, kg, r16);
         return;
     }
     if (p.beta == 0.0f) {
