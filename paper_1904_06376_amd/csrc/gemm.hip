@@ -211,7 +211,7 @@ gemm_planes_kernel(GemmParams p, PlaneArgs q) {
 // stream of K-steps, so that each tile's epilogue overlaps the helper waves'
 // loads and split of the next tile's first K-steps (which a one-tile
 // workgroup cannot overlap with anything: one such workgroup fills a CU).
-template <int V, int BM = 128>
+template <int V, int BM = 128, int EPI = 0>
 __global__ void __launch_bounds__(512, BM == 64 ? 2 : 1)
 gemm_persist_kernel(GemmParams p, int total, int tiles_m, int tiles_n) {
     extern __shared__ __align__(16) uint16_t smem[];
@@ -222,7 +222,8 @@ gemm_persist_kernel(GemmParams p, int total, int tiles_m, int tiles_n) {
     seq.total = total;
     seq.tiles_m = tiles_m;
     seq.tiles_n = tiles_n;
-    gemm_tile_fast<V, BM, BM, 0, true, 2>(p, 0, 0, 0, p.K, 0, smem, &seq);
+    seq_init(seq);
+    gemm_tile_fast<V, BM, BM, 0, true, 2, EPI>(p, 0, 0, 0, p.K, 0, smem, &seq);
 }
 
 // Fixed-order reduction of split-K partials, then the epilogue.  Two passes
@@ -507,12 +508,12 @@ static int device_cus() {
     return cus;
 }
 
-template <int V, int BM>
-static int launch_persist(const GemmParams &p, hipStream_t s) {
+template <int V, int BM, int EPI>
+static int launch_persist_epi(const GemmParams &p, hipStream_t s) {
     const size_t lds = fast_lds_bytes<V, BM, BM>();
     static bool attr_set = false;
     if (!attr_set) {
-        BFX_HIP(hipFuncSetAttribute((const void *)gemm_persist_kernel<V, BM>,
+        BFX_HIP(hipFuncSetAttribute((const void *)gemm_persist_kernel<V, BM, EPI>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
@@ -520,10 +521,20 @@ static int launch_persist(const GemmParams &p, hipStream_t s) {
     const int total = tiles_m * tiles_n;
     const int slots = (p.grid_cus > 0 ? p.grid_cus : device_cus()) * (BM == 64 ? 2 : 1);
     const int grid = total < slots ? total : slots;
-    hipLaunchKernelGGL((gemm_persist_kernel<V, BM>), dim3((unsigned)grid), dim3(512), lds, s, p, total, tiles_m,
-                       tiles_n);
+    hipLaunchKernelGGL((gemm_persist_kernel<V, BM, EPI>), dim3((unsigned)grid), dim3(512), lds, s, p, total,
+                       tiles_m, tiles_n);
     BFX_LAUNCH_CHECK("gemm_persist_kernel launch");
     return BFX_OK;
+}
+
+// beta != 0 with the FP32 sum (the LU's trailing updates): a kernel whose
+// epilogue has that one case (64 x 64 tiles: each tile's C loaded at its first
+// K-step, which the 128 x 128 tiles have no registers for); otherwise the
+// kernel that selects the case at run time.
+template <int V, int BM>
+static int launch_persist(const GemmParams &p, hipStream_t s) {
+    if (p.beta != 0.0f && !p.fp64_sum) return launch_persist_epi<V, BM, BM == 64 ? 1 : 2>(p, s);
+    return launch_persist_epi<V, BM, 0>(p, s);
 }
 
 // Every tile full, one K range, and K short enough that the per-tile

@@ -115,19 +115,42 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
 // then 8 tile rows per group, column-major inside the group).
 struct TileSeq {
     int first, stride, count, total, tiles_m, tiles_n;
+    uint32_t inv_band, inv_last;   // udiv_inv of 8 tiles_n and of tiles_m % 8
 };
+
+// Division of uniform 32-bit values by a divisor fixed for the launch, in
+// scalar registers (no floating-point reciprocal on the vector ALU): inv =
+// floor((2^32 - 1) / d) makes mulhi(n, inv) equal to n / d or up to two less,
+// which the two corrections fix.
+__device__ __forceinline__ uint32_t udiv_inv(uint32_t d) { return d ? 0xFFFFFFFFu / d : 0u; }
+__device__ __forceinline__ uint32_t udiv(uint32_t n, uint32_t d, uint32_t inv) {
+    uint32_t q = __umulhi(n, inv);
+    if (n - q * d >= d) ++q;
+    if (n - q * d >= d) ++q;
+    return q;
+}
+
+__device__ __forceinline__ void seq_init(TileSeq &q) {
+    q.inv_band = udiv_inv(8u * (uint32_t)q.tiles_n);
+    q.inv_last = udiv_inv((uint32_t)q.tiles_m & 7u);
+}
 
 __device__ __forceinline__ void seq_tile(const TileSeq &q, int k, int &tm, int &tn) {
     const int bid = q.first + k * q.stride;
-    const int qq = q.total / 8, r = q.total % 8;
-    const int xcd = bid % 8, slot = bid / 8;
+    const int qq = q.total >> 3, r = q.total & 7;
+    const int xcd = bid & 7, slot = bid >> 3;
     const int id = (xcd < r) ? xcd * (qq + 1) + slot : r * (qq + 1) + (xcd - r) * qq + slot;
-    const int group = id / (8 * q.tiles_n);
+    const int group = (int)udiv((uint32_t)id, 8u * (uint32_t)q.tiles_n, q.inv_band);
     const int first_m = group * 8;
-    const int gsz = (q.tiles_m - first_m < 8) ? q.tiles_m - first_m : 8;
     const int in_g = id - group * 8 * q.tiles_n;
-    tm = first_m + in_g % gsz;
-    tn = in_g / gsz;
+    if (q.tiles_m - first_m >= 8) {
+        tm = first_m + (in_g & 7);
+        tn = in_g >> 3;
+    } else {
+        const uint32_t gsz = (uint32_t)(q.tiles_m - first_m);
+        tn = (int)udiv((uint32_t)in_g, gsz, q.inv_last);
+        tm = first_m + (in_g - tn * (int)gsz);
+    }
 }
 
 // LDS bytes one tile call needs.
@@ -170,6 +193,15 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Buffer resource over a wave's C block at (r0, c0) (uniform), rows x cols
+// of it inside C, the block spanning less than 2^31 bytes.
+template <int TM, int TN>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t c_block_rsrc(const GemmParams &p, int64_t r0, int64_t c0,
+                                                              int rows = TM * 16, int cols = TN * 16) {
+    const int bytes = ((rows - 1) * (int)p.ldc + cols) * 4;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(p.C + r0 * p.ldc + c0), (short)0, bytes, 0x00020000);
+}
+
 // Epilogue of one wave's block whose TM*16 rows span less than 2^31 bytes of
 // C: straight-line code with no per-element branch.  Buffer loads and stores
 // take the lane's part of the address in one VGPR and the element's (uniform)
@@ -179,7 +211,7 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 // origin to its last element inside C, and an element outside C takes a
 // lane offset beyond that range, so its load returns 0 and its store is
 // dropped.  Same arithmetic as the general epilogue.
-template <int TM, int TN, int CB, bool MASK = false>
+template <int TM, int TN, int CB, bool MASK = false, bool ONLY_BETA_F32 = false>
 __device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f32x4 (&hi)[TM][TN],
                                                const bfx_f32x4 (&lo)[TM][TN], int64_t row0, int64_t col0,
                                                int kg, int r16) {
@@ -191,9 +223,7 @@ __device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f3
         if (p.N - c0 < cols) cols = (int)(p.N - c0);
         if (rows <= 0 || cols <= 0) return;
     }
-    const int bytes = ((rows - 1) * ldc + cols) * 4;
-    const __amdgpu_buffer_rsrc_t rc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(p.C + r0 * p.ldc + c0), (short)0, bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rc = c_block_rsrc<TM, TN>(p, r0, c0, rows, cols);
     const int vo_ = (kg * 4 * ldc + r16) * 4;
     auto vo = [&](int i, int j, int e) {
         if constexpr (MASK)
@@ -239,6 +269,10 @@ __device__ __forceinline__ void epilogue_block(const GemmParams &p, const bfx_f3
     static_assert(TM % CB == 0, "bands per batch must divide the bands");
     using T = std::true_type;
     using F = std::false_type;
+    if constexpr (ONLY_BETA_F32) {
+        body(F{}, F{});   // the caller has beta != 0 and the FP32 sum
+        return;
+    }
     if (beta == 0.0f) {
         if (p.fp64_sum) body(T{}, T{});
         else body(F{}, T{});
@@ -658,7 +692,7 @@ __device__ __forceinline__ int bcol_row(int n) { return (n & ~3) | ((n & 3) ^ ((
 // ECB: 16-row bands whose C values the epilogue loads together (0: all of
 // them).  One band by default: more raise the kernel's register count, which
 // cost the 8192^3 x6 launch 3%.
-template <int V, int BM, int BN, int NST_ = 0, bool PERSIST = false, int ECB = 1>
+template <int V, int BM, int BN, int NST_ = 0, bool PERSIST = false, int ECB = 1, int EPI = 0>
 __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, int64_t n0,
                                                int64_t kb, int64_t ke, int64_t split,
                                                uint16_t *smem, const TileSeq *seq = nullptr) {
@@ -700,19 +734,60 @@ __device__ __forceinline__ void gemm_tile_fast(const GemmParams &p, int64_t m0, 
             aoff[i] = SWZ ? swz_off(wm * (BM / 2) + i * 16 + r16, kg * 8)
                           : (wm * (BM / 2) + i * 16 + r16) * FLDK + kg * 8;
         int tile_k = 0, step_in_tile = 0;   // persistent: tile and step within it
+        // EPI == 1 (persistent, beta != 0, FP32 sum): the C values of a tile
+        // are loaded at its first K-step and land while its K-steps run
+        // (all of its address arithmetic in scalar registers: a vector
+        // register written there would have to wait for the loads still in
+        // flight into registers the allocator reuses)
+        __amdgpu_buffer_rsrc_t crc;
+        float cpre[EPI == 1 ? TM : 1][EPI == 1 ? TN : 1][4];
+        const int cvo = (kg * 4 * (int)p.ldc + r16) * 4;
+        auto cso = [&](int i, int j, int e) { return ((i * 16 + e) * (int)p.ldc + j * 16) * 4; };
+        const int wm_u = __builtin_amdgcn_readfirstlane(wm), wn_u = __builtin_amdgcn_readfirstlane(wn);
+        int next_tm = 0, next_tn = 0;   // EPI == 1: the next tile's indices
+        if constexpr (PERSIST && EPI == 1) seq_tile(*seq, 0, next_tm, next_tn);
         for (int s = 0; s < S; ++s) {
             __syncthreads();  // buffer s&1 holds step s
+            if constexpr (PERSIST && EPI == 1) {
+                if (step_in_tile == 0) {
+                    crc = c_block_rsrc<TM, TN>(p, (int64_t)next_tm * BM + wm_u * (BM / 2),
+                                               (int64_t)next_tn * BN + wn_u * (BN / 2));
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                cpre[i][j][e] = __uint_as_float(
+                                    __builtin_amdgcn_raw_buffer_load_b32(crc, cvo, cso(i, j, e), 0));
+                }
+            }
             mfma_step<V, TM, TN, PLANE>(smem + (s & 1) * P * PLANE, aoff, boff, hi, lo);
             if constexpr (PERSIST) {
                 if (++step_in_tile == KT) {
                     // last K-step of this tile: its epilogue, overlapped with the
                     // helpers' loads and split of the next tile's first steps
-                    int tm, tn;
-                    seq_tile(*seq, tile_k, tm, tn);
-                    // every tile of a persistent launch is full
-                    epilogue_block<TM, TN, ECB ? ECB : TM>(p, hi, lo,
-                                                          uniform_i64((int64_t)tm * BM + wm * (BM / 2)),
-                                                          uniform_i64((int64_t)tn * BN + wn * (BN / 2)), kg, r16);
+                    // (every tile of a persistent launch is full)
+                    if constexpr (EPI == 1) {
+#pragma unroll
+                        for (int i = 0; i < TM; ++i)
+#pragma unroll
+                            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const float x = fmaf(p.alpha, hi[i][j][e] + lo[i][j][e], p.beta * cpre[i][j][e]);
+                                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), crc, cvo, cso(i, j, e), 0);
+                                }
+                        if (tile_k + 1 < seq->count) seq_tile(*seq, tile_k + 1, next_tm, next_tn);
+                    } else {
+                        // EPI == 2: beta != 0 and the FP32 sum only (one code
+                        // path, so no wait for the stores at the next step)
+                        int tm, tn;
+                        seq_tile(*seq, tile_k, tm, tn);
+                        epilogue_block<TM, TN, ECB ? ECB : TM, false, EPI == 2>(p, hi, lo,
+                                                              uniform_i64((int64_t)tm * BM + wm * (BM / 2)),
+                                                              uniform_i64((int64_t)tn * BN + wn * (BN / 2)), kg, r16);
+                    }
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
