@@ -636,7 +636,18 @@ __device__ __forceinline__ float *uniform_ptr(float *p) {
     return (float *)(((uint64_t)hi << 32) | lo);
 }
 
+// Buffer resource over len floats from p (p uniform over the wave).  Loads
+// at a byte offset of len*4 or more return 0 and stores there are dropped, so
+// a loop can issue all its loads before the first use without a branch per
+// element: an element past the end takes an out-of-range offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const float *p, int len) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(const_cast<float *>(p)), (short)0, len * 4,
+                                             0x00020000);
+}
+constexpr int OOB = 0x40000000;   // a byte offset past every span here
+
 template <int V>
+
 __device__ __forceinline__ void rank32_update(float *LU_, int n_, int j_, int rest_) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -677,12 +688,24 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
     __shared__ int s_i[4];
     __shared__ double s_d[4];
 
-    // ---- copy A into the factor storage (a wave per row, lanes along it)
+    // ---- copy A into the factor storage: a wave per row, lanes along it,
+    // 8 loads in flight before their stores
     for (int r = wave; r < n; r += 4) {
-        const float *src = it.A + (int64_t)r * it.lda;
-        float *dst = LU + (int64_t)r * n;
-#pragma unroll 4
-        for (int c = lane; c < n; c += 64) dst[c] = src[c];
+        const __amdgpu_buffer_rsrc_t rs = span_rsrc(it.A + (int64_t)r * it.lda, n);
+        const __amdgpu_buffer_rsrc_t rd = span_rsrc(LU + (int64_t)r * n, n);
+        for (int c0 = 0; c0 < n; c0 += 512) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c0 + lane + 64 * k;
+                v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, c < n ? c * 4 : OOB, 0, 0));
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c0 + lane + 64 * k;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[k]), rd, c < n ? c * 4 : OOB, 0, 0);
+            }
+        }
     }
     if (t == 0) *it.info = 0;
     __syncthreads();
@@ -693,9 +716,23 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
         const int jb = (n - j < SNB) ? n - j : SNB;
         const int m = n - j;
         float *P = reinterpret_cast<float *>(smem);
-        for (int e = t; e < m * SNB; e += 256) {
-            const int r = e / SNB, q = e % SNB;
-            if (q < jb) P[r * SLD + q] = LU[(int64_t)(j + r) * n + j + q];
+        {
+            // 8 loads in flight per thread before their LDS stores
+            const __amdgpu_buffer_rsrc_t rp = span_rsrc(LU + (int64_t)j * n + j, (m - 1) * n + jb);
+            for (int e0 = 0; e0 < m * SNB; e0 += 8 * 256) {
+                float v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = e0 + 256 * k + t, r = e >> 5, q = e & (SNB - 1);
+                    v[k] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(rp, (r < m && q < jb) ? (r * n + q) * 4 : OOB, 0, 0));
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = e0 + 256 * k + t, r = e >> 5, q = e & (SNB - 1);
+                    if (r < m && q < jb) P[r * SLD + q] = v[k];
+                }
+            }
         }
         __syncthreads();
         for (int c = 0; c < jb; ++c) {
@@ -789,8 +826,30 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
                 const int i = e / SNB, p = e % SNB;
                 L[e] = (i < jb && p < i) ? LU[(int64_t)(j + i) * n + j + p] : 0.0f;
             }
-            for (int i = 0; i < jb; ++i)
-                for (int c = t; c < rest; c += 256) X[i * XLD + c] = LU[(int64_t)(j + i) * n + j + jb + c];
+            {
+                // rows of A12: a thread's loads of 4 rows x 2 columns in
+                // flight before their LDS stores
+                const __amdgpu_buffer_rsrc_t rx = span_rsrc(LU + (int64_t)j * n + j + jb, (jb - 1) * n + rest);
+                for (int i0 = 0; i0 < jb; i0 += 4)
+                    for (int c0 = 0; c0 < rest; c0 += 512) {
+                        float v[4][2];
+#pragma unroll
+                        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int i = i0 + ii, c = c0 + 256 * h + t;
+                                v[ii][h] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                    rx, (i < jb && c < rest) ? (i * n + c) * 4 : OOB, 0, 0));
+                            }
+#pragma unroll
+                        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int i = i0 + ii, c = c0 + 256 * h + t;
+                                if (i < jb && c < rest) X[i * XLD + c] = v[ii][h];
+                            }
+                    }
+            }
             __syncthreads();
             for (int c = t; c < rest; c += 256)
                 for (int i = 1; i < jb; ++i) {
@@ -839,8 +898,21 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
     // norms
     double rowmax = 0.0;
     for (int row = wave; row < n; row += 4) {
+        // the row's loads in flight together; each lane sums its entries in
+        // increasing column order (elements past n load as 0 and are not added)
+        const __amdgpu_buffer_rsrc_t ra = span_rsrc(A + (int64_t)row * it.lda, n);
         double s = 0.0;
-        for (int c = lane; c < n; c += 64) s += fabs((double)A[(int64_t)row * it.lda + c]);
+        for (int c0 = 0; c0 < n; c0 += 512) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c0 + lane + 64 * k;
+                v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ra, c < n ? c * 4 : OOB, 0, 0));
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (c0 + lane + 64 * k < n) s += fabs((double)v[k]);
+        }
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         if (s > rowmax) rowmax = s;
     }
