@@ -113,6 +113,25 @@ __device__ __forceinline__ double block_max_d(double v, double *sd) {
     return m;
 }
 
+// a pointer the whole wave holds, made explicitly uniform (so that buffer
+// resources built from it live in scalar registers)
+__device__ __forceinline__ float *uniform_ptr(float *p) {
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (float *)(((uint64_t)hi << 32) | lo);
+}
+
+// Buffer resource over len floats from p (p uniform over the wave).  Loads
+// at a byte offset of len*4 or more return 0 and stores there are dropped, so
+// a loop can issue all its loads before the first use without a branch per
+// element: an element past the end takes an out-of-range offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const float *p, int len) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(const_cast<float *>(p)), (short)0, len * 4,
+                                             0x00020000);
+}
+constexpr int OOB = 0x40000000;   // a byte offset past every span here
+
 // In-place solve of (L or U) y = y with y in LDS (T = float for LU-IR, double
 // for the GMRES preconditioner), FP32 factors in global LU.
 template <typename T, bool LOWER>
@@ -123,9 +142,22 @@ __device__ void block_trsv(const float *LU, int n, T *y, float *D) {
         const int blk = LOWER ? bb : nblk - 1 - bb;
         const int k0 = blk * STB;
         const int rows = (n - k0 < STB) ? n - k0 : STB;
-        for (int e = t; e < STB * STB; e += 256) {
-            const int i = e / STB, c = e % STB;
-            D[i * (STB + 1) + c] = (i < rows && c < rows) ? LU[(int64_t)(k0 + i) * n + k0 + c] : 0.0f;
+        {
+            // the diagonal block: a thread's 16 loads in flight before their
+            // LDS stores (entries outside it load as 0)
+            const __amdgpu_buffer_rsrc_t rd = span_rsrc(LU + (int64_t)k0 * n + k0, (rows - 1) * n + rows);
+            float v[STB * STB / 256];
+#pragma unroll
+            for (int k = 0; k < STB * STB / 256; ++k) {
+                const int e = t + 256 * k, i = e / STB, c = e % STB;
+                v[k] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rd, (i < rows && c < rows) ? (i * n + c) * 4 : OOB, 0, 0));
+            }
+#pragma unroll
+            for (int k = 0; k < STB * STB / 256; ++k) {
+                const int e = t + 256 * k, i = e / STB, c = e % STB;
+                D[i * (STB + 1) + c] = v[k];
+            }
         }
         __syncthreads();
         if (t < 64) {
@@ -627,24 +659,7 @@ __device__ __forceinline__ void rank32_compute(__amdgpu_buffer_rsrc_t rC, int n,
             }
 }
 
-// a pointer the whole wave holds, made explicitly uniform (so that buffer
-// resources built from it live in scalar registers)
-__device__ __forceinline__ float *uniform_ptr(float *p) {
-    const uint64_t u = (uint64_t)p;
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
-    return (float *)(((uint64_t)hi << 32) | lo);
-}
 
-// Buffer resource over len floats from p (p uniform over the wave).  Loads
-// at a byte offset of len*4 or more return 0 and stores there are dropped, so
-// a loop can issue all its loads before the first use without a branch per
-// element: an element past the end takes an out-of-range offset.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const float *p, int len) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(const_cast<float *>(p)), (short)0, len * 4,
-                                             0x00020000);
-}
-constexpr int OOB = 0x40000000;   // a byte offset past every span here
 
 template <int V>
 
@@ -803,11 +818,23 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
             }
             __syncthreads();
             float *tmp = reinterpret_cast<float *>(s_nd + 4);   // [2 SNB][256] staged entries
+            // rows j .. n-1 of every column, addressed from row j
+            const __amdgpu_buffer_rsrc_t rw = span_rsrc(LU + (int64_t)j * n, m * n);
             for (int col = t; col < n - jb; col += 256) {
                 const int cc = col < j ? col : col + jb;
-                const float *src = LU + (int64_t)j * n + cc;
-#pragma unroll 8
-                for (int e = 0; e < nd; ++e) tmp[e * 256 + t] = src[(int64_t)spos[e] * n];
+                // 16 loads in flight before their LDS stores
+                for (int e0 = 0; e0 < nd; e0 += 16) {
+                    float v[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int e = e0 + k;
+                        v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                            rw, e < nd ? (spos[e < nd ? e : 0] * n + cc) * 4 : OOB, 0, 0));
+                    }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (e0 + k < nd) tmp[(e0 + k) * 256 + t] = v[k];
+                }
                 float *dst = LU + (int64_t)j * n + cc;
 #pragma unroll 8
                 for (int e = 0; e < nd; ++e) dst[(int64_t)dpos[e] * n] = tmp[e * 256 + t];
