@@ -849,9 +849,19 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
             float *L = reinterpret_cast<float *>(smem);
             float *X = L + SNB * SNB;
             const int XLD = rest + 1;
-            for (int e = t; e < SNB * SNB; e += 256) {
-                const int i = e / SNB, p = e % SNB;
-                L[e] = (i < jb && p < i) ? LU[(int64_t)(j + i) * n + j + p] : 0.0f;
+            {
+                // the strictly lower part of L11: a thread's 4 loads in flight
+                // before their LDS stores (other entries load as 0)
+                const __amdgpu_buffer_rsrc_t rl = span_rsrc(LU + (int64_t)j * n + j, (jb - 1) * n + jb);
+                float v[SNB * SNB / 256];
+#pragma unroll
+                for (int k = 0; k < SNB * SNB / 256; ++k) {
+                    const int e = t + 256 * k, i = e / SNB, p = e % SNB;
+                    v[k] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(rl, (i < jb && p < i) ? (i * n + p) * 4 : OOB, 0, 0));
+                }
+#pragma unroll
+                for (int k = 0; k < SNB * SNB / 256; ++k) L[t + 256 * k] = v[k];
             }
             {
                 // rows of A12: a thread's loads of 4 rows x 2 columns in

@@ -507,9 +507,29 @@ trsm_kernel(float *A, int64_t lda, int64_t n, int64_t c0, int64_t c1, int64_t j,
         const int e = se + (1024 / TRSM_COLS) * k;
         v[k] = (cok && e < nd) ? A[(j + spos[e]) * lda + cb + sc] : 0.0f;
     }
-    for (int e = t; e < PNB * PNB; e += 1024) {
-        const int i = e / PNB, p = e % PNB;
-        Lt[p * TRSM_LD + i] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
+    if ((int64_t)PNB * lda * 4 >= (int64_t(1) << 31)) {
+        // rows too far apart for 32-bit buffer offsets
+        for (int e = t; e < PNB * PNB; e += 1024) {
+            const int i = e / PNB, p = e % PNB;
+            Lt[p * TRSM_LD + i] = (i < w && p < i) ? A[(j + i) * lda + j + p] : 0.0f;
+        }
+    } else {
+        // L11: a thread's 16 loads in flight before their LDS stores (entries
+        // on or above the diagonal take an out-of-range offset and load as 0)
+        const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + j * lda + j), (short)0, (int)(((w - 1) * lda + w) * 4), 0x00020000);
+        float lv[PNB * PNB / 1024];
+#pragma unroll
+        for (int k = 0; k < PNB * PNB / 1024; ++k) {
+            const int e = t + 1024 * k, i = e / PNB, p = e % PNB;
+            lv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                rl, (i < w && p < i) ? (int)((i * lda + p) * 4) : 0x40000000, 0, 0));
+        }
+#pragma unroll
+        for (int k = 0; k < PNB * PNB / 1024; ++k) {
+            const int e = t + 1024 * k, i = e / PNB, p = e % PNB;
+            Lt[p * TRSM_LD + i] = lv[k];
+        }
     }
     if (!plan) {
         for (int e = t; e < PNB * TRSM_COLS; e += 1024) {
