@@ -772,11 +772,35 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
                 }
             __syncthreads();
             const float piv = P[c * SLD + c];
-            for (int r = c + 1 + t; r < m; r += 256) {
-                float l = P[r * SLD + c];
-                if (piv != 0.0f) l = l / piv;
-                P[r * SLD + c] = l;
-                for (int q = c + 1; q < jb; ++q) P[r * SLD + q] = fmaf(-l, P[c * SLD + q], P[r * SLD + q]);
+            if (jb == SNB) {
+                // whole rows through registers: all of a row's LDS reads issue
+                // before its FMAs (columns q <= c are written back unchanged,
+                // then column c receives the multiplier)
+                float u[SNB];
+#pragma unroll
+                for (int q = 0; q < SNB; ++q) u[q] = P[c * SLD + q];
+                for (int r = c + 1 + t; r < m; r += 256) {
+                    float x[SNB];
+#pragma unroll
+                    for (int q = 0; q < SNB; ++q) x[q] = P[r * SLD + q];
+                    float l = P[r * SLD + c];
+                    if (piv != 0.0f) l = l / piv;
+#pragma unroll
+                    for (int q = 0; q < SNB; ++q) {
+                        const float y = fmaf(-l, u[q], x[q]);
+                        x[q] = q > c ? y : x[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < SNB; ++q) P[r * SLD + q] = x[q];
+                    P[r * SLD + c] = l;
+                }
+            } else {
+                for (int r = c + 1 + t; r < m; r += 256) {
+                    float l = P[r * SLD + c];
+                    if (piv != 0.0f) l = l / piv;
+                    P[r * SLD + c] = l;
+                    for (int q = c + 1; q < jb; ++q) P[r * SLD + q] = fmaf(-l, P[c * SLD + q], P[r * SLD + q]);
+                }
             }
             __syncthreads();
         }
