@@ -915,7 +915,19 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
             for (int c = t; c < rest; c += 256)
                 for (int i = 1; i < jb; ++i) {
                     float s = X[i * XLD + c];
-                    for (int p = 0; p < i; ++p) s = fmaf(-L[i * SNB + p], X[p * XLD + c], s);
+                    int p = 0;
+                    // four terms' LDS reads issued together, then their FMAs
+                    // in increasing p (the same chain as one term at a time)
+                    for (; p + 4 <= i; p += 4) {
+                        const float4 l4 = *reinterpret_cast<const float4 *>(L + i * SNB + p);
+                        const float x0 = X[p * XLD + c], x1 = X[(p + 1) * XLD + c];
+                        const float x2 = X[(p + 2) * XLD + c], x3 = X[(p + 3) * XLD + c];
+                        s = fmaf(-l4.x, x0, s);
+                        s = fmaf(-l4.y, x1, s);
+                        s = fmaf(-l4.z, x2, s);
+                        s = fmaf(-l4.w, x3, s);
+                    }
+                    for (; p < i; ++p) s = fmaf(-L[i * SNB + p], X[p * XLD + c], s);
                     X[i * XLD + c] = s;
                 }
             __syncthreads();
