@@ -679,16 +679,22 @@ __device__ __forceinline__ void rank32_update(float *LU_, int n_, int j_, int re
     const __amdgpu_buffer_rsrc_t rC =
         __builtin_amdgcn_make_buffer_rsrc((void *)C, (short)0, ((rest - 1) * n + rest) * 4, 0x00020000);
     const int nb = (rest + 31) / 32, total = nb * nb;
-    Rank32Frag f0, f1;
+    // two blocks in flight ahead of the one being computed
+    Rank32Frag f0, f1, f2;
     int b = wave;
     if (b < total) rank32_load(rL, rU, rC, n, rest, nb, b, r16, kg, f0);
+    if (b + 4 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f1);
     while (b < total) {
-        if (b + 4 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f1);
+        if (b + 8 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f2);
         rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f0);
         b += 4;
         if (b >= total) break;
-        if (b + 4 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f0);
+        if (b + 8 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f0);
         rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f1);
+        b += 4;
+        if (b >= total) break;
+        if (b + 8 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f1);
+        rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f2);
         b += 4;
     }
 }
