@@ -576,6 +576,10 @@ struct Rank32Frag {
 };
 constexpr uint32_t R32_OOR = 0x80000000u;   // beyond every buffer's range
 
+// VEC (n % 4 == 0: the A fragment's 8 values start on a 16-byte boundary):
+// two 16-byte loads for them instead of eight 4-byte loads, which keeps a
+// block's loads and stores within what the wave's memory counter tells apart.
+template <bool VEC>
 __device__ __forceinline__ void rank32_load(__amdgpu_buffer_rsrc_t rL, __amdgpu_buffer_rsrc_t rU,
                                             __amdgpu_buffer_rsrc_t rC, int n, int rest, int nb, int blk,
                                             int r16, int kg, Rank32Frag &f) {
@@ -585,11 +589,23 @@ __device__ __forceinline__ void rank32_load(__amdgpu_buffer_rsrc_t rL, __amdgpu_
         const int row = m0 + i * 16 + r16, col = n0 + i * 16 + r16;
         const uint32_t oa = row < rest ? (uint32_t)(row * n + kg * 8) * 4u : R32_OOR;
         const uint32_t ob = col < rest ? (uint32_t)(kg * 8 * n + col) * 4u : R32_OOR;
+        if constexpr (VEC) {
+            const bfx_f32x4 v0 = __builtin_bit_cast(bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rL, oa, 0, 0));
+            const bfx_f32x4 v1 =
+                __builtin_bit_cast(bfx_f32x4, __builtin_amdgcn_raw_buffer_load_b128(rL, oa + 16u, 0, 0));
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            f.a[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rL, oa + 4u * e, 0, 0));
-            f.b[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rU, ob + 4u * n * e, 0, 0));
+            for (int e = 0; e < 4; ++e) {
+                f.a[i][e] = v0[e];
+                f.a[i][4 + e] = v1[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                f.a[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rL, oa + 4u * e, 0, 0));
         }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            f.b[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rU, ob + 4u * n * e, 0, 0));
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -661,8 +677,7 @@ __device__ __forceinline__ void rank32_compute(__amdgpu_buffer_rsrc_t rC, int n,
 
 
 
-template <int V>
-
+template <int V, bool VEC>
 __device__ __forceinline__ void rank32_update(float *LU_, int n_, int j_, int rest_) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -682,18 +697,18 @@ __device__ __forceinline__ void rank32_update(float *LU_, int n_, int j_, int re
     // two blocks in flight ahead of the one being computed
     Rank32Frag f0, f1, f2;
     int b = wave;
-    if (b < total) rank32_load(rL, rU, rC, n, rest, nb, b, r16, kg, f0);
-    if (b + 4 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f1);
+    if (b < total) rank32_load<VEC>(rL, rU, rC, n, rest, nb, b, r16, kg, f0);
+    if (b + 4 < total) rank32_load<VEC>(rL, rU, rC, n, rest, nb, b + 4, r16, kg, f1);
     while (b < total) {
-        if (b + 8 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f2);
+        if (b + 8 < total) rank32_load<VEC>(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f2);
         rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f0);
         b += 4;
         if (b >= total) break;
-        if (b + 8 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f0);
+        if (b + 8 < total) rank32_load<VEC>(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f0);
         rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f1);
         b += 4;
         if (b >= total) break;
-        if (b + 8 < total) rank32_load(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f1);
+        if (b + 8 < total) rank32_load<VEC>(rL, rU, rC, n, rest, nb, b + 8, r16, kg, f1);
         rank32_compute<V>(rC, n, rest, nb, b, r16, kg, f2);
         b += 4;
     }
@@ -951,7 +966,8 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
         gp.vecA = (n % 4 == 0) && (j % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
         gp.vecB = (n % 4 == 0) && ((j + jb) % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
         if (jb == SNB) {
-            rank32_update<V>(LU, n, j, rest);
+            if (n % 4 == 0) rank32_update<V, true>(LU, n, j, rest);
+            else rank32_update<V, false>(LU, n, j, rest);
         } else if (rest > 256) {
             // (a narrower last panel leaves no trailing matrix; kept general)
             const int tiles = (rest + 127) / 128;
