@@ -19,8 +19,9 @@ def bits16(t):
 
 
 def gemm_bound(variant, K):
-    """Componentwise error bound relative to |A||B| (spec bounds; for K < 8
-    the dropped-term allowance (513/512) 2^-23 is added)."""
+    """Componentwise error bound relative to |A||B|: the FP32 accumulation's
+    2K 2^-24 plus the dropped split terms' 3 2^-16 (x3) or 3 2^-8 (x1) (Sec.
+    II-D, II-G); for K < 8 the dropped-term allowance (513/512) 2^-23 is added."""
     k = 2 * K + (8 if K < 8 else 0)
     if variant >= 10:
         # per-operand split counts 10 pa + pb: the weaker operand's count decides
