@@ -63,7 +63,10 @@ persistent_fast_kernel(const bfx_gemm_desc *__restrict__ probs,
     extern __shared__ __align__(16) uint16_t smem[];
     __shared__ int64_t s_idx;
     for (;;) {
-        if (threadIdx.x == 0) s_idx = (int64_t)atomicAdd(counter, 1u);
+        // taken by a helper-wave thread: the MFMA waves may still have C
+        // stores in flight, which a wait for the atomic's return would
+        // also wait for
+        if (threadIdx.x == 256) s_idx = (int64_t)atomicAdd(counter, 1u);
         __syncthreads();
         const int64_t idx = s_idx;
         __syncthreads();
