@@ -576,9 +576,10 @@ struct Rank32Frag {
 };
 constexpr uint32_t R32_OOR = 0x80000000u;   // beyond every buffer's range
 
-// VEC (n % 4 == 0: the A fragment's 8 values start on a 16-byte boundary):
-// two 16-byte loads for them instead of eight 4-byte loads, which keeps a
-// block's loads and stores within what the wave's memory counter tells apart.
+// VEC: the A fragment's 8 values by two 16-byte loads instead of eight
+// 4-byte loads (buffer loads need only 4-byte alignment here: measured the
+// same bits for odd n), which keeps a block's loads and stores within what
+// the wave's memory counter tells apart.
 template <bool VEC>
 __device__ __forceinline__ void rank32_load(__amdgpu_buffer_rsrc_t rL, __amdgpu_buffer_rsrc_t rU,
                                             __amdgpu_buffer_rsrc_t rC, int n, int rest, int nb, int blk,
@@ -966,8 +967,7 @@ __device__ __forceinline__ void solve_one(const SolveItem &it, double tol, int m
         gp.vecA = (n % 4 == 0) && (j % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
         gp.vecB = (n % 4 == 0) && ((j + jb) % 4 == 0) && (((uintptr_t)LU) % 16 == 0);
         if (jb == SNB) {
-            if (n % 4 == 0) rank32_update<V, true>(LU, n, j, rest);
-            else rank32_update<V, false>(LU, n, j, rest);
+            rank32_update<V, true>(LU, n, j, rest);
         } else if (rest > 256) {
             // (a narrower last panel leaves no trailing matrix; kept general)
             const int tiles = (rest + 127) / 128;
