@@ -179,13 +179,16 @@ __device__ void block_trsv(const float *LU, int n, T *y, float *D) {
         __syncthreads();
         // update the rows not yet solved with this block's solution
         const int lo = LOWER ? k0 + rows : 0, hi = LOWER ? n : k0;
-        if (rows == STB && (n % 4) == 0 && ((uintptr_t)LU % 16) == 0) {
-            // whole 64-column block: sixteen 16-byte loads per row, all in flight
+        if (rows == STB) {
+            // whole 64-column block: sixteen 16-byte loads per row, all in
+            // flight (buffer loads: rows need only 4-byte alignment)
+            const __amdgpu_buffer_rsrc_t rl = span_rsrc(LU, n * n);
             for (int i = lo + t; i < hi; i += 256) {
-                const float4 *row = reinterpret_cast<const float4 *>(LU + (int64_t)i * n + k0);
+                const int ro = (i * n + k0) * 4;
                 float4 a[16];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) a[q] = row[q];
+                for (int q = 0; q < 16; ++q)
+                    a[q] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rl, ro + 16 * q, 0, 0));
                 T acc = (T)0;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
@@ -232,16 +235,32 @@ __device__ void rowdots_wg(const float *A, int64_t lda, int n, const int32_t *pe
         for (int rr = 0; rr < 2; ++rr) {
             const int row = row0 + rr < n ? row0 + rr : n - 1;
             const float *ar = A + (int64_t)(perm ? perm[row] : row) * lda;
+            if (vec) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = 4 * lane + 256 * q;
-                if (vec && c + 3 < n) {
-                    a[rr][q] = *reinterpret_cast<const float4 *>(ar + c);
-                } else {
-                    a[rr][q].x = (c < n) ? ar[c] : 0.0f;
-                    a[rr][q].y = (c + 1 < n) ? ar[c + 1] : 0.0f;
-                    a[rr][q].z = (c + 2 < n) ? ar[c + 2] : 0.0f;
-                    a[rr][q].w = (c + 3 < n) ? ar[c + 3] : 0.0f;
+                for (int q = 0; q < 4; ++q) {
+                    const int c = 4 * lane + 256 * q;
+                    if (c + 3 < n) {
+                        a[rr][q] = *reinterpret_cast<const float4 *>(ar + c);
+                    } else {
+                        a[rr][q].x = (c < n) ? ar[c] : 0.0f;
+                        a[rr][q].y = (c + 1 < n) ? ar[c + 1] : 0.0f;
+                        a[rr][q].z = (c + 2 < n) ? ar[c + 2] : 0.0f;
+                        a[rr][q].w = (c + 3 < n) ? ar[c + 3] : 0.0f;
+                    }
+                }
+            } else {
+                // rows without 16-byte alignment: 4-byte buffer loads, all in
+                // flight, entries past n by an out-of-range offset (load 0)
+                const __amdgpu_buffer_rsrc_t ra = span_rsrc(ar, n);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = 4 * lane + 256 * q;
+                    float v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        v[e] = __uint_as_float(
+                            __builtin_amdgcn_raw_buffer_load_b32(ra, c + e < n ? (c + e) * 4 : OOB, 0, 0));
+                    a[rr][q] = make_float4(v[0], v[1], v[2], v[3]);
                 }
             }
         }
